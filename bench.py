@@ -1,0 +1,180 @@
+"""Benchmark of the two-component colour-gradient LB step on one MI355X.
+
+Default workload: the D3Q27 channel (256x128x128, no-slip y/z walls, body
+force 1e-6 along x, 64 droplets R=10 at seeded random centres, near-contact
+range 3 / strength 0.02, tau 1, FP32 storage and arithmetic).  A step is one
+pass of the whole hot path (phase-field pass + collision pass) over the
+lattice, with the populations already resident in HBM.
+
+Prints ONE JSON line: MLUPS (million lattice-site updates per second), the
+roofline of the dominant kernel (the collision pass) from HIP events recorded
+on the library's stream around each launch, and the FP64 CPU oracle timed on
+a bounded crop of the same physics.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS & % HBM roofline, 2-comp D3Q27; FP16-store/learned vs plain FP32"
+ELEM = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def algorithmic_bytes(q, storage):
+    """Per lattice update: every population of both colours read once and
+    written once, plus the phase field written once (pass 1) and read once
+    (pass 2).  Collision pass alone: populations read + written + phase read."""
+    s = ELEM[storage]
+    r = 8 if storage == "f64" else 4
+    step = 2 * q * s * 2 + 2 * r
+    collide = 2 * q * s * 2 + r
+    phase = 2 * q * s + r
+    return step, collide, phase
+
+
+def traffic_from_profiles(kernel_tag, workload_tag):
+    """HBM bytes per launch measured with rocprofv3 counters, if a summary for
+    this kernel source is committed (profiles/traffic_<kernel>_<workload>.txt
+    holds key = value lines incl. the source hash); None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}_{workload_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2405_14551_amd", "csrc", "step_kernels.hpp")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("source_hash") != h or "bytes_per_launch" not in kv:
+        return None
+    return float(kv["bytes_per_launch"])
+
+
+def cpu_baseline(seconds_target=10.0):
+    """The FP64 oracle, single-threaded, on a 64^3 crop of the channel physics
+    (walls y/z, body force, near contact, 4 droplets R=10)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.sim import OracleSim, OracleParams
+    from paper_2405_14551_amd import workloads as W
+    shape = (64, 64, 64)
+    w = W.channel_3d(shape=shape, count=4, radius=10.0)
+    p = OracleParams(lattice="D3Q27", nx=64, ny=64, nz=64, walls=(False, True, True), tau=1.0,
+                     A=0.01, beta=0.7, body_force=(1e-6, 0, 0), nc=True, nc_A=0.02,
+                     nc_hmin=2.0, nc_hmax=3.0)
+    with threadpool_limits(1):
+        sim = OracleSim(p).init_droplets(w["centres"], w["radii"])
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            sim.step(1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds_target or steps >= 50:
+                break
+    n = shape[0] * shape[1] * shape[2]
+    return {"value": n * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy oracle, 1 thread, 64x64x64 crop of the channel physics "
+                      f"(walls y/z, force 1e-6, near contact on, 4 droplets R=10), {steps} steps "
+                      f"in {el:.1f} s on {platform.processor() or platform.machine()} "
+                      f"(host nproc {os.cpu_count()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="channel_3d", choices=["channel_3d", "big_3d", "dense_3d"])
+    ap.add_argument("--storage", default=None, help="f32 (default), f16, bf16, f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU slab "
+                                   "decomposition is not part of this build", "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+    from paper_2405_14551_amd import lb, workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    wl = {"channel_3d": W.channel_3d, "big_3d": W.big_3d, "dense_3d": W.dense_3d}[args.workload]
+    w = wl(storage=args.storage) if args.storage else wl()
+    if args.storage:
+        w["storage"] = args.storage
+    kw, cen, rad = W.sim_kwargs(w)
+    storage = kw["storage"]
+    print(f"# workload {args.workload} storage {storage} shape {kw['shape']}", file=sys.stderr, flush=True)
+    sim = lb.Simulation(**kw)
+    sim.init_droplets(cen, rad)
+    nx, ny, nz = kw["shape"]
+    N = nx * ny * nz
+    q = sim.q
+    sim.step(args.warmup)
+    sim.sync()
+    stream = sim.stream
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    sim.profile_begin()
+    with torch.cuda.stream(stream):
+        t_start.record(stream)
+        sim.step(args.steps)
+        t_end.record(stream)
+    prof = sim.profile_end()
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    ms_per_step = ms / args.steps
+    mlups = N * args.steps / (ms / 1e3) / 1e6
+    b_step, b_col, b_phase = algorithmic_bytes(q, storage)
+    col_ms = prof["ms_collide"] / max(prof["n_collide"], 1)
+    ph_ms = prof["ms_phase"] / max(prof["n_phase"], 1)
+    achieved = b_col * N / (col_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles("collide", f"{args.workload}_{storage}")
+    diag = sim.diagnostics()
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if storage == "f64" else "f32",
+        "data": "synthetic (seeded droplet placement)",
+        "config": {"workload": args.workload, "lattice": kw["lattice"], "storage": storage,
+                   "shape": list(kw["shape"]), "walls": list(kw["walls"]), "droplets": int(len(rad)),
+                   "near_contact": kw["nc"], "sites": N},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_collide (collision pass)",
+                     "bytes_per_site": b_col, "avg_launch_ms": round(col_ms, 5)},
+        "step_roofline": {"bytes_per_site": b_step, "frac": round(mlups * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
+                          "phase_pass_ms": round(ph_ms, 5), "phase_pass_GBs": round(b_phase * N / (ph_ms / 1e3) / 1e9, 1)},
+        "sanity": {"droplets_end": int(diag[6]), "umax": float(diag[5])},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    sim.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

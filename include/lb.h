@@ -1,0 +1,183 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) two-component colour-gradient lattice
+ * Boltzmann library.
+ *
+ * The library advances two immiscible fluids A and B (total density
+ * rho = rho_A + rho_B, phase field phi = (rho_A - rho_B)/rho) on a D2Q9, D3Q19
+ * or D3Q27 lattice with pull streaming, BGK collision with body forcing, the
+ * colour-gradient surface-tension perturbation, Latva-Kokko recolouring and
+ * the near-contact repulsive force between approaching interfaces
+ * (paper: Sec. III.B, Eqs. lbm and disteq; Sec. III.C.1, Eqs. CGLBE, ome3_1,
+ * ome3_2, near_cont_force; Sec. III.D boundary conditions; Sec. IV "Second
+ * group" for shifted storage).
+ *
+ * Conventions shared by every call:
+ *  - Return value: LB_OK (0) or a negative lb_status.  No exception or C++
+ *    type crosses the ABI.  lb_last_error() returns a thread-local message
+ *    for the most recent failure on the calling thread.
+ *  - Ownership: a handle owns all of its device memory (two population
+ *    buffers, the phase field and the macroscopic field buffers).  The caller
+ *    owns every buffer it passes in; the library never keeps a pointer to it
+ *    after the call returns.
+ *  - Streams: all device work of a handle is ordered on the HIP stream given
+ *    to lb_create (NULL = the legacy default stream).  Calls with a host
+ *    destination synchronise that stream before returning; calls with a
+ *    device destination only enqueue.
+ *  - Layout: sites are numbered s = x + nx*(y + ny*z), x fastest.  Populations
+ *    are structure-of-arrays f[k][i][s] (k = 0 for A, 1 for B; i the velocity
+ *    index).  The velocity numbering is the one lb_lattice_table reports; for
+ *    D2Q9 it is the numbering the paper's boundary equations use.
+ *  - Threading: a handle is not thread-safe.  Separate handles are independent.
+ *  - One GPU: the handle lives on the device that is current when lb_create
+ *    is called.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lb_status {
+  LB_OK = 0,
+  LB_EINVAL = -1,      /* invalid argument (bad size, enum, tau <= 1/2, channel, mask ...) */
+  LB_ENOMEM = -2,      /* device allocation failed                                        */
+  LB_EHIP = -3,        /* a HIP runtime call failed; lb_last_error() names it             */
+  LB_ENUMERIC = -4,    /* watchdog: NaN/Inf, rho <= 0 or |u| > 0.3 found by a check       */
+  LB_ENODEV = -5,      /* no HIP device                                                   */
+  LB_EUNSUPPORTED = -6 /* valid request this build does not implement                     */
+} lb_status;
+
+typedef enum lb_lattice { LB_D2Q9 = 0, LB_D3Q19 = 1, LB_D3Q27 = 2 } lb_lattice;
+
+/* Storage precision of the populations.  Collision arithmetic is FP64 for
+ * LB_F64 and FP32 otherwise.  The 16-bit modes store the shifted value
+ * f^k_i - w_i rho0 / 2 of each colour, rounded to nearest even (paper: Sec. IV,
+ * Eqs. shift_f, shift-lbm), and add the shift back on load. */
+typedef enum lb_storage {
+  LB_F64 = 0,
+  LB_F32 = 1,
+  LB_F16_SHIFTED = 2,
+  LB_BF16_SHIFTED = 3
+} lb_storage;
+
+typedef enum lb_nc_mode { LB_NC_OFF = 0, LB_NC_EXPLICIT = 1 } lb_nc_mode;
+
+/* field selection bits for lb_fields; dst[k] belongs to bit k */
+enum {
+  LB_FIELD_RHO_A = 1u << 0,   /* real[N]                                   */
+  LB_FIELD_RHO_B = 1u << 1,   /* real[N]                                   */
+  LB_FIELD_PHI = 1u << 2,     /* real[N]                                   */
+  LB_FIELD_U = 1u << 3,       /* real[3][N]  (u_x block, u_y, u_z)         */
+  LB_FIELD_FNC = 1u << 4,     /* real[3][N]  near-contact force density    */
+  LB_FIELD_FLAGS = 1u << 5,   /* uint8[N]    1 where |phi| < phi_interface */
+  LB_FIELD_LABELS = 1u << 6   /* int32[N]    droplet label or -1           */
+};
+#define LB_NUM_FIELDS 7
+
+typedef struct lb_params {
+  int lattice;            /* lb_lattice                                                  */
+  int storage;            /* lb_storage                                                  */
+  int nc_mode;            /* lb_nc_mode                                                  */
+  int nx, ny, nz;         /* sites per axis; nz must be 1 for D2Q9                       */
+  int wall[3];            /* per axis: 0 periodic, 1 halfway bounce-back wall on both faces */
+  double tau;             /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3              */
+  double A;               /* perturbation amplitude A = A_A = A_B                        */
+  double beta;            /* recolouring parameter                                       */
+  double rho0;            /* reference total density (initial state and storage shift)   */
+  double body_force[3];   /* force density added at every site                           */
+  double u0[3];           /* uniform velocity of the initial equilibrium                 */
+  double nc_A;            /* near-contact plateau strength A_h for h <= nc_hmin          */
+  double nc_hmin;         /* plateau end (sites); A_h = nc_A (nc_hmin/h)^3 beyond        */
+  double nc_hmax;         /* scan range (sites), 1 <= nc_hmax <= 3                       */
+  double phi_interface;   /* interface flag threshold phi_I in (0, 1)                    */
+  int diag_every;         /* run the watchdog every this many steps inside lb_step (0 = never) */
+} lb_params;
+
+typedef struct lb_handle lb_handle;
+
+/* Fill *p with defaults: D3Q27, FP32, nc off, 64^3 periodic, tau 1, A 0.01,
+ * beta 0.7, rho0 1, no force, u0 = 0, nc_A 0.02, hmin 2, hmax 3, phi_I 0.9. */
+void lb_params_default(lb_params* p);
+
+/* Create a simulation.  p points at n_channels parameter sets; this build
+ * accepts n_channels == 1.  hip_stream is a hipStream_t (NULL allowed).
+ * Allocates 2 * 2 * Q * N populations of the storage type plus the fields.
+ * Errors: LB_EINVAL, LB_ENOMEM, LB_ENODEV, LB_EHIP.  *out is NULL on error. */
+int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** out);
+
+/* Initialise channel `channel` with n droplets of the phase phi_in (+1: the
+ * droplets are fluid A):
+ *   phi(x) = phi_in * max_d tanh(2 (R_d - |x - c_d|) / width)
+ * with minimum-image distances along periodic axes (2D ignores z), then
+ * rho_A = rho0 (1 + phi)/2, rho_B = rho0 (1 - phi)/2 and f^k_i = f^eq_i(rho_k, u0)
+ * (tanh interface profile of the free-energy section; Eq. disteq).
+ * centres: host double[n][3] in site units; radii: host double[n].
+ * n == 0 gives the uniform continuous phase.  Resets the step counter. */
+int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres,
+                     const double* radii, double width, double phi_in);
+
+/* Enqueue nsteps >= 0 time steps.  Each step pulls the populations, forms the
+ * moments and phase field, the colour gradient and interface flags, the
+ * near-contact force, collides (Guo-forced BGK, perturbation, recolouring)
+ * and swaps buffers.  The macroscopic fields of the last step are kept for
+ * lb_fields / lb_diagnostics.  With diag_every > 0 the watchdog runs every
+ * diag_every steps (this synchronises) and a failure stops the loop with
+ * LB_ENUMERIC. */
+int lb_step(lb_handle* h, int nsteps);
+
+/* Copy the fields selected by `mask` (LB_FIELD_* bits) of the last step (or of
+ * the initial state) to dst[bit]: device pointers if dst_on_device, else host
+ * pointers (then the call synchronises).  real = double for LB_F64, float
+ * otherwise.  Labels are computed on demand. */
+int lb_fields(lb_handle* h, int channel, unsigned mask, void* const* dst, int dst_on_device);
+
+/* FP64 global diagnostics of the last step's fields, written to host out[8]:
+ * [sum rho_A, sum rho_B, sum j_x, sum j_y, sum j_z, max |u|, droplet count,
+ *  Laplace jump cs2 (<rho>_{phi > 0.9} - <rho>_{phi < -0.9}) (NaN if a side is empty)]
+ * with j = rho u - F/2.  Synchronises. */
+int lb_diagnostics(lb_handle* h, int channel, double out[8]);
+
+/* Size in bytes of the raw population state (2 * Q * N storage elements). */
+int lb_state_bytes(const lb_handle* h, size_t* bytes);
+/* Copy the current post-collision populations out / in (f[k][i][s] in the
+ * storage type; 16-bit modes hold the shifted values).  Host buffers when
+ * *_on_device == 0 (synchronises).  lb_set_state keeps the step counter. */
+int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device);
+int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device);
+
+/* Steps taken since the last lb_init_droplets. */
+int lb_step_count(const lb_handle* h, long long* t);
+
+/* Per-kernel timing for benchmarks.  Between lb_profile_begin and
+ * lb_profile_end, lb_step records a hipEvent pair on the handle's stream
+ * around every launch of the phase-field pass and of the collision pass.
+ * lb_profile_end synchronises and returns the summed milliseconds and the
+ * launch counts of each pass (any pointer may be NULL). */
+int lb_profile_begin(lb_handle* h);
+int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_phase, int* n_collide);
+
+/* Block until all work of the handle is done. */
+int lb_sync(lb_handle* h);
+
+/* Destroy a handle and free its device memory.  NULL is accepted. */
+int lb_destroy(lb_handle* h);
+
+/* Host-only: the velocity set this library uses.  q receives Q; c (int[Q][3]),
+ * w (double[Q]), opp (int[Q]) and B (double[Q], perturbation coefficients)
+ * may be NULL.  Needs no device. */
+int lb_lattice_table(int lattice, int* q, int* c, double* w, int* opp, double* B);
+
+/* Static text for a status code. */
+const char* lb_error_string(int code);
+/* Thread-local detail of the last failure (empty string if none). */
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

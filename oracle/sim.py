@@ -375,3 +375,53 @@ def viscosity(tau):
 
 __all__ = ["OracleParams", "OracleSim", "round_half_away", "flags_from_phi",
            "surface_tension", "viscosity"]
+
+
+def step_window(params: OracleParams, fA, fB, site, radius=6):
+    """One step of the site at ``site`` = (x, y, z) from the full post-collision
+    state (fA, fB) of shape (q, nz, ny, nx), computed by running the oracle on
+    the window of half-width ``radius`` around it.
+
+    The post-collision value at x depends on data within 5 sites only (pull
+    radius 1 for the populations of the sites whose phase field enters the
+    gradient at the near-contact scan points: 3 + 1 + 1), so with radius >= 6
+    the window's own boundary (periodic wrap on periodic axes, a wall on
+    walled axes, which coincides with the true wall where the window reaches
+    it) cannot influence the centre.  Returns (fA_site (q,), fB_site (q,),
+    fields dict at the site)."""
+    p = params
+    n = (p.nx, p.ny, p.nz)
+    lat = make_lattice(p.lattice)
+    idx = []
+    centre = []
+    walls = []
+    for a in range(3):
+        na, xa = n[a], int(site[a])
+        if lat.d == 2 and a == 2:
+            idx.append(np.array([0]))
+            centre.append(0)
+            walls.append(False)
+            continue
+        if p.walls[a]:
+            lo, hi = max(0, xa - radius), min(na - 1, xa + radius)
+            idx.append(np.arange(lo, hi + 1))
+            centre.append(xa - lo)
+            walls.append(True)
+        elif na <= 2 * radius + 1:
+            idx.append(np.arange(na))
+            centre.append(xa)
+            walls.append(False)
+        else:
+            idx.append(np.arange(xa - radius, xa + radius + 1) % na)
+            centre.append(radius)
+            walls.append(False)
+    ix, iy, iz = idx
+    sub = np.ix_(np.arange(fA.shape[0]), iz, iy, ix)
+    wp = p.replace(nx=len(ix), ny=len(iy), nz=len(iz), walls=tuple(walls))
+    sim = OracleSim(wp).set_state(np.asarray(fA)[sub].astype(np.float64),
+                                  np.asarray(fB)[sub].astype(np.float64))
+    sim.step()
+    cx, cy, cz = centre
+    fl = sim.fields()
+    out = {k: (v[..., cz, cy, cx] if v.ndim == 3 else v[:, cz, cy, cx]) for k, v in fl.items()}
+    return sim.fA[:, cz, cy, cx].copy(), sim.fB[:, cz, cy, cx].copy(), out

@@ -1,0 +1,546 @@
+// C ABI of the library (declared in include/lb.h): handle lifetime, argument
+// checking, buffer ownership, the step loop and the field/diagnostic copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lb.h"
+#include "diag_kernels.hpp"
+#include "engine.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(LB_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                   \
+  } while (0)
+
+const LatticeOps* ops_for(int lattice) {
+  switch (lattice) {
+    case LB_D2Q9: return ops_d2q9();
+    case LB_D3Q19: return ops_d3q19();
+    case LB_D3Q27: return ops_d3q27();
+  }
+  return nullptr;
+}
+
+size_t storage_bytes(int st) {
+  switch (st) {
+    case LB_F64: return 8;
+    case LB_F32: return 4;
+    case LB_F16_SHIFTED:
+    case LB_BF16_SHIFTED: return 2;
+  }
+  return 0;
+}
+
+}  // namespace
+
+struct lb_handle {
+  lb_params p;
+  const LatticeOps* ops = nullptr;
+  int q = 0, d = 0;
+  uint32_t N = 0;
+  size_t esize = 0;  // bytes per stored population
+  size_t rsize = 0;  // bytes per field value (8 for FP64, else 4)
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* f[2] = {nullptr, nullptr};
+  int cur = 0;
+  void* phi = nullptr;
+  void* rho_a = nullptr;
+  void* rho_b = nullptr;
+  void* u = nullptr;
+  void* fnc = nullptr;
+  uint8_t* flags = nullptr;
+  int32_t* labels = nullptr;
+  double* diag_partial = nullptr;
+  double* diag_out = nullptr;
+  unsigned int* ccl_count = nullptr;
+  double* drops = nullptr;
+  int drops_cap = 0;
+  long long t = 0;
+  bool initialised = false;
+  bool fields_valid = false;  // macroscopic fields describe the current state
+  int z_per_block = 1;
+  // per-kernel timing: hipEvent pairs recorded on the handle's stream around
+  // each launch while profiling is on
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_events;
+  std::vector<int> prof_kind;  // one entry per event pair: 0 phase, 1 collide
+  size_t prof_used = 0;
+
+  StepArgs step_args() const {
+    StepArgs a{};
+    a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
+    a.wall_x = p.wall[0]; a.wall_y = p.wall[1]; a.wall_z = p.wall[2];
+    a.N = N;
+    a.QN = (uint32_t)q * N;
+    a.omega = 1.0 / p.tau;
+    a.guo = 1.0 - 0.5 / p.tau;
+    a.A = p.A;
+    a.beta = p.beta;
+    a.half_rho0 = 0.5 * p.rho0;
+    a.fx = p.body_force[0]; a.fy = p.body_force[1]; a.fz = p.body_force[2];
+    a.nc_A = p.nc_A;
+    a.nc_hmin = p.nc_hmin;
+    a.nc_steps = (int)std::floor(p.nc_hmax);
+    a.phi_I = p.phi_interface;
+    a.z_per_block = z_per_block;
+    return a;
+  }
+  FieldPtrs field_ptrs() const { return FieldPtrs{rho_a, rho_b, u, fnc, flags}; }
+};
+
+extern "C" {
+
+void lb_params_default(lb_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->lattice = LB_D3Q27;
+  p->storage = LB_F32;
+  p->nc_mode = LB_NC_OFF;
+  p->nx = p->ny = p->nz = 64;
+  p->tau = 1.0;
+  p->A = 0.01;
+  p->beta = 0.7;
+  p->rho0 = 1.0;
+  p->nc_A = 0.02;
+  p->nc_hmin = 2.0;
+  p->nc_hmax = 3.0;
+  p->phi_interface = 0.9;
+}
+
+const char* lb_error_string(int code) {
+  switch (code) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "out of device memory";
+    case LB_EHIP: return "HIP runtime error";
+    case LB_ENUMERIC: return "numerical watchdog tripped (NaN/Inf, rho <= 0 or |u| > 0.3)";
+    case LB_ENODEV: return "no HIP device";
+    case LB_EUNSUPPORTED: return "not supported by this build";
+  }
+  return "unknown status";
+}
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+int lb_lattice_table(int lattice, int* q, int* c, double* w, int* opp, double* B) {
+  auto fill = [&](auto L) -> int {
+    using Lt = decltype(L);
+    if (q) *q = Lt::Q;
+    for (int i = 0; i < Lt::Q; ++i) {
+      if (c) { c[3 * i] = Lt::cx[i]; c[3 * i + 1] = Lt::cy[i]; c[3 * i + 2] = Lt::cz[i]; }
+      if (w) w[i] = Lt::w[i];
+      if (opp) opp[i] = Lt::opp[i];
+      if (B) B[i] = B_coef<Lt>(i);
+    }
+    return LB_OK;
+  };
+  switch (lattice) {
+    case LB_D2Q9: return fill(D2Q9{});
+    case LB_D3Q19: return fill(D3Q19{});
+    case LB_D3Q27: return fill(D3Q27{});
+  }
+  return fail(LB_EINVAL, "unknown lattice %d", lattice);
+}
+
+static int validate(const lb_params* p) {
+  if (!p) return fail(LB_EINVAL, "params is NULL");
+  if (!ops_for(p->lattice)) return fail(LB_EINVAL, "unknown lattice %d", p->lattice);
+  if (storage_bytes(p->storage) == 0) return fail(LB_EINVAL, "unknown storage %d", p->storage);
+  if (p->nc_mode != LB_NC_OFF && p->nc_mode != LB_NC_EXPLICIT) return fail(LB_EINVAL, "unknown nc_mode %d", p->nc_mode);
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return fail(LB_EINVAL, "sizes must be positive");
+  if (p->lattice == LB_D2Q9 && (p->nz != 1 || p->wall[2])) return fail(LB_EINVAL, "D2Q9 needs nz == 1 and no z wall");
+  if (p->lattice == LB_D2Q9 && (p->body_force[2] != 0.0 || p->u0[2] != 0.0))
+    return fail(LB_EINVAL, "D2Q9 needs zero z components of body_force and u0");
+  for (int a = 0; a < 3; ++a)
+    if (p->wall[a] != 0 && p->wall[a] != 1) return fail(LB_EINVAL, "wall[%d] must be 0 or 1", a);
+  const double N = (double)p->nx * p->ny * p->nz;
+  const int q = ops_for(p->lattice)->q;
+  if (N * q >= 4294967295.0) return fail(LB_EINVAL, "Q * sites must stay below 2^32 (got %.0f)", N * q);
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must exceed 1/2");
+  if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive");
+  if (!(p->phi_interface > 0.0 && p->phi_interface < 1.0)) return fail(LB_EINVAL, "phi_interface must lie in (0,1)");
+  if (!std::isfinite(p->A) || !std::isfinite(p->beta)) return fail(LB_EINVAL, "A and beta must be finite");
+  if (p->nc_mode != LB_NC_OFF) {
+    if (!(p->nc_hmax >= 1.0 && p->nc_hmax < 4.0)) return fail(LB_EINVAL, "nc_hmax must lie in [1, 4)");
+    if (!(p->nc_hmin > 0.0)) return fail(LB_EINVAL, "nc_hmin must be positive");
+  }
+  if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
+  return LB_OK;
+}
+
+int lb_destroy(lb_handle* h) {
+  if (!h) return LB_OK;
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipSetDevice(h->device);
+  if (h->stream) hipStreamSynchronize(h->stream);
+  else hipDeviceSynchronize();
+  for (hipEvent_t e : h->prof_events) hipEventDestroy(e);
+  void* bufs[] = {h->f[0], h->f[1], h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
+                  h->diag_partial, h->diag_out, h->ccl_count, h->drops};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  hipSetDevice(dev);
+  delete h;
+  return LB_OK;
+}
+
+static int dev_alloc(void** p, size_t bytes, const char* what) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EHIP, "hipMalloc(%s, %zu bytes): %s", what, bytes,
+                hipGetErrorString(e));
+  }
+  return LB_OK;
+}
+
+int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** out) {
+  if (!out) return fail(LB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_channels != 1) return fail(LB_EINVAL, "this build takes n_channels == 1 (got %d)", n_channels);
+  int rc = validate(p);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(LB_ENODEV, "no HIP device");
+  }
+  lb_handle* h = new lb_handle();
+  h->p = *p;
+  h->ops = ops_for(p->lattice);
+  h->q = h->ops->q;
+  h->d = h->ops->d;
+  h->N = (uint32_t)((size_t)p->nx * p->ny * p->nz);
+  h->esize = storage_bytes(p->storage);
+  h->rsize = p->storage == LB_F64 ? 8 : 4;
+  h->stream = (hipStream_t)hip_stream;
+  hipGetDevice(&h->device);
+  // pass-2 blocks march through z; aim for about 2048 blocks in flight
+  {
+    const long bxy = (long)((p->nx + TILE_X - 1) / TILE_X) * ((p->ny + TILE_Y - 1) / TILE_Y);
+    long zb = (bxy * p->nz) / 2048;
+    if (zb < 1) zb = 1;
+    if (zb > 16) zb = 16;
+    if (zb > p->nz) zb = p->nz;
+    if (const char* env = std::getenv("LB_Z_PER_BLOCK")) {
+      const long v = std::atol(env);
+      if (v >= 1) zb = v;
+    }
+    h->z_per_block = (int)zb;
+  }
+  const size_t N = h->N;
+  const size_t pop = 2ull * h->q * N * h->esize;
+#define ALLOC(ptr, bytes)                                              \
+  do {                                                                 \
+    int r_ = dev_alloc((void**)&(ptr), (bytes), #ptr);                 \
+    if (r_) { lb_destroy(h); return r_; }                              \
+  } while (0)
+  ALLOC(h->f[0], pop);
+  ALLOC(h->f[1], pop);
+  ALLOC(h->phi, N * h->rsize);
+  ALLOC(h->rho_a, N * h->rsize);
+  ALLOC(h->rho_b, N * h->rsize);
+  ALLOC(h->u, 3 * N * h->rsize);
+  ALLOC(h->fnc, 3 * N * h->rsize);
+  ALLOC(h->flags, N);
+  ALLOC(h->labels, N * 4);
+  ALLOC(h->diag_partial, sizeof(double) * DIAG_BLOCKS * DG_COUNT);
+  ALLOC(h->diag_out, sizeof(double) * DG_COUNT);
+  ALLOC(h->ccl_count, sizeof(unsigned int));
+#undef ALLOC
+  *out = h;
+  g_err.clear();
+  return LB_OK;
+}
+
+int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, const double* radii, double width,
+                     double phi_in) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
+  if (n < 0 || (n > 0 && (!centres || !radii))) return fail(LB_EINVAL, "bad droplet list");
+  if (!(width > 0.0)) return fail(LB_EINVAL, "width must be positive");
+  if (!(phi_in == 1.0 || phi_in == -1.0)) return fail(LB_EINVAL, "phi_in must be +1 or -1");
+  std::vector<double> host(4 * (size_t)(n > 0 ? n : 1), 0.0);
+  for (int d = 0; d < n; ++d) {
+    for (int a = 0; a < 3; ++a) host[4 * d + a] = centres[3 * d + a];
+    host[4 * d + 3] = radii[d];
+    if (!(radii[d] >= 0.0) || !std::isfinite(centres[3 * d]) || !std::isfinite(centres[3 * d + 1]) ||
+        !std::isfinite(centres[3 * d + 2]))
+      return fail(LB_EINVAL, "droplet %d has a bad centre or radius", d);
+  }
+  hipSetDevice(h->device);
+  if (n > h->drops_cap) {
+    if (h->drops) HIP_TRY(hipFree(h->drops));
+    h->drops = nullptr;
+    h->drops_cap = 0;
+    int r = dev_alloc((void**)&h->drops, sizeof(double) * 4 * n, "drops");
+    if (r) return r;
+    h->drops_cap = n;
+  }
+  if (n > 0) HIP_TRY(hipMemcpyAsync(h->drops, host.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice, h->stream));
+  InitArgs a{};
+  a.nx = h->p.nx; a.ny = h->p.ny; a.nz = h->p.nz; a.dims = h->d;
+  a.wall_x = h->p.wall[0]; a.wall_y = h->p.wall[1]; a.wall_z = h->p.wall[2];
+  a.N = h->N; a.QN = (uint32_t)h->q * h->N;
+  a.ndrop = n;
+  a.width = width; a.phi_in = phi_in; a.rho0 = h->p.rho0;
+  a.u0x = h->p.u0[0]; a.u0y = h->p.u0[1]; a.u0z = h->d == 3 ? h->p.u0[2] : 0.0;
+  a.half_rho0 = 0.5 * h->p.rho0;
+  a.phi_I = h->p.phi_interface;
+  h->cur = 0;
+  HIP_TRY(h->ops->init(h->p.storage, h->f[0], h->phi, h->field_ptrs(), h->drops, a, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));  // the host droplet list goes out of scope
+  h->t = 0;
+  h->initialised = true;
+  h->fields_valid = true;
+  return LB_OK;
+}
+
+// record the first (begin) or second (end) event of pair slot `k`; grows the pool
+static int prof_mark(lb_handle* h, int kind, bool begin) {
+  if (!h->prof_on) return LB_OK;
+  if (begin) {
+    if (2 * (h->prof_used + 1) > h->prof_events.size()) {
+      for (int j = 0; j < 2; ++j) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        h->prof_events.push_back(e);
+      }
+      h->prof_kind.push_back(kind);
+    }
+    h->prof_kind[h->prof_used] = kind;
+    HIP_TRY(hipEventRecord(h->prof_events[2 * h->prof_used], h->stream));
+  } else {
+    HIP_TRY(hipEventRecord(h->prof_events[2 * h->prof_used + 1], h->stream));
+    h->prof_used += 1;
+  }
+  return LB_OK;
+}
+
+static int run_diag(lb_handle* h) {
+  DiagArgs a{};
+  a.N = h->N;
+  a.fx = h->p.body_force[0]; a.fy = h->p.body_force[1]; a.fz = h->d == 3 ? h->p.body_force[2] : 0.0;
+  a.umax_ok = 0.3;
+  if (h->p.storage == LB_F64) {
+    k_diag_partial<double><<<DIAG_BLOCKS, DIAG_THREADS, 0, h->stream>>>(
+        (const double*)h->rho_a, (const double*)h->rho_b, (const double*)h->u, (const double*)h->fnc,
+        (const double*)h->phi, h->diag_partial, a);
+  } else {
+    k_diag_partial<float><<<DIAG_BLOCKS, DIAG_THREADS, 0, h->stream>>>(
+        (const float*)h->rho_a, (const float*)h->rho_b, (const float*)h->u, (const float*)h->fnc,
+        (const float*)h->phi, h->diag_partial, a);
+  }
+  HIP_TRY(hipGetLastError());
+  k_diag_final<<<1, DIAG_THREADS, 0, h->stream>>>(h->diag_partial, DIAG_BLOCKS, h->diag_out);
+  HIP_TRY(hipGetLastError());
+  return LB_OK;
+}
+
+int lb_step(lb_handle* h, int nsteps) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  if (!h->initialised) return fail(LB_EINVAL, "call lb_init_droplets or lb_set_state first");
+  hipSetDevice(h->device);
+  const StepArgs a = h->step_args();
+  const FieldPtrs fo = h->field_ptrs();
+  const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
+  for (int s = 0; s < nsteps; ++s) {
+    const bool diag_now = h->p.diag_every > 0 && ((h->t + 1) % h->p.diag_every) == 0;
+    const bool fields = (s == nsteps - 1) || diag_now;
+    void* fin = h->f[h->cur];
+    void* fout = h->f[1 - h->cur];
+    int r = prof_mark(h, 0, true);
+    if (r) return r;
+    HIP_TRY(h->ops->phase(h->p.storage, fin, h->phi, a, h->stream));
+    if ((r = prof_mark(h, 0, false))) return r;
+    if ((r = prof_mark(h, 1, true))) return r;
+    HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->phi, fo, a, h->stream));
+    if ((r = prof_mark(h, 1, false))) return r;
+    h->cur = 1 - h->cur;
+    h->t += 1;
+    if (fields) h->fields_valid = true;
+    if (diag_now) {
+      r = run_diag(h);
+      if (r) return r;
+      double bad = 0.0;
+      HIP_TRY(hipMemcpyAsync(&bad, h->diag_out + DG_BAD, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      if (bad > 0.0)
+        return fail(LB_ENUMERIC, "watchdog at step %lld: %.0f sites with NaN/Inf, rho <= 0 or |u| > 0.3", h->t, bad);
+    }
+  }
+  return LB_OK;
+}
+
+static int run_labels(lb_handle* h, unsigned int* count_host) {
+  CclArgs c{};
+  c.nx = h->p.nx; c.ny = h->p.ny; c.nz = h->p.nz; c.dims = h->d;
+  c.wall_x = h->p.wall[0]; c.wall_y = h->p.wall[1]; c.wall_z = h->p.wall[2];
+  c.N = h->N;
+  const dim3 grid((h->N + 255) / 256), block(256);
+  if (h->p.storage == LB_F64)
+    k_ccl_init<double><<<grid, block, 0, h->stream>>>((const double*)h->phi, h->labels, h->N);
+  else
+    k_ccl_init<float><<<grid, block, 0, h->stream>>>((const float*)h->phi, h->labels, h->N);
+  HIP_TRY(hipGetLastError());
+  k_ccl_merge<<<grid, block, 0, h->stream>>>(h->labels, c);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemsetAsync(h->ccl_count, 0, sizeof(unsigned int), h->stream));
+  k_ccl_flatten<<<grid, block, 0, h->stream>>>(h->labels, h->N, h->ccl_count);
+  HIP_TRY(hipGetLastError());
+  if (count_host) {
+    HIP_TRY(hipMemcpyAsync(count_host, h->ccl_count, sizeof(unsigned int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  return LB_OK;
+}
+
+int lb_fields(lb_handle* h, int channel, unsigned mask, void* const* dst, int dst_on_device) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
+  if (mask >> LB_NUM_FIELDS) return fail(LB_EINVAL, "unknown field bits in mask 0x%x", mask);
+  if (mask && !dst) return fail(LB_EINVAL, "dst is NULL");
+  if (!h->fields_valid) return fail(LB_EINVAL, "no fields yet: initialise or take a step after lb_set_state");
+  for (int b = 0; b < LB_NUM_FIELDS; ++b)
+    if ((mask >> b) & 1u)
+      if (!dst[b]) return fail(LB_EINVAL, "dst[%d] is NULL for a selected field", b);
+  hipSetDevice(h->device);
+  const size_t N = h->N, r = h->rsize;
+  const void* src[LB_NUM_FIELDS] = {h->rho_a, h->rho_b, h->phi, h->u, h->fnc, h->flags, h->labels};
+  const size_t bytes[LB_NUM_FIELDS] = {N * r, N * r, N * r, 3 * N * r, 3 * N * r, N, 4 * N};
+  if (mask & LB_FIELD_LABELS) {
+    int rc = run_labels(h, nullptr);
+    if (rc) return rc;
+  }
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int b = 0; b < LB_NUM_FIELDS; ++b)
+    if ((mask >> b) & 1u) HIP_TRY(hipMemcpyAsync(dst[b], src[b], bytes[b], kind, h->stream));
+  if (!dst_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+int lb_diagnostics(lb_handle* h, int channel, double out[8]) {
+  if (!h || !out) return fail(LB_EINVAL, "NULL argument");
+  if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
+  if (!h->fields_valid) return fail(LB_EINVAL, "no fields yet: initialise or take a step after lb_set_state");
+  hipSetDevice(h->device);
+  int rc = run_diag(h);
+  if (rc) return rc;
+  double d[DG_COUNT];
+  HIP_TRY(hipMemcpyAsync(d, h->diag_out, sizeof d, hipMemcpyDeviceToHost, h->stream));
+  unsigned int count = 0;
+  rc = run_labels(h, &count);  // synchronises
+  if (rc) return rc;
+  out[0] = d[DG_RHOA];
+  out[1] = d[DG_RHOB];
+  out[2] = d[DG_JX];
+  out[3] = d[DG_JY];
+  out[4] = d[DG_JZ];
+  out[5] = d[DG_UMAX];
+  out[6] = (double)count;
+  out[7] = (d[DG_N_IN] > 0 && d[DG_N_OUT] > 0)
+               ? (d[DG_RHO_IN] / d[DG_N_IN] - d[DG_RHO_OUT] / d[DG_N_OUT]) / 3.0
+               : std::nan("");
+  return LB_OK;
+}
+
+int lb_state_bytes(const lb_handle* h, size_t* bytes) {
+  if (!h || !bytes) return fail(LB_EINVAL, "NULL argument");
+  *bytes = 2ull * h->q * h->N * h->esize;
+  return LB_OK;
+}
+
+int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device) {
+  if (!h || !dst) return fail(LB_EINVAL, "NULL argument");
+  const size_t need = 2ull * h->q * h->N * h->esize;
+  if (bytes != need) return fail(LB_EINVAL, "state is %zu bytes, got %zu", need, bytes);
+  hipSetDevice(h->device);
+  HIP_TRY(hipMemcpyAsync(dst, h->f[h->cur], need, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         h->stream));
+  if (!dst_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device) {
+  if (!h || !src) return fail(LB_EINVAL, "NULL argument");
+  const size_t need = 2ull * h->q * h->N * h->esize;
+  if (bytes != need) return fail(LB_EINVAL, "state is %zu bytes, got %zu", need, bytes);
+  hipSetDevice(h->device);
+  HIP_TRY(hipMemcpyAsync(h->f[h->cur], src, need, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         h->stream));
+  if (!src_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
+  h->initialised = true;
+  h->fields_valid = false;
+  return LB_OK;
+}
+
+int lb_step_count(const lb_handle* h, long long* t) {
+  if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+  *t = h->t;
+  return LB_OK;
+}
+
+int lb_profile_begin(lb_handle* h) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  h->prof_on = true;
+  h->prof_used = 0;
+  return LB_OK;
+}
+
+int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_phase, int* n_collide) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  hipSetDevice(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  double t[2] = {0.0, 0.0};
+  int n[2] = {0, 0};
+  for (size_t k = 0; k < h->prof_used; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->prof_events[2 * k], h->prof_events[2 * k + 1]));
+    t[h->prof_kind[k]] += ms;
+    n[h->prof_kind[k]] += 1;
+  }
+  h->prof_on = false;
+  h->prof_used = 0;
+  if (ms_phase) *ms_phase = t[0];
+  if (ms_collide) *ms_collide = t[1];
+  if (n_phase) *n_phase = n[0];
+  if (n_collide) *n_collide = n[1];
+  return LB_OK;
+}
+
+int lb_sync(lb_handle* h) {
+  if (!h) return fail(LB_EINVAL, "handle is NULL");
+  hipSetDevice(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+}  // extern "C"

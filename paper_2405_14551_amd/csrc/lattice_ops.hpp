@@ -1,0 +1,89 @@
+// Host-side launchers of the step kernels for one velocity set; included once
+// per lattice by lattice_d2q9.hip / lattice_d3q19.hip / lattice_d3q27.hip so
+// that the heavy instantiations compile in parallel.
+#pragma once
+
+#include "engine.hpp"
+
+namespace lbm {
+
+template <class L>
+struct Launch {
+  template <class S>
+  static hipError_t phase_t(const void* fin, void* phi, const StepArgs& a, hipStream_t s) {
+    using R = typename Storage<S>::real;
+    dim3 block(64, 4, 1);
+    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz);
+    k_phase<L, S><<<grid, block, 0, s>>>((const S*)fin, (R*)phi, a);
+    return hipGetLastError();
+  }
+
+  static hipError_t phase(int st, const void* fin, void* phi, const StepArgs& a, hipStream_t s) {
+    switch (st) {
+      case ST_F64: return phase_t<double>(fin, phi, a, s);
+      case ST_F32: return phase_t<float>(fin, phi, a, s);
+      case ST_F16: return phase_t<_Float16>(fin, phi, a, s);
+      case ST_BF16: return phase_t<__bf16>(fin, phi, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+
+  template <class S, int RAD, bool NC, bool FIELDS>
+  static hipError_t collide_t(const void* fin, void* fout, const void* phi, const FieldPtrs& fo,
+                              const StepArgs& a, hipStream_t s) {
+    using R = typename Storage<S>::real;
+    using T = Tile<TILE_X, TILE_Y, RAD, L::D>;
+    dim3 block(T::TX, T::TY, 1);
+    const int zb = a.z_per_block;
+    dim3 grid((a.nx + T::TX - 1) / T::TX, (a.ny + T::TY - 1) / T::TY, (a.nz + zb - 1) / zb);
+    k_collide<L, S, T, NC, FIELDS><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, fo, a);
+    return hipGetLastError();
+  }
+
+  template <class S>
+  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, const void* phi,
+                              const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+    if (nc) {
+      return fields ? collide_t<S, 4, true, true>(fin, fout, phi, fo, a, s)
+                    : collide_t<S, 4, true, false>(fin, fout, phi, fo, a, s);
+    }
+    return fields ? collide_t<S, 1, false, true>(fin, fout, phi, fo, a, s)
+                  : collide_t<S, 1, false, false>(fin, fout, phi, fo, a, s);
+  }
+
+  static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, const void* phi,
+                            const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+    switch (st) {
+      case ST_F64: return collide_s<double>(nc, fields, fin, fout, phi, fo, a, s);
+      case ST_F32: return collide_s<float>(nc, fields, fin, fout, phi, fo, a, s);
+      case ST_F16: return collide_s<_Float16>(nc, fields, fin, fout, phi, fo, a, s);
+      case ST_BF16: return collide_s<__bf16>(nc, fields, fin, fout, phi, fo, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+
+  template <class S>
+  static hipError_t init_t(void* f, void* phi, const FieldPtrs& fo, const double* drops, const InitArgs& a,
+                           hipStream_t s) {
+    using R = typename Storage<S>::real;
+    dim3 block(256);
+    dim3 grid((a.N + 255) / 256);
+    k_init<L, S><<<grid, block, 0, s>>>((S*)f, (R*)phi, fo, drops, a);
+    return hipGetLastError();
+  }
+
+  static hipError_t init(int st, void* f, void* phi, const FieldPtrs& fo, const double* drops,
+                         const InitArgs& a, hipStream_t s) {
+    switch (st) {
+      case ST_F64: return init_t<double>(f, phi, fo, drops, a, s);
+      case ST_F32: return init_t<float>(f, phi, fo, drops, a, s);
+      case ST_F16: return init_t<_Float16>(f, phi, fo, drops, a, s);
+      case ST_BF16: return init_t<__bf16>(f, phi, fo, drops, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+
+  static LatticeOps ops() { return LatticeOps{L::Q, L::D, &phase, &collide, &init}; }
+};
+
+}  // namespace lbm

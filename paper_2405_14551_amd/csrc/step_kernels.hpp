@@ -1,0 +1,396 @@
+// Device kernels of one colour-gradient lattice Boltzmann time step on gfx950.
+//
+// A step is two launches over the lattice:
+//   pass 1  (k_phase):   pull the 2Q populations of every site (periodic wrap or
+//                        halfway bounce-back) and write the phase field
+//                        phi = (rho_A - rho_B)/(rho_A + rho_B)            [Sec. III.C.1]
+//   pass 2  (k_collide): stage phi of a tile plus a halo in LDS, marching along z
+//                        through a ring of planes; colour gradient (isotropic
+//                        lattice stencil), interface flag, near-contact scan on
+//                        interface sites (Eq. near_cont_force), pull the
+//                        populations again, Guo-forced BGK on the total
+//                        (Eq. disteq), perturbation Omega^(2), recolouring
+//                        (Eqs. ome3_1, ome3_2), store into the other buffer.
+// The colour gradient at t+1 needs phi of the neighbours after streaming, so
+// the phase field has to be complete before any site collides; the two passes
+// are that dependency.
+//
+// Layout: populations f[k][i][s] (k colour, i velocity, s = x + nx (y + ny z)),
+// x fastest, so each wave's 64 lanes touch 64 consecutive sites of one row for
+// every (k, i): the ±1 pull offsets keep the accesses within two 128-byte lines.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+// ----------------------------------------------------------------------------
+// compile-time loop
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// storage policies: how a population is kept in HBM and turned into the
+// arithmetic type.  The 16-bit policies store the shifted value
+// f^k_i - w_i rho0 / 2 rounded to nearest even and add the shift on load.
+template <class S>
+struct Storage;
+
+template <>
+struct Storage<double> {
+  using real = double;
+  template <int I, class L>
+  __device__ static __forceinline__ double load(const double* p, double) { return *p; }
+  template <int I, class L>
+  __device__ static __forceinline__ void store(double* p, double v, double) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Storage<float> {
+  using real = float;
+  template <int I, class L>
+  __device__ static __forceinline__ float load(const float* p, float) { return *p; }
+  template <int I, class L>
+  __device__ static __forceinline__ void store(float* p, float v, float) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Storage<_Float16> {
+  using real = float;
+  template <int I, class L>
+  __device__ static __forceinline__ float load(const _Float16* p, float half_rho0) {
+    return (float)(*p) + (float)L::w[I] * half_rho0;
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ void store(_Float16* p, float v, float half_rho0) {
+    *p = (_Float16)(v - (float)L::w[I] * half_rho0);
+  }
+};
+
+template <>
+struct Storage<__bf16> {
+  using real = float;
+  template <int I, class L>
+  __device__ static __forceinline__ float load(const __bf16* p, float half_rho0) {
+    return (float)(*p) + (float)L::w[I] * half_rho0;
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ void store(__bf16* p, float v, float half_rho0) {
+    *p = (__bf16)(v - (float)L::w[I] * half_rho0);
+  }
+};
+
+// ----------------------------------------------------------------------------
+// per-launch constants (passed by value, lives in SGPRs)
+struct StepArgs {
+  int nx, ny, nz;
+  int wall_x, wall_y, wall_z;
+  uint32_t N;        // sites
+  uint32_t QN;       // Q * N (elements per colour)
+  double omega;      // 1/tau
+  double guo;        // 1 - 1/(2 tau)
+  double A;          // perturbation amplitude
+  double beta;       // recolouring
+  double half_rho0;  // storage shift per colour is w_i * rho0 / 2
+  double fx, fy, fz; // body force density
+  double nc_A, nc_hmin;
+  int nc_steps;      // floor(nc_hmax)
+  double phi_I;      // interface threshold
+  int z_per_block;   // planes a pass-2 block marches through
+};
+
+struct FieldPtrs {
+  void* rho_a;
+  void* rho_b;
+  void* u;      // [3][N]
+  void* fnc;    // [3][N]
+  uint8_t* flags;
+};
+
+// ----------------------------------------------------------------------------
+// neighbour bookkeeping of one site for the pull: the source of direction i
+// is x - c_i; on a walled axis a source outside [0, n) is solid and the
+// population is bounced back from the site itself (halfway bounce-back).
+struct Nbr {
+  uint32_t site;
+  uint32_t xs[3];   // x - 1, x, x + 1 (wrapped)      indexed by 1 - c
+  uint32_t ys[3];   // row offsets
+  uint32_t zs[3];   // plane offsets
+  bool solid_x[3], solid_y[3], solid_z[3];
+};
+
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const StepArgs& a) {
+  Nbr n;
+  const uint32_t nx = a.nx, nxy = (uint32_t)a.nx * a.ny;
+  n.site = x + nx * y + nxy * z;
+  int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
+  int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
+  // index 0 <-> c = +1 (source x-1), 1 <-> c = 0, 2 <-> c = -1 (source x+1)
+  n.xs[0] = xm; n.xs[1] = x; n.xs[2] = xp;
+  n.ys[0] = ym * nx; n.ys[1] = y * nx; n.ys[2] = yp * nx;
+  n.zs[0] = zm * nxy; n.zs[1] = z * nxy; n.zs[2] = zp * nxy;
+  n.solid_x[0] = a.wall_x && x == 0; n.solid_x[1] = false; n.solid_x[2] = a.wall_x && x == a.nx - 1;
+  n.solid_y[0] = a.wall_y && y == 0; n.solid_y[1] = false; n.solid_y[2] = a.wall_y && y == a.ny - 1;
+  n.solid_z[0] = a.wall_z && z == 0; n.solid_z[1] = false; n.solid_z[2] = a.wall_z && z == a.nz - 1;
+  return n;
+}
+
+// element index (within one colour block) of the pulled population i at site n
+template <class L, int I>
+__device__ __forceinline__ uint32_t pull_index(const Nbr& n, uint32_t N) {
+  constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
+  const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
+  const uint32_t src = n.xs[ix] + n.ys[iy] + n.zs[iz];
+  return solid ? (uint32_t)L::opp[I] * N + n.site : (uint32_t)I * N + src;
+}
+
+// ----------------------------------------------------------------------------
+// pass 1: phase field of the post-streaming populations
+template <class L, class S>
+__global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
+                                               typename Storage<S>::real* __restrict__ phi,
+                                               StepArgs a) {
+  using R = typename Storage<S>::real;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const Nbr n = make_nbr(x, y, z, a);
+  const R h = (R)a.half_rho0;
+  R ra = 0, rb = 0;
+  static_for<0, L::Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const uint32_t e = pull_index<L, I>(n, a.N);
+    ra += Storage<S>::template load<I, L>(fin + e, h);
+    rb += Storage<S>::template load<I, L>(fin + a.QN + e, h);
+  });
+  phi[n.site] = (ra - rb) / (ra + rb);
+}
+
+// ----------------------------------------------------------------------------
+// pass 2 geometry
+template <int TX_, int TY_, int RAD_, int D_>
+struct Tile {
+  static constexpr int TX = TX_, TY = TY_, RAD = RAD_;
+  static constexpr int RZ = D_ == 3 ? RAD_ : 0;        // z halo
+  static constexpr int NPL = 2 * RZ + 1;               // planes in the ring
+  static constexpr int TXH = TX + 2 * RAD, TYH = TY + 2 * RAD;
+  static constexpr int PL = TXH * TYH;                  // elements per plane
+  static constexpr int NT = TX * TY;
+};
+
+// map a halo coordinate to the node whose phi it holds: periodic wrap, or the
+// mirror image across the wall plane (ghost at -1-k holds node k); positions
+// more than one layer beyond a wall are never read by a valid computation and
+// are clamped.
+__device__ __forceinline__ int halo_coord(int g, int n, int wall) {
+  if (wall) {
+    if (g < 0) g = -1 - g;
+    else if (g >= n) g = 2 * n - 1 - g;
+    g = g < 0 ? 0 : (g >= n ? n - 1 : g);
+  } else {
+    while (g < 0) g += n;
+    while (g >= n) g -= n;
+  }
+  return g;
+}
+
+template <class T, class R>
+__device__ __forceinline__ void load_plane(R* __restrict__ ring, int slot, int zz,
+                                           const R* __restrict__ phi, int x0, int y0,
+                                           const StepArgs& a, int tid) {
+  const int gz = halo_coord(zz, a.nz, a.wall_z);
+  const size_t zoff = (size_t)gz * a.nx * a.ny;
+  R* dst = ring + slot * T::PL;
+  for (int e = tid; e < T::PL; e += T::NT) {
+    const int hy = e / T::TXH, hx = e - hy * T::TXH;
+    const int gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
+    const int gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
+    dst[e] = phi[zoff + (size_t)gy * a.nx + gx];
+  }
+}
+
+__device__ __forceinline__ int ring_slot(int zc, int dz, int npl) {
+  int s = zc + dz;
+  s = s >= npl ? s - npl : s;
+  s = s < 0 ? s + npl : s;
+  return s;
+}
+
+template <class R>
+__device__ __forceinline__ R round_half_away(R v) {
+  return v >= R(0) ? floor(v + R(0.5)) : -floor(-v + R(0.5));
+}
+
+// colour gradient g = 3 sum_i w_i c_i phi(x + c_i) at ring position `c0`, with
+// the three plane bases for dz = -1, 0, +1
+template <class L, class T, class R>
+__device__ __forceinline__ void ring_gradient(const R* __restrict__ ring, int c0, int pm, int p0, int pp,
+                                              R& gx, R& gy, R& gz) {
+  gx = 0; gy = 0; gz = 0;
+  static_for<1, L::Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+    const int pb = cz < 0 ? pm : (cz > 0 ? pp : p0);
+    const R v = ring[pb + c0 + cy * T::TXH + cx] * (R)(3.0 * L::w[I]);
+    if constexpr (cx != 0) gx += (R)cx * v;
+    if constexpr (cy != 0) gy += (R)cy * v;
+    if constexpr (cz != 0) gz += (R)cz * v;
+  });
+}
+
+// ----------------------------------------------------------------------------
+// pass 2: gradient, flags, near contact, collision, recolouring, store
+template <class L, class S, class T, bool NC, bool FIELDS>
+__global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
+                                                    const typename Storage<S>::real* __restrict__ phi,
+                                                    FieldPtrs fo, StepArgs a) {
+  using R = typename Storage<S>::real;
+  __shared__ R ring[T::NPL * T::PL];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + T::TX * ty;
+  const int x0 = blockIdx.x * T::TX, y0 = blockIdx.y * T::TY;
+  const int z0 = blockIdx.z * a.z_per_block;
+  const int z1 = min(z0 + a.z_per_block, a.nz);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool valid_xy = x < a.nx && y < a.ny;
+
+  // preload planes z0 - RZ .. z0 + RZ - 1; plane zz lives in slot (zz + NPL) % NPL
+  for (int dz = -T::RZ; dz < T::RZ; ++dz)
+    load_plane<T>(ring, (z0 + dz + T::NPL * 4) % T::NPL, z0 + dz, phi, x0, y0, a, tid);
+
+  const R omega = (R)a.omega, guo = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
+  const R hshift = (R)a.half_rho0, phiI = (R)a.phi_I;
+  const int c0 = (ty + T::RAD) * T::TXH + (tx + T::RAD);
+
+  for (int z = z0; z < z1; ++z) {
+    const int zc = (z + T::NPL * 4) % T::NPL;
+    load_plane<T>(ring, ring_slot(zc, T::RZ, T::NPL), z + T::RZ, phi, x0, y0, a, tid);
+    __syncthreads();
+    if (valid_xy) {
+      const int p0 = zc * T::PL;
+      constexpr int dz1 = T::RZ ? 1 : 0;   // 2D: a single plane
+      const int pm = ring_slot(zc, -dz1, T::NPL) * T::PL;
+      const int pp = ring_slot(zc, dz1, T::NPL) * T::PL;
+      // ---- colour gradient, flag
+      R gx, gy, gz;
+      ring_gradient<L, T, R>(ring, c0, pm, p0, pp, gx, gy, gz);
+      const R phic = ring[p0 + c0];
+      const bool flag = fabs(phic) < phiI;
+      const R gg = gx * gx + gy * gy + gz * gz;
+      // ---- near-contact force (explicit scan, interface sites only)
+      R fnx = 0, fny = 0, fnz = 0;
+      if constexpr (NC) {
+        if (flag && gg > R(0)) {
+          const R inv = R(1) / sqrt(gg);
+          const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
+          int hit = 0;
+          for (int s = 1; s <= a.nc_steps; ++s) {
+            // |s m| <= 3; the clamp only guards the LDS index against non-finite m
+            const int ox = max(-3, min(3, (int)round_half_away((R)s * mx)));
+            const int oy = max(-3, min(3, (int)round_half_away((R)s * my)));
+            const int oz = max(-3, min(3, (int)round_half_away((R)s * mz)));
+            if (a.wall_x && (x + ox < 0 || x + ox >= a.nx)) break;
+            if (a.wall_y && (y + oy < 0 || y + oy >= a.ny)) break;
+            if (a.wall_z && (z + oz < 0 || z + oz >= a.nz)) break;
+            const int cy0 = c0 + oy * T::TXH + ox;
+            const int py0 = ring_slot(zc, oz, T::NPL) * T::PL;
+            const R phy = ring[py0 + cy0];
+            if (fabs(phy) < phiI) {
+              const int pym = T::RZ ? ring_slot(zc, oz - 1, T::NPL) * T::PL : py0;
+              const int pyp = T::RZ ? ring_slot(zc, oz + 1, T::NPL) * T::PL : py0;
+              R hx, hy, hz;
+              ring_gradient<L, T, R>(ring, cy0, pym, py0, pyp, hx, hy, hz);
+              if (hx * gx + hy * gy + hz * gz < R(0)) { hit = s; break; }
+            }
+          }
+          if (hit) {
+            const R h = (R)hit, hmin = (R)a.nc_hmin;
+            R Ah = (R)a.nc_A;
+            if (h > hmin) { const R r = hmin / h; Ah = Ah * r * r * r; }
+            fnx = R(0.5) * Ah * gx; fny = R(0.5) * Ah * gy; fnz = R(0.5) * Ah * gz;
+          }
+        }
+      }
+      // ---- pull the populations
+      const Nbr n = make_nbr(x, y, z, a);
+      R f[L::Q];
+      R ra = 0, rb = 0;
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const uint32_t e = pull_index<L, I>(n, a.N);
+        const R va = Storage<S>::template load<I, L>(fin + e, hshift);
+        const R vb = Storage<S>::template load<I, L>(fin + a.QN + e, hshift);
+        ra += va; rb += vb;
+        f[I] = va + vb;
+      });
+      R jx = 0, jy = 0, jz = 0;
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if constexpr (L::cx[I] != 0) jx += (R)L::cx[I] * f[I];
+        if constexpr (L::cy[I] != 0) jy += (R)L::cy[I] * f[I];
+        if constexpr (L::cz[I] != 0) jz += (R)L::cz[I] * f[I];
+      });
+      const R rho = ra + rb;
+      const R inv_rho = R(1) / rho;
+      const R Fx = (R)a.fx + fnx, Fy = (R)a.fy + fny, Fz = (R)a.fz + fnz;
+      const R ux = (jx + R(0.5) * Fx) * inv_rho;
+      const R uy = (jy + R(0.5) * Fy) * inv_rho;
+      const R uz = (jz + R(0.5) * Fz) * inv_rho;
+      const R uu = ux * ux + uy * uy + uz * uz;
+      const R uF = ux * Fx + uy * Fy + uz * Fz;
+      const bool has_g = gg > R(0);
+      const R gn = has_g ? sqrt(gg) : R(0);
+      const R inv_gg = has_g ? R(1) / gg : R(0);
+      const R inv_gn = has_g ? R(1) / gn : R(0);
+      const R Agn = has_g ? Aamp * gn : R(0);
+      const R fa_frac = ra * inv_rho;                  // rho_A / rho
+      const R coef = beta * ra * rb * inv_rho;         // beta rho_A rho_B / rho
+      const R base_eq = R(1) - R(1.5) * uu;
+      // ---- collide each direction and store the two colours
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+        const R wi = (R)L::w[I];
+        R cu = 0, cF = 0, cg = 0;
+        if constexpr (cx != 0) { cu += (R)cx * ux; cF += (R)cx * Fx; cg += (R)cx * gx; }
+        if constexpr (cy != 0) { cu += (R)cy * uy; cF += (R)cy * Fy; cg += (R)cy * gy; }
+        if constexpr (cz != 0) { cu += (R)cz * uz; cF += (R)cz * Fz; cg += (R)cz * gz; }
+        const R feq = wi * rho * (base_eq + R(3) * cu + R(4.5) * cu * cu);
+        const R src = guo * wi * (R(3) * (cF - uF) + R(9) * cu * cF);
+        R fs = f[I] - omega * (f[I] - feq) + src;
+        fs += Agn * (wi * cg * cg * inv_gg - (R)B_coef<L>(I));
+        R rec = 0;
+        if constexpr (I != 0) rec = coef * wi * (cg * (R)inv_norm<L>(I) * inv_gn);
+        const R fa = fa_frac * fs + rec;
+        const R fb = fs - fa;
+        Storage<S>::template store<I, L>(fout + (size_t)I * a.N + n.site, fa, hshift);
+        Storage<S>::template store<I, L>(fout + a.QN + (size_t)I * a.N + n.site, fb, hshift);
+      });
+      if constexpr (FIELDS) {
+        R* rA = (R*)fo.rho_a;
+        R* rB = (R*)fo.rho_b;
+        R* U = (R*)fo.u;
+        R* Fn = (R*)fo.fnc;
+        rA[n.site] = ra;
+        rB[n.site] = rb;
+        U[n.site] = ux; U[a.N + n.site] = uy; U[2 * (size_t)a.N + n.site] = uz;
+        Fn[n.site] = fnx; Fn[a.N + n.site] = fny; Fn[2 * (size_t)a.N + n.site] = fnz;
+        fo.flags[n.site] = flag ? 1 : 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,263 @@
+"""ctypes binding of the C ABI in ``include/lb.h`` (argument marshalling only).
+
+Every step of the path runs in the HIP library ``liblbmi.so``; this module
+converts Python arguments, allocates caller-owned output tensors with
+PyTorch (device memory) and passes the current PyTorch stream.  If the
+library is missing it raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblbmi.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENUMERIC, LB_ENODEV, LB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+LATTICE = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+NC_MODE = {"off": 0, "explicit": 1}
+FIELD_BITS = {"rho_a": 0, "rho_b": 1, "phi": 2, "u": 3, "f_nc": 4, "flags": 5, "labels": 6}
+Q_OF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class LbParams(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int), ("storage", ctypes.c_int), ("nc_mode", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("wall", ctypes.c_int * 3),
+        ("tau", ctypes.c_double), ("A", ctypes.c_double), ("beta", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3), ("u0", ctypes.c_double * 3),
+        ("nc_A", ctypes.c_double), ("nc_hmin", ctypes.c_double), ("nc_hmax", ctypes.c_double),
+        ("phi_interface", ctypes.c_double),
+        ("diag_every", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+EXPORTED = [
+    "lb_params_default", "lb_create", "lb_init_droplets", "lb_step", "lb_fields",
+    "lb_diagnostics", "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count",
+    "lb_sync", "lb_destroy", "lb_lattice_table", "lb_error_string", "lb_last_error",
+    "lb_profile_begin", "lb_profile_end",
+]
+
+
+def lib():
+    """Load liblbmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2405_14551_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    L.lb_params_default.argtypes = [P(LbParams)]
+    L.lb_params_default.restype = None
+    L.lb_create.argtypes = [P(LbParams), i, vp, P(vp)]
+    L.lb_init_droplets.argtypes = [vp, i, i, P(d), P(d), d, d]
+    L.lb_step.argtypes = [vp, i]
+    L.lb_fields.argtypes = [vp, i, ctypes.c_uint, P(vp), i]
+    L.lb_diagnostics.argtypes = [vp, i, P(d)]
+    L.lb_state_bytes.argtypes = [vp, P(sz)]
+    L.lb_get_state.argtypes = [vp, vp, sz, i]
+    L.lb_set_state.argtypes = [vp, vp, sz, i]
+    L.lb_step_count.argtypes = [vp, P(ctypes.c_longlong)]
+    L.lb_sync.argtypes = [vp]
+    L.lb_destroy.argtypes = [vp]
+    L.lb_lattice_table.argtypes = [i, P(i), P(i), P(d), P(i), P(d)]
+    L.lb_profile_begin.argtypes = [vp]
+    L.lb_profile_end.argtypes = [vp, P(d), P(d), P(i), P(i)]
+    L.lb_error_string.argtypes = [i]
+    L.lb_error_string.restype = ctypes.c_char_p
+    L.lb_last_error.argtypes = []
+    L.lb_last_error.restype = ctypes.c_char_p
+    for name in ["lb_create", "lb_init_droplets", "lb_step", "lb_fields", "lb_diagnostics",
+                 "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count", "lb_sync",
+                 "lb_destroy", "lb_lattice_table", "lb_profile_begin", "lb_profile_end"]:
+        getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def check(code):
+    if code != LB_OK:
+        L = lib()
+        raise LBError(code, f"{L.lb_error_string(code).decode()}: {L.lb_last_error().decode()}")
+    return code
+
+
+def lattice_table(name):
+    """(c int[q,3], w float64[q], opp int[q], B float64[q]) as the library defines them."""
+    L = lib()
+    q = Q_OF[name]
+    qq = ctypes.c_int()
+    c = (ctypes.c_int * (3 * q))()
+    w = (ctypes.c_double * q)()
+    o = (ctypes.c_int * q)()
+    B = (ctypes.c_double * q)()
+    check(L.lb_lattice_table(LATTICE[name], ctypes.byref(qq), c, w, o, B))
+    return (np.array(c[:], dtype=np.int64).reshape(q, 3), np.array(w[:]), np.array(o[:], dtype=np.int64),
+            np.array(B[:]))
+
+
+def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), walls=(0, 0, 0),
+                tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
+                nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0):
+    p = LbParams()
+    lib().lb_params_default(ctypes.byref(p))
+    p.lattice = LATTICE[lattice]
+    p.storage = STORAGE[storage]
+    p.nc_mode = NC_MODE[nc] if isinstance(nc, str) else (1 if nc else 0)
+    p.nx, p.ny, p.nz = (int(v) for v in shape)
+    for a in range(3):
+        p.wall[a] = int(bool(walls[a]))
+        p.body_force[a] = float(body_force[a])
+        p.u0[a] = float(u0[a])
+    p.tau, p.A, p.beta, p.rho0 = float(tau), float(A), float(beta), float(rho0)
+    p.nc_A, p.nc_hmin, p.nc_hmax = float(nc_A), float(nc_hmin), float(nc_hmax)
+    p.phi_interface = float(phi_interface)
+    p.diag_every = int(diag_every)
+    return p
+
+
+class Simulation:
+    """One lattice on the current GPU.  Fields come back as torch tensors of
+    shape (nz, ny, nx) or (3, nz, ny, nx)."""
+
+    def __init__(self, lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), stream=None,
+                 **kw):
+        import torch
+        self.torch = torch
+        self.lattice = lattice
+        self.storage = storage
+        self.shape = tuple(int(v) for v in shape)
+        self.q = Q_OF[lattice]
+        self.params = make_params(lattice, storage, nc, shape, **kw)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        check(lib().lb_create(ctypes.byref(self.params), 1, ctypes.c_void_p(stream.cuda_stream),
+                              ctypes.byref(h)))
+        self.h = h
+        self.real = torch.float64 if storage == "f64" else torch.float32
+        self.state_dtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
+                            "bf16": torch.bfloat16}[storage]
+
+    # -------------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            check(lib().lb_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- calls
+    def init_droplets(self, centres, radii, width=2.0, phi_in=1.0):
+        c = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
+        r = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
+        if c.shape[0] != r.shape[0]:
+            raise ValueError("centres and radii differ in length")
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().lb_init_droplets(self.h, 0, int(r.shape[0]), c.ctypes.data_as(dp),
+                                     r.ctypes.data_as(dp), float(width), float(phi_in)))
+        return self
+
+    def step(self, n=1):
+        check(lib().lb_step(self.h, int(n)))
+        return self
+
+    def sync(self):
+        check(lib().lb_sync(self.h))
+
+    def profile_begin(self):
+        check(lib().lb_profile_begin(self.h))
+
+    def profile_end(self):
+        """Returns dict(ms_phase, ms_collide, n_phase, n_collide) summed over launches."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        na, nb = ctypes.c_int(), ctypes.c_int()
+        check(lib().lb_profile_end(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(na),
+                                   ctypes.byref(nb)))
+        return dict(ms_phase=a.value, ms_collide=b.value, n_phase=na.value, n_collide=nb.value)
+
+    @property
+    def t(self):
+        v = ctypes.c_longlong()
+        check(lib().lb_step_count(self.h, ctypes.byref(v)))
+        return v.value
+
+    def fields(self, names=("rho_a", "rho_b", "phi", "u", "f_nc", "flags")):
+        torch = self.torch
+        nx, ny, nz = self.shape
+        out = {}
+        ptrs = (ctypes.c_void_p * 7)()
+        mask = 0
+        for nm in names:
+            b = FIELD_BITS[nm]
+            if nm in ("u", "f_nc"):
+                t = torch.empty((3, nz, ny, nx), dtype=self.real, device=self.device)
+            elif nm == "flags":
+                t = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
+            elif nm == "labels":
+                t = torch.empty((nz, ny, nx), dtype=torch.int32, device=self.device)
+            else:
+                t = torch.empty((nz, ny, nx), dtype=self.real, device=self.device)
+            out[nm] = t
+            ptrs[b] = t.data_ptr()
+            mask |= 1 << b
+        check(lib().lb_fields(self.h, 0, mask, ptrs, 1))
+        self.stream.synchronize()
+        return out
+
+    def diagnostics(self):
+        d = (ctypes.c_double * 8)()
+        check(lib().lb_diagnostics(self.h, 0, d))
+        return np.array(d[:])
+
+    def state_bytes(self):
+        v = ctypes.c_size_t()
+        check(lib().lb_state_bytes(self.h, ctypes.byref(v)))
+        return v.value
+
+    def get_state(self):
+        """Post-collision populations as a device tensor (2, q, nz, ny, nx) of the storage type."""
+        nx, ny, nz = self.shape
+        t = self.torch.empty((2, self.q, nz, ny, nx), dtype=self.state_dtype, device=self.device)
+        check(lib().lb_get_state(self.h, ctypes.c_void_p(t.data_ptr()), self.state_bytes(), 1))
+        self.stream.synchronize()
+        return t
+
+    def set_state(self, t):
+        t = t.to(device=self.device, dtype=self.state_dtype).contiguous()
+        if t.numel() * t.element_size() != self.state_bytes():
+            raise ValueError("state has the wrong size")
+        self.stream.synchronize()
+        check(lib().lb_set_state(self.h, ctypes.c_void_p(t.data_ptr()), self.state_bytes(), 1))
+        self.stream.synchronize()
+        return self

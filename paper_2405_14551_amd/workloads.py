@@ -1,0 +1,119 @@
+"""Seeded synthetic inputs of the benchmark workloads (no method arithmetic).
+
+Droplet centres are drawn by random sequential addition with numpy's PCG64
+generator: a candidate centre is uniform inside the box (keeping a clearance
+of R + 2 sites from walled faces) and is accepted when its surface stays at
+least ``min_gap`` sites from every accepted droplet (minimum image along
+periodic axes).  Both the oracle-based tests and the GPU path receive the
+same explicit centre list.
+
+Workloads (sizes as in the benchmark definitions):
+  laplace_2d    D2Q9 128x64 periodic, FP64, one droplet R=16 at the centre
+  channel_3d    D3Q27 256x128x128, walls y/z, body force 1e-6 x, 64 droplets R=10,
+                near-contact range 3 / strength 0.02, FP32
+  big_3d        same physics on 512x256x256 with 1024 droplets R=8
+  dense_3d      D3Q27 384x384x192, 2000 droplets R=8 on a jittered FCC slab
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED = 14551
+
+
+def rsa_centres(shape, walls, radius, count, seed=SEED, min_gap=3.0, max_tries=200000, dims=3):
+    """Random sequential addition of equal droplets; returns (count, 3) float64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = np.asarray(shape, dtype=np.float64)
+    lo = np.zeros(3)
+    hi = n.copy()
+    for a in range(3):
+        if walls[a]:
+            lo[a] = radius + 2.0
+            hi[a] = n[a] - 1 - (radius + 2.0)
+    cen = np.zeros((0, 3))
+    tries = 0
+    while cen.shape[0] < count:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError(f"placed only {cen.shape[0]} of {count} droplets")
+        c = lo + rng.random(3) * (hi - lo)
+        if dims == 2:
+            c[2] = 0.0
+        if cen.shape[0]:
+            d = cen - c
+            for a in range(dims):
+                if not walls[a]:
+                    d[:, a] -= n[a] * np.round(d[:, a] / n[a])
+            if dims == 2:
+                d[:, 2] = 0.0
+            if np.min(np.sqrt((d * d).sum(1))) < 2 * radius + min_gap:
+                continue
+        cen = np.vstack([cen, c])
+    return cen
+
+
+def fcc_slab_centres(shape, radius, count, gap=2.0, jitter=0.5, seed=SEED):
+    """Droplets on an FCC lattice with nearest-neighbour surface gap ``gap``
+    (+- ``jitter`` uniform displacement per coordinate), filling a slab
+    centred in z; periodic x/y, walls z."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = shape
+    dnn = 2 * radius + gap                   # nearest-neighbour distance
+    a = dnn * np.sqrt(2.0)                   # cubic cell edge
+    mx, my = int(nx // a), int(ny // a)
+    ax, ay = nx / mx, ny / my                # stretch so the cell tiles the periodic box
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    pts = []
+    k = 0
+    zlo = radius + 2.0
+    while len(pts) < count:
+        for i in range(mx):
+            for j in range(my):
+                for b in basis:
+                    z = zlo + (k + b[2]) * a
+                    if z > nz - 1 - (radius + 2.0):
+                        continue
+                    pts.append([(i + b[0]) * ax, (j + b[1]) * ay, z])
+        k += 1
+        if zlo + k * a > nz:
+            break
+    pts = np.array(pts[:count], dtype=np.float64)
+    pts += rng.uniform(-jitter, jitter, pts.shape)
+    # centre the slab in z
+    pts[:, 2] += (nz - 1) / 2.0 - 0.5 * (pts[:, 2].min() + pts[:, 2].max())
+    return pts
+
+
+def laplace_2d():
+    return dict(lattice="D2Q9", storage="f64", nc="off", shape=(128, 64, 1), walls=(0, 0, 0),
+                tau=1.0, A=0.01, beta=0.7, rho0=1.0,
+                centres=np.array([[64.0, 32.0, 0.0]]), radii=np.array([16.0]))
+
+
+def channel_3d(storage="f32", shape=(256, 128, 128), count=64, radius=10.0, seed=SEED):
+    walls = (0, 1, 1)
+    cen = rsa_centres(shape, walls, radius, count, seed)
+    return dict(lattice="D3Q27", storage=storage, nc="explicit", shape=shape, walls=walls,
+                tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(1e-6, 0.0, 0.0),
+                nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0,
+                centres=cen, radii=np.full(count, radius))
+
+
+def big_3d(storage="f16"):
+    return channel_3d(storage=storage, shape=(512, 256, 256), count=1024, radius=8.0)
+
+
+def dense_3d(storage="f32", count=2000, radius=8.0):
+    shape = (384, 384, 192)
+    cen = fcc_slab_centres(shape, radius, count)
+    return dict(lattice="D3Q27", storage=storage, nc="explicit", shape=shape, walls=(0, 0, 1),
+                tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(1e-6, 0.0, 0.0),
+                nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0,
+                centres=cen, radii=np.full(len(cen), radius))
+
+
+def sim_kwargs(w):
+    """Split a workload dict into Simulation kwargs and the droplet list."""
+    kw = {k: v for k, v in w.items() if k not in ("centres", "radii")}
+    return kw, w["centres"], w["radii"]

@@ -1,0 +1,99 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every symbol the header declares, its velocity tables agree with the
+oracle's, and argument validation rejects bad parameters before touching a
+device.  No compute call is made."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2405_14551_amd import lb
+from oracle.lattice import make_lattice, LATTICES
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+pytestmark = pytest.mark.skipif(not os.path.exists(lb.LIB_PATH), reason="library not built")
+
+
+def _declared_symbols():
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lb.lib()
+    declared = _declared_symbols()
+    assert {"lb_create", "lb_init_droplets", "lb_step", "lb_fields", "lb_destroy"} <= declared
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} declared in include/ but not exported"
+    assert set(lb.EXPORTED) <= declared
+
+
+@pytest.mark.parametrize("name", LATTICES)
+def test_tables_agree_with_oracle(name):
+    c, w, opp, B = lb.lattice_table(name)
+    ref = make_lattice(name)
+    assert np.array_equal(c, ref.c)
+    assert np.array_equal(opp, ref.opp)
+    np.testing.assert_array_equal(w, ref.w)
+    np.testing.assert_allclose(B, ref.B, rtol=0, atol=2e-16)
+
+
+def _create(**kw):
+    p = lb.make_params(**kw)
+    h = ctypes.c_void_p()
+    rc = lb.lib().lb_create(ctypes.byref(p), 1, None, ctypes.byref(h))
+    if rc == 0:
+        lb.lib().lb_destroy(h)
+    return rc
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tau=0.5),
+    dict(tau=0.3),
+    dict(shape=(0, 4, 4)),
+    dict(lattice="D2Q9", shape=(8, 8, 2)),
+    dict(lattice="D2Q9", shape=(8, 8, 1), walls=(0, 0, 1)),
+    dict(lattice="D2Q9", shape=(8, 8, 1), body_force=(0, 0, 1e-5)),
+    dict(phi_interface=1.0),
+    dict(nc="explicit", nc_hmax=5.0),
+    dict(nc="explicit", nc_hmin=0.0),
+    dict(rho0=-1.0),
+    dict(shape=(2048, 2048, 2048)),
+])
+def test_invalid_params_rejected(kw):
+    assert _create(**kw) == lb.LB_EINVAL
+
+
+def test_bad_enum_and_null():
+    L = lb.lib()
+    p = lb.make_params()
+    p.lattice = 7
+    h = ctypes.c_void_p()
+    assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
+    p = lb.make_params()
+    p.storage = 9
+    assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
+    p = lb.make_params()
+    p.wall[0] = 2
+    assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
+    p = lb.make_params()
+    assert L.lb_create(ctypes.byref(p), 2, None, ctypes.byref(h)) == lb.LB_EINVAL
+    assert L.lb_create(None, 1, None, ctypes.byref(h)) == lb.LB_EINVAL
+    assert L.lb_destroy(None) == lb.LB_OK
+    assert L.lb_step(None, 1) == lb.LB_EINVAL
+    assert L.lb_error_string(lb.LB_ENUMERIC).decode().startswith("numerical watchdog")
+
+
+def test_valid_params_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    assert _create() == lb.LB_ENODEV

@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Bars: FP64 storage/arithmetic within 1e-12 relative (per field
+||a - b||_inf / ||b||_inf); FP32 within 1e-5 relative for densities and
+velocity after 100 steps (velocity against max |u|); interface flags and
+droplet labels bit-exact when both sides take the decision on the same
+phase field in the kernel's precision."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_14551_amd import lb, workloads as W  # noqa: E402
+from oracle.sim import OracleSim, OracleParams, flags_from_phi, step_window, surface_tension  # noqa: E402
+from oracle.ccl import label as oracle_label  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oparams(kw, decision=np.float64):
+    nx, ny, nz = kw["shape"]
+    return OracleParams(lattice=kw["lattice"], nx=nx, ny=ny, nz=nz,
+                        walls=tuple(bool(v) for v in kw.get("walls", (0, 0, 0))),
+                        tau=kw.get("tau", 1.0), A=kw.get("A", 0.01), beta=kw.get("beta", 0.7),
+                        rho0=kw.get("rho0", 1.0), body_force=tuple(kw.get("body_force", (0, 0, 0))),
+                        u0=tuple(kw.get("u0", (0, 0, 0))), nc=kw.get("nc", "off") == "explicit",
+                        nc_A=kw.get("nc_A", 0.02), nc_hmin=kw.get("nc_hmin", 2.0),
+                        nc_hmax=kw.get("nc_hmax", 3.0), phi_interface=kw.get("phi_interface", 0.9),
+                        decision_dtype=decision)
+
+
+def gpu_state(sim):
+    s = sim.get_state().double().cpu().numpy()
+    return s[0], s[1]
+
+
+def gpu_fields(sim, names=("rho_a", "rho_b", "phi", "u", "f_nc", "flags")):
+    return {k: v.cpu().numpy() for k, v in sim.fields(names).items()}
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def run_pair(kw, centres, radii, steps, decision=np.float64):
+    say(f"case {kw['lattice']} {kw['storage']} shape={kw['shape']} walls={kw.get('walls')} "
+        f"nc={kw.get('nc')} steps={steps}")
+    sim = lb.Simulation(**kw)
+    sim.init_droplets(centres, radii)
+    orc = OracleSim(oparams(kw, decision)).init_droplets(centres, radii)
+    if steps:
+        sim.step(steps)
+        orc.step(steps)
+    return sim, orc
+
+
+# ----------------------------------------------------------------------- init
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_init_matches_oracle(storage):
+    kw = dict(lattice="D3Q27", storage=storage, nc="explicit", shape=(37, 20, 13), walls=(0, 1, 1),
+              u0=(0.01, -0.02, 0.005))
+    cen = np.array([[10.0, 9.5, 6.0], [25.2, 10.0, 6.5]])
+    sim, orc = run_pair(kw, cen, [5.0, 4.0], 0)
+    g = gpu_fields(sim)
+    o = orc.fields()
+    tol = 1e-15 if storage == "f64" else 1e-7
+    for k in ("rho_a", "rho_b", "phi", "u"):
+        assert rel(g[k], o[k]) < tol, k
+    fA, fB = gpu_state(sim)
+    assert rel(fA, orc.fA) < tol and rel(fB, orc.fB) < tol
+    assert np.array_equal(g["flags"].astype(bool),
+                          flags_from_phi(g["phi"], 0.9, np.float64 if storage == "f64" else np.float32))
+    sim.close()
+
+
+# ----------------------------------------------------------------- FP64 parity
+FP64_CASES = [
+    ("D2Q9", (70, 37, 1), (0, 1, 0), "explicit", 300),
+    ("D2Q9", (128, 64, 1), (0, 0, 0), "off", 200),
+    ("D3Q19", (67, 21, 14), (0, 1, 1), "explicit", 60),
+    ("D3Q27", (70, 20, 13), (0, 1, 1), "explicit", 60),
+    ("D3Q27", (64, 8, 24), (1, 0, 0), "off", 40),
+]
+
+
+@pytest.mark.parametrize("lat,shape,walls,nc,steps", FP64_CASES)
+def test_fp64_parity_steps(lat, shape, walls, nc, steps):
+    d3 = lat != "D2Q9"
+    nx, ny, nz = shape
+    cen = np.array([[nx * 0.3, ny * 0.5, nz * 0.5 if d3 else 0.0],
+                    [nx * 0.3 + 13.5, ny * 0.5, nz * 0.5 if d3 else 0.0]])
+    R = min(6.0, ny * 0.3, (nz * 0.3 if d3 else 99))
+    kw = dict(lattice=lat, storage="f64", nc=nc, shape=shape, walls=walls, tau=0.9, A=0.02,
+              body_force=(2e-5, 0, 0), nc_A=0.03)
+    sim, orc = run_pair(kw, cen, [R, R], steps)
+    fA, fB = gpu_state(sim)
+    ea, eb = rel(fA, orc.fA), rel(fB, orc.fB)
+    g = gpu_fields(sim)
+    o = orc.fields()
+    say(f"  state rel err A {ea:.2e} B {eb:.2e}; nc sites {(np.abs(o['f_nc']).sum(0) > 0).sum()}")
+    assert ea < 1e-12 and eb < 1e-12
+    for k in ("rho_a", "rho_b", "phi"):
+        assert rel(g[k], o[k]) < 1e-12, k
+    umax = np.abs(o["u"]).max()
+    assert np.abs(g["u"] - o["u"]).max() / umax < 1e-12
+    assert np.abs(g["f_nc"] - o["f_nc"]).max() <= 1e-12 * max(np.abs(o["f_nc"]).max(), 1e-30)
+    assert np.array_equal(g["flags"].astype(bool), o["flags"])
+    if nc == "explicit":
+        assert np.abs(o["f_nc"]).max() > 0, "near-contact force never fired"
+    sim.close()
+
+
+@pytest.mark.parametrize("lat,shape,walls", [("D2Q9", (67, 9, 1), (1, 1, 0)),
+                                              ("D3Q19", (66, 6, 5), (0, 1, 0)),
+                                              ("D3Q27", (65, 7, 6), (1, 0, 1))])
+def test_fp64_random_state_one_step(lat, shape, walls):
+    """Random populations exercise every branch (many interface sites, scan
+    hits at all distances, bounce-back at every face)."""
+    rng = np.random.default_rng(21)
+    nx, ny, nz = shape
+    kw = dict(lattice=lat, storage="f64", nc="explicit", shape=shape, walls=walls, tau=0.8, A=0.05,
+              body_force=(1e-3, -2e-3, 5e-4 if nz > 1 else 0.0), nc_A=0.05, phi_interface=0.95)
+    say(f"case random {lat} {shape} {walls}")
+    sim = lb.Simulation(**kw)
+    orc = OracleSim(oparams(kw))
+    q = orc.lat.q
+    w = orc.w.reshape(q, 1, 1, 1)
+    fA = w * rng.uniform(0.0, 1.0, (q,) + orc.shape)
+    fB = w * rng.uniform(0.0, 1.0, (q,) + orc.shape)
+    sim.set_state(torch.from_numpy(np.stack([fA, fB])))
+    orc.set_state(fA, fB)
+    sim.step(1)
+    orc.step(1)
+    gA, gB = gpu_state(sim)
+    assert rel(gA, orc.fA) < 1e-13 and rel(gB, orc.fB) < 1e-13
+    g = gpu_fields(sim)
+    o = orc.fields()
+    assert np.abs(o["f_nc"]).max() > 0
+    assert np.abs(g["f_nc"] - o["f_nc"]).max() < 1e-15
+    assert np.array_equal(g["flags"].astype(bool), o["flags"])
+    sim.close()
+
+
+def test_laplace_case_fp64_1000_steps():
+    """128x64 D2Q9 droplet R=16, 1000 FP64 steps: parity with the oracle and the
+    Laplace law (within 10% of sigma/R, sigma = (4/9) A tau)."""
+    w = W.laplace_2d()
+    kw, cen, rad = W.sim_kwargs(w)
+    sim, orc = run_pair(kw, cen, rad, 1000)
+    fA, fB = gpu_state(sim)
+    say(f"  rel err {rel(fA, orc.fA):.2e} {rel(fB, orc.fB):.2e}")
+    assert rel(fA, orc.fA) < 1e-12 and rel(fB, orc.fB) < 1e-12
+    dg = sim.diagnostics()
+    do = orc.diagnostics()
+    say(f"  gpu diag {dg}\n  orc diag {do}")
+    assert abs(dg[7] - do[7]) < 1e-12 * abs(do[7]) + 1e-15
+    assert abs(dg[7] / (surface_tension(0.01, 1.0) / 16.0) - 1) < 0.10
+    assert dg[6] == do[6] == 1
+    for k in range(5):
+        assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[0]), 1.0)
+    sim.close()
+
+
+# ----------------------------------------------------------------- FP32 parity
+def test_fp32_parity_100_steps():
+    """Periodic D3Q27 box, two droplets, uniform u0 = 0.02, body force, near
+    contact on: densities and velocity within 1e-5 relative after 100 steps."""
+    shape = (40, 32, 32)
+    kw = dict(lattice="D3Q27", storage="f32", nc="explicit", shape=shape, walls=(0, 0, 0),
+              u0=(0.02, 0.0, 0.0), body_force=(1e-6, 0.0, 0.0))
+    cen = np.array([[11.0, 16.0, 16.0], [29.5, 16.0, 16.0]])
+    sim, orc = run_pair(kw, cen, [7.5, 7.5], 100, decision=np.float32)
+    g = gpu_fields(sim)
+    o = orc.fields()
+    umax = np.abs(o["u"]).max()
+    errs = {k: rel(g[k], o[k]) for k in ("rho_a", "rho_b")}
+    errs["u"] = np.abs(g["u"] - o["u"]).max() / umax
+    say(f"  fp32 errors {errs}, umax {umax:.3e}, nc sites {(np.abs(o['f_nc']).sum(0) > 0).sum()}")
+    for k, e in errs.items():
+        assert e < 1e-5, (k, e)
+    sim.close()
+
+
+def test_flags_and_labels_bit_exact():
+    w = W.channel_3d(shape=(96, 48, 40), count=12, radius=7.0)
+    kw, cen, rad = W.sim_kwargs(w)
+    say(f"case labels {kw['shape']}")
+    sim = lb.Simulation(**kw)
+    sim.init_droplets(cen, rad)
+    sim.step(25)
+    g = gpu_fields(sim, ("phi", "flags", "labels"))
+    assert np.array_equal(g["flags"].astype(bool), flags_from_phi(g["phi"], 0.9, np.float32))
+    lab, count = oracle_label(g["phi"] > 0, periodic=(True, False, False))
+    assert np.array_equal(g["labels"].astype(np.int64), lab)
+    d = sim.diagnostics()
+    assert d[6] == count == 12
+    sim.close()
+
+
+# --------------------------------------------------------- full-size sampled
+def test_channel_full_size_sampled_sites():
+    """256x128x128 D3Q27 FP32 channel, 64 droplets, in the benchmark's launch
+    configuration: after 30 steps take the state, step once, and compare sampled
+    sites (interface sites with near-contact force, walls, edges and corners,
+    tile seams, bulk) against the oracle's windowed step on the same input."""
+    w = W.channel_3d()
+    kw, cen, rad = W.sim_kwargs(w)
+    say("case channel full size")
+    sim = lb.Simulation(**kw)
+    sim.init_droplets(cen, rad)
+    sim.step(30)
+    sA, sB = [a.float().cpu().numpy() for a in sim.get_state()]
+    sim.step(1)
+    g = gpu_fields(sim, ("f_nc", "flags", "rho_a"))
+    nA, nB = [a.float().cpu().numpy() for a in sim.get_state()]
+    nx, ny, nz = kw["shape"]
+    rng = np.random.default_rng(5)
+    sites = []
+    fnc_sites = np.argwhere(np.abs(g["f_nc"]).sum(0) > 0)
+    assert len(fnc_sites) > 0, "no near-contact force in the channel"
+    for arr, k in ((fnc_sites, 24), (np.argwhere(g["flags"] > 0), 12)):
+        for j in rng.choice(len(arr), size=min(k, len(arr)), replace=False):
+            z, y, x = arr[j]
+            sites.append((x, y, z))
+    sites += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (5, 0, 64), (100, ny - 1, 3), (63, 3, 7), (64, 4, 8),
+              (127, 64, nz - 1), (200, 1, 1)]
+    for _ in range(16):
+        sites.append((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    p = oparams(kw, np.float32)
+    worst = 0.0
+    for (x, y, z) in sites:
+        a, b, fl = step_window(p, sA, sB, (x, y, z))
+        e = max(np.abs(nA[:, z, y, x] - a).max(), np.abs(nB[:, z, y, x] - b).max()) / np.abs(a + b).max()
+        worst = max(worst, e)
+        assert e < 2e-6, ((x, y, z), e)
+    say(f"  sampled {len(sites)} sites, worst rel err {worst:.2e}")
+    sim.close()
+
+
+# ------------------------------------------------------------- ABI behaviour
+def test_determinism_and_checkpoint_roundtrip():
+    w = W.channel_3d(shape=(64, 40, 32), count=6, radius=6.0)
+    kw, cen, rad = W.sim_kwargs(w)
+    say("case determinism")
+    s1 = lb.Simulation(**kw).init_droplets(cen, rad)
+    s1.step(20)
+    mid = s1.get_state().clone()
+    s1.step(20)
+    end1 = s1.get_state()
+    s2 = lb.Simulation(**kw).init_droplets(cen, rad)
+    s2.step(40)
+    assert torch.equal(end1, s2.get_state())
+    s3 = lb.Simulation(**kw)
+    s3.set_state(mid)
+    s3.step(20)
+    assert torch.equal(end1, s3.get_state())
+    for s in (s1, s2, s3):
+        s.close()
+
+
+def test_watchdog_reports_nan():
+    kw = dict(lattice="D3Q19", storage="f32", shape=(64, 8, 8), diag_every=1)
+    say("case watchdog")
+    sim = lb.Simulation(**kw).init_droplets(np.zeros((0, 3)), [])
+    st = sim.get_state()
+    st[0, 3, 4, 4, 10] = float("nan")
+    sim.set_state(st)
+    with pytest.raises(lb.LBError) as ei:
+        sim.step(3)
+    assert ei.value.code == lb.LB_ENUMERIC
+    sim.close()
+
+
+def test_mass_conservation_gpu():
+    w = W.channel_3d(shape=(64, 48, 48), count=8, radius=7.0)
+    kw, cen, rad = W.sim_kwargs(w)
+    say("case mass f64/f32")
+    for st, tol in (("f64", 1e-13), ("f32", 2e-6)):
+        kw["storage"] = st
+        sim = lb.Simulation(**kw).init_droplets(cen, rad)
+        d0 = sim.diagnostics()
+        sim.step(200)
+        d1 = sim.diagnostics()
+        say(f"  {st}: dA {abs(d1[0] - d0[0]) / d0[0]:.2e} dB {abs(d1[1] - d0[1]) / d0[1]:.2e}")
+        assert abs(d1[0] - d0[0]) / d0[0] < tol
+        assert abs(d1[1] - d0[1]) / d0[1] < tol
+        sim.close()
