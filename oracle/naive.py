@@ -123,7 +123,7 @@ class NaiveSim:
             gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2]
             # near-contact scan
             fnc = [0.0, 0.0, 0.0]
-            if p.nc and flag[s] and gg > 0:
+            if p.nc and flag[s] and gg > p.g_eps ** 2:
                 gn = math.sqrt(gg)
                 m = [-g[a] / gn for a in range(3)]
                 for step in range(1, int(math.floor(p.nc_hmax)) + 1):
@@ -157,7 +157,7 @@ class NaiveSim:
                 val = f[i] - (f[i] - feq) / p.tau + src
                 cnorm = math.sqrt(ci[0] ** 2 + ci[1] ** 2 + ci[2] ** 2)
                 cos = 0.0
-                if gg > 0:
+                if gg > p.g_eps ** 2:
                     val += p.A * gn * (self.w[i] * cg * cg / gg - self.B[i])
                     if cnorm > 0:
                         cos = cg / (cnorm * gn)

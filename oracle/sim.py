@@ -62,6 +62,11 @@ class OracleParams:
     nc_hmin: float = 2.0
     nc_hmax: float = 3.0
     phi_interface: float = 0.9
+    # |g| at or below g_eps counts as no gradient: the normal, cos(theta_i),
+    # the perturbation and the near-contact scan are then skipped.  A phase
+    # gradient of 1e-12 is rounding noise at symmetric points (a droplet
+    # centre on a site), where the direction of g would otherwise be random.
+    g_eps: float = 1e-12
     # precision in which integer-valued decisions (flag threshold, rounding of
     # scan offsets, sign tests) are taken; float32 when comparing a float32 run
     decision_dtype: type = np.float64
@@ -219,7 +224,7 @@ class OracleSim:
         """Explicit near-contact repulsion, F_rep = -A_h[h] n delta_I (Eq.
         near_cont_force) with delta_I = |g|/2 and the sign chosen repulsive.
 
-        For an interface site x (flag set, |g|^2 > 0): m = -g/|g| points out of
+        For an interface site x (flag set, |g| > g_eps): m = -g/|g| points out of
         the phi = +1 region.  For s = 1 .. floor(h_max): y = x + round(s m)
         (halves away from zero).  A solid y ends the scan with no force;
         periodic axes wrap.  The first y that is an interface site whose
@@ -231,7 +236,7 @@ class OracleSim:
             return F
         dt = p.decision_dtype
         gg = (g * g).sum(0)
-        cand = flags & (gg > 0)
+        cand = flags & (gg > p.g_eps ** 2)
         iz, iy, ix = np.nonzero(cand)
         if iz.size == 0:
             return F
@@ -307,7 +312,7 @@ class OracleSim:
         gg = (g * g).sum(0)
         gn = np.sqrt(gg)
         cg = np.einsum("ia,a...->i...", self.c, g)
-        has = gg > 0
+        has = gg > p.g_eps ** 2
         safe_gg = np.where(has, gg, 1.0)
         pert = np.where(has, p.A * gn * (wq * cg * cg / safe_gg - Bq), 0.0)
         fstar = fpost + pert

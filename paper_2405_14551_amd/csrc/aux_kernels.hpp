@@ -55,8 +55,9 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ f, typename Storag
     constexpr int I = decltype(ic)::value;
     const double cu = L::cx[I] * a.u0x + L::cy[I] * a.u0y + L::cz[I] * a.u0z;
     const double shape = L::w[I] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-    Storage<S>::template store<I, L>(f + (size_t)I * a.N + s, (R)(rho_k[0] * shape), hs);
-    Storage<S>::template store<I, L>(f + a.QN + (size_t)I * a.N + s, (R)(rho_k[1] * shape), hs);
+    const double hw = L::w[I] * a.half_rho0;  // kernels keep f^k_i - w_i rho0 / 2
+    Storage<S>::template store<I, L>(f + (size_t)I * a.N + s, (R)(rho_k[0] * shape - hw), hs);
+    Storage<S>::template store<I, L>(f + a.QN + (size_t)I * a.N + s, (R)(rho_k[1] * shape - hw), hs);
   });
   phi_out[s] = (R)phi;
   R* rA = (R*)fo.rho_a;

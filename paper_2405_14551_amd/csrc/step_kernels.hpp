@@ -40,9 +40,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // ----------------------------------------------------------------------------
-// storage policies: how a population is kept in HBM and turned into the
-// arithmetic type.  The 16-bit policies store the shifted value
-// f^k_i - w_i rho0 / 2 rounded to nearest even and add the shift on load.
+// storage policies.  The kernels work on shifted populations
+//   d^k_i = f^k_i - w_i rho0 / 2,
+// i.e. each colour minus its share of the rest equilibrium, so that sums and
+// BGK differences are formed from small numbers (the shifted-population
+// idea of the paper's mixed-precision section, applied to the arithmetic).
+// FP64/FP32 keep f^k_i in memory and shift on load/store; the 16-bit types
+// keep d^k_i itself, rounded to nearest even.
 template <class S>
 struct Storage;
 
@@ -50,44 +54,40 @@ template <>
 struct Storage<double> {
   using real = double;
   template <int I, class L>
-  __device__ static __forceinline__ double load(const double* p, double) { return *p; }
+  __device__ static __forceinline__ double load(const double* p, double h) { return *p - L::w[I] * h; }
   template <int I, class L>
-  __device__ static __forceinline__ void store(double* p, double v, double) { __builtin_nontemporal_store(v, p); }
+  __device__ static __forceinline__ void store(double* p, double d, double h) {
+    __builtin_nontemporal_store(d + L::w[I] * h, p);
+  }
 };
 
 template <>
 struct Storage<float> {
   using real = float;
   template <int I, class L>
-  __device__ static __forceinline__ float load(const float* p, float) { return *p; }
+  __device__ static __forceinline__ float load(const float* p, float h) { return *p - (float)L::w[I] * h; }
   template <int I, class L>
-  __device__ static __forceinline__ void store(float* p, float v, float) { __builtin_nontemporal_store(v, p); }
+  __device__ static __forceinline__ void store(float* p, float d, float h) {
+    __builtin_nontemporal_store(d + (float)L::w[I] * h, p);
+  }
 };
 
 template <>
 struct Storage<_Float16> {
   using real = float;
   template <int I, class L>
-  __device__ static __forceinline__ float load(const _Float16* p, float half_rho0) {
-    return (float)(*p) + (float)L::w[I] * half_rho0;
-  }
+  __device__ static __forceinline__ float load(const _Float16* p, float) { return (float)(*p); }
   template <int I, class L>
-  __device__ static __forceinline__ void store(_Float16* p, float v, float half_rho0) {
-    *p = (_Float16)(v - (float)L::w[I] * half_rho0);
-  }
+  __device__ static __forceinline__ void store(_Float16* p, float d, float) { *p = (_Float16)d; }
 };
 
 template <>
 struct Storage<__bf16> {
   using real = float;
   template <int I, class L>
-  __device__ static __forceinline__ float load(const __bf16* p, float half_rho0) {
-    return (float)(*p) + (float)L::w[I] * half_rho0;
-  }
+  __device__ static __forceinline__ float load(const __bf16* p, float) { return (float)(*p); }
   template <int I, class L>
-  __device__ static __forceinline__ void store(__bf16* p, float v, float half_rho0) {
-    *p = (__bf16)(v - (float)L::w[I] * half_rho0);
-  }
+  __device__ static __forceinline__ void store(__bf16* p, float d, float) { *p = (__bf16)d; }
 };
 
 // ----------------------------------------------------------------------------
@@ -101,7 +101,7 @@ struct StepArgs {
   double guo;        // 1 - 1/(2 tau)
   double A;          // perturbation amplitude
   double beta;       // recolouring
-  double half_rho0;  // storage shift per colour is w_i * rho0 / 2
+  double half_rho0;  // shift per colour is w_i * rho0 / 2
   double fx, fy, fz; // body force density
   double nc_A, nc_hmin;
   int nc_steps;      // floor(nc_hmax)
@@ -168,14 +168,14 @@ __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
   if (x >= a.nx || y >= a.ny) return;
   const Nbr n = make_nbr(x, y, z, a);
   const R h = (R)a.half_rho0;
-  R ra = 0, rb = 0;
+  R sa = 0, sb = 0;  // sums of the shifted populations: rho_k = rho0/2 + s_k
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const uint32_t e = pull_index<L, I>(n, a.N);
-    ra += Storage<S>::template load<I, L>(fin + e, h);
-    rb += Storage<S>::template load<I, L>(fin + a.QN + e, h);
+    sa += Storage<S>::template load<I, L>(fin + e, h);
+    sb += Storage<S>::template load<I, L>(fin + a.QN + e, h);
   });
-  phi[n.site] = (ra - rb) / (ra + rb);
+  phi[n.site] = (sa - sb) / (R(2) * h + (sa + sb));
 }
 
 // ----------------------------------------------------------------------------
@@ -290,8 +290,10 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
       const R gg = gx * gx + gy * gy + gz * gz;
       // ---- near-contact force (explicit scan, interface sites only)
       R fnx = 0, fny = 0, fnz = 0;
+      // |g| <= 1e-12 counts as no gradient (rounding noise at symmetric points)
+      const bool has_g = gg > R(1e-24);
       if constexpr (NC) {
-        if (flag && gg > R(0)) {
+        if (flag && has_g) {
           const R inv = R(1) / sqrt(gg);
           const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
           int hit = 0;
@@ -322,26 +324,29 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
           }
         }
       }
-      // ---- pull the populations
+      // ---- pull the populations (shifted by w_i rho0/2 per colour)
       const Nbr n = make_nbr(x, y, z, a);
-      R f[L::Q];
-      R ra = 0, rb = 0;
+      R d[L::Q];  // d_i = f_i - w_i rho0, total over both colours
+      R sa = 0, sb = 0;
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         const uint32_t e = pull_index<L, I>(n, a.N);
         const R va = Storage<S>::template load<I, L>(fin + e, hshift);
         const R vb = Storage<S>::template load<I, L>(fin + a.QN + e, hshift);
-        ra += va; rb += vb;
-        f[I] = va + vb;
+        sa += va; sb += vb;
+        d[I] = va + vb;
       });
-      R jx = 0, jy = 0, jz = 0;
+      R jx = 0, jy = 0, jz = 0, drho = 0;
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        if constexpr (L::cx[I] != 0) jx += (R)L::cx[I] * f[I];
-        if constexpr (L::cy[I] != 0) jy += (R)L::cy[I] * f[I];
-        if constexpr (L::cz[I] != 0) jz += (R)L::cz[I] * f[I];
+        drho += d[I];
+        if constexpr (L::cx[I] != 0) jx += (R)L::cx[I] * d[I];
+        if constexpr (L::cy[I] != 0) jy += (R)L::cy[I] * d[I];
+        if constexpr (L::cz[I] != 0) jz += (R)L::cz[I] * d[I];
       });
-      const R rho = ra + rb;
+      const R rho0 = R(2) * hshift;
+      const R ra = hshift + sa, rb = hshift + sb;
+      const R rho = rho0 + drho;
       const R inv_rho = R(1) / rho;
       const R Fx = (R)a.fx + fnx, Fy = (R)a.fy + fny, Fz = (R)a.fz + fnz;
       const R ux = (jx + R(0.5) * Fx) * inv_rho;
@@ -349,14 +354,13 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
       const R uz = (jz + R(0.5) * Fz) * inv_rho;
       const R uu = ux * ux + uy * uy + uz * uz;
       const R uF = ux * Fx + uy * Fy + uz * Fz;
-      const bool has_g = gg > R(0);
       const R gn = has_g ? sqrt(gg) : R(0);
       const R inv_gg = has_g ? R(1) / gg : R(0);
       const R inv_gn = has_g ? R(1) / gn : R(0);
       const R Agn = has_g ? Aamp * gn : R(0);
       const R fa_frac = ra * inv_rho;                  // rho_A / rho
       const R coef = beta * ra * rb * inv_rho;         // beta rho_A rho_B / rho
-      const R base_eq = R(1) - R(1.5) * uu;
+      const R half_phi_rho0 = (sa - sb) * inv_rho * hshift;  // rho0 phi / 2
       // ---- collide each direction and store the two colours
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
@@ -366,16 +370,18 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
         if constexpr (cx != 0) { cu += (R)cx * ux; cF += (R)cx * Fx; cg += (R)cx * gx; }
         if constexpr (cy != 0) { cu += (R)cy * uy; cF += (R)cy * Fy; cg += (R)cy * gy; }
         if constexpr (cz != 0) { cu += (R)cz * uz; cF += (R)cz * Fz; cg += (R)cz * gz; }
-        const R feq = wi * rho * (base_eq + R(3) * cu + R(4.5) * cu * cu);
+        // f^eq - w rho0 = w [(rho - rho0) + rho (3 cu + 4.5 cu^2 - 1.5 uu)]
+        const R deq = wi * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
         const R src = guo * wi * (R(3) * (cF - uF) + R(9) * cu * cF);
-        R fs = f[I] - omega * (f[I] - feq) + src;
-        fs += Agn * (wi * cg * cg * inv_gg - (R)B_coef<L>(I));
+        R ds = d[I] - omega * (d[I] - deq) + src;                        // f* - w rho0
+        ds += Agn * (wi * cg * cg * inv_gg - (R)B_coef<L>(I));
         R rec = 0;
         if constexpr (I != 0) rec = coef * wi * (cg * (R)inv_norm<L>(I) * inv_gn);
-        const R fa = fa_frac * fs + rec;
-        const R fb = fs - fa;
-        Storage<S>::template store<I, L>(fout + (size_t)I * a.N + n.site, fa, hshift);
-        Storage<S>::template store<I, L>(fout + a.QN + (size_t)I * a.N + n.site, fb, hshift);
+        // recolouring in shifted form: f^A - w rho0/2 = (rho_A/rho) (f* - w rho0) + w rho0 phi/2 + rec
+        const R da = fa_frac * ds + wi * half_phi_rho0 + rec;
+        const R db = ds - da;
+        Storage<S>::template store<I, L>(fout + (size_t)I * a.N + n.site, da, hshift);
+        Storage<S>::template store<I, L>(fout + a.QN + (size_t)I * a.N + n.site, db, hshift);
       });
       if constexpr (FIELDS) {
         R* rA = (R*)fo.rho_a;

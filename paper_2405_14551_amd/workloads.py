@@ -8,7 +8,9 @@ periodic axes).  Both the oracle-based tests and the GPU path receive the
 same explicit centre list.
 
 Workloads (sizes as in the benchmark definitions):
-  laplace_2d    D2Q9 128x64 periodic, FP64, one droplet R=16 at the centre
+  laplace_2d    D2Q9 128x64 periodic, FP64, one droplet R=16 at the box centre
+                ((nx-1)/2, (ny-1)/2) = (63.5, 31.5), so that no site is a point
+                of exact symmetry (see the note on symmetric points below)
   channel_3d    D3Q27 256x128x128, walls y/z, body force 1e-6 x, 64 droplets R=10,
                 near-contact range 3 / strength 0.02, FP32
   big_3d        same physics on 512x256x256 with 1024 droplets R=8
@@ -19,6 +21,14 @@ from __future__ import annotations
 import numpy as np
 
 SEED = 14551
+
+# Symmetric points: where the phase gradient vanishes by symmetry and a site
+# sits exactly there (a droplet centre on a site, the midpoint between
+# periodic images), the computed gradient is rounding noise, its direction is
+# random, and the recolouring amplifies that noise by a factor of about 3 per
+# step.  Two correct implementations then drift apart at those sites (by
+# amounts far below any physical scale).  Centres used for parity checks are
+# therefore placed off such points.
 
 
 def rsa_centres(shape, walls, radius, count, seed=SEED, min_gap=3.0, max_tries=200000, dims=3):
@@ -88,7 +98,7 @@ def fcc_slab_centres(shape, radius, count, gap=2.0, jitter=0.5, seed=SEED):
 def laplace_2d():
     return dict(lattice="D2Q9", storage="f64", nc="off", shape=(128, 64, 1), walls=(0, 0, 0),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0,
-                centres=np.array([[64.0, 32.0, 0.0]]), radii=np.array([16.0]))
+                centres=np.array([[63.5, 31.5, 0.0]]), radii=np.array([16.0]))
 
 
 def channel_3d(storage="f32", shape=(256, 128, 128), count=64, radius=10.0, seed=SEED):

@@ -73,7 +73,7 @@ def run_pair(kw, centres, radii, steps, decision=np.float64):
 def test_init_matches_oracle(storage):
     kw = dict(lattice="D3Q27", storage=storage, nc="explicit", shape=(37, 20, 13), walls=(0, 1, 1),
               u0=(0.01, -0.02, 0.005))
-    cen = np.array([[10.0, 9.5, 6.0], [25.2, 10.0, 6.5]])
+    cen = np.array([[10.1, 9.5, 6.2], [25.2, 10.3, 6.5]])
     sim, orc = run_pair(kw, cen, [5.0, 4.0], 0)
     g = gpu_fields(sim)
     o = orc.fields()
@@ -101,9 +101,11 @@ FP64_CASES = [
 def test_fp64_parity_steps(lat, shape, walls, nc, steps):
     d3 = lat != "D2Q9"
     nx, ny, nz = shape
-    cen = np.array([[nx * 0.3, ny * 0.5, nz * 0.5 if d3 else 0.0],
-                    [nx * 0.3 + 13.5, ny * 0.5, nz * 0.5 if d3 else 0.0]])
+    # off-site centres (no site is a point of exact symmetry); surfaces 3 sites
+    # apart so that the near-contact force stays active
     R = min(6.0, ny * 0.3, (nz * 0.3 if d3 else 99))
+    cen = np.array([[nx * 0.3 + 0.17, ny * 0.5 - 0.23, nz * 0.5 + 0.31 if d3 else 0.0],
+                    [nx * 0.3 + 2 * R + 3.17, ny * 0.5 + 0.11, nz * 0.5 - 0.13 if d3 else 0.0]])
     kw = dict(lattice=lat, storage="f64", nc=nc, shape=shape, walls=walls, tau=0.9, A=0.02,
               body_force=(2e-5, 0, 0), nc_A=0.03)
     sim, orc = run_pair(kw, cen, [R, R], steps)
@@ -182,7 +184,7 @@ def test_fp32_parity_100_steps():
     shape = (40, 32, 32)
     kw = dict(lattice="D3Q27", storage="f32", nc="explicit", shape=shape, walls=(0, 0, 0),
               u0=(0.02, 0.0, 0.0), body_force=(1e-6, 0.0, 0.0))
-    cen = np.array([[11.0, 16.0, 16.0], [29.5, 16.0, 16.0]])
+    cen = np.array([[11.13, 15.77, 16.21], [29.61, 16.19, 15.83]])
     sim, orc = run_pair(kw, cen, [7.5, 7.5], 100, decision=np.float32)
     g = gpu_fields(sim)
     o = orc.fields()
