@@ -91,6 +91,23 @@ def cpu_baseline(seconds_target=10.0):
                       f"(host nproc {os.cpu_count()})"}
 
 
+def copy_calibration(nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy of known size: rocprofv3 FETCH_SIZE /
+    WRITE_SIZE of these launches give the counter scale (ideal: nbytes each)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes_each_way": nbytes, "reps": reps,
+                      "GBps_read_plus_write": 2 * nbytes * reps / dt / 1e9}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,7 +116,11 @@ def main():
     ap.add_argument("--workload", default="channel_3d", choices=["channel_3d", "big_3d", "dense_3d"])
     ap.add_argument("--storage", default=None, help="f32 (default), f16, bf16, f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU slab "
                                    "decomposition is not part of this build", "n_gpus": args.gpus}))
