@@ -12,9 +12,15 @@ struct Launch {
   template <class S>
   static hipError_t phase_t(const void* fin, void* phi, const StepArgs& a, hipStream_t s) {
     using R = typename Storage<S>::real;
-    dim3 block(64, 4, 1);
-    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz);
-    k_phase<L, S><<<grid, block, 0, s>>>((const S*)fin, (R*)phi, a);
+    // one block spans up to 256 consecutive x-sites of a row, so the cache
+    // lines the +-1 pulls share between neighbouring waves stay in one CU
+    const int bx = a.nx >= 192 ? 256 : (a.nx >= 96 ? 128 : 64);
+    dim3 block(bx, 256 / bx, 1);
+    StepArgs b = a;
+    b.tiles_x = (a.nx + bx - 1) / bx;
+    b.tiles_y = (a.ny + block.y - 1) / block.y;
+    dim3 grid((unsigned)b.tiles_x * b.tiles_y * a.nz);
+    k_phase<L, S><<<grid, block, 0, s>>>((const S*)fin, (R*)phi, b);
     return hipGetLastError();
   }
 
@@ -35,8 +41,11 @@ struct Launch {
     using T = Tile<TILE_X, TILE_Y, RAD, L::D>;
     dim3 block(T::TX, T::TY, 1);
     const int zb = a.z_per_block;
-    dim3 grid((a.nx + T::TX - 1) / T::TX, (a.ny + T::TY - 1) / T::TY, (a.nz + zb - 1) / zb);
-    k_collide<L, S, T, NC, FIELDS><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, fo, a);
+    StepArgs b = a;
+    b.tiles_x = (a.nx + T::TX - 1) / T::TX;
+    b.tiles_y = (a.ny + T::TY - 1) / T::TY;
+    dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
+    k_collide<L, S, T, NC, FIELDS><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, fo, b);
     return hipGetLastError();
   }
 

@@ -107,7 +107,19 @@ struct StepArgs {
   int nc_steps;      // floor(nc_hmax)
   double phi_I;      // interface threshold
   int z_per_block;   // planes a pass-2 block marches through
+  int tiles_x, tiles_y;  // tile counts of the launch (x fastest)
 };
+
+// Workgroups are handed to the 8 XCDs round-robin in dispatch order.  Renumber
+// them so that each XCD receives one contiguous range of tiles: x-neighbour
+// tiles (whose +-1 pulls read the same cache lines) and the rows of a plane
+// then share one L2 instead of fetching the shared lines once per XCD.
+__device__ __forceinline__ uint32_t xcd_tile_index(uint32_t b, uint32_t nb) {
+  constexpr uint32_t NXCD = 8;
+  const uint32_t xcd = b % NXCD, k = b / NXCD;
+  const uint32_t per = nb / NXCD, rem = nb % NXCD;
+  return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
 
 struct FieldPtrs {
   void* rho_a;
@@ -162,9 +174,13 @@ __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
                                                typename Storage<S>::real* __restrict__ phi,
                                                StepArgs a) {
   using R = typename Storage<S>::real;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
+  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
+  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
+  const int z = t / txy;
+  const uint32_t r = t - z * txy;
+  const int ty_ = r / a.tiles_x, tx_ = r - ty_ * a.tiles_x;
+  const int x = tx_ * blockDim.x + threadIdx.x;
+  const int y = ty_ * blockDim.y + threadIdx.y;
   if (x >= a.nx || y >= a.ny) return;
   const Nbr n = make_nbr(x, y, z, a);
   const R h = (R)a.half_rho0;
@@ -184,10 +200,12 @@ template <int TX_, int TY_, int RAD_, int D_>
 struct Tile {
   static constexpr int TX = TX_, TY = TY_, RAD = RAD_;
   static constexpr int RZ = D_ == 3 ? RAD_ : 0;        // z halo
-  static constexpr int NPL = 2 * RZ + 1;               // planes in the ring
+  // planes in the ring: the 2 RZ + 1 in use plus one that is being filled
+  static constexpr int NPL = RZ ? 2 * RZ + 2 : 1;
   static constexpr int TXH = TX + 2 * RAD, TYH = TY + 2 * RAD;
   static constexpr int PL = TXH * TYH;                  // elements per plane
   static constexpr int NT = TX * TY;
+  static constexpr int NPER = (PL + NT - 1) / NT;      // plane elements per thread
 };
 
 // map a halo coordinate to the node whose phi it holds: periodic wrap, or the
@@ -220,6 +238,36 @@ __device__ __forceinline__ void load_plane(R* __restrict__ ring, int slot, int z
     dst[e] = phi[zoff + (size_t)gy * a.nx + gx];
   }
 }
+
+// the phase values of halo plane zz that thread `tid` stages (NPER of them)
+template <class T, class R>
+__device__ __forceinline__ void fetch_plane(R (&v)[T::NPER], int zz, const R* __restrict__ phi, int x0, int y0,
+                                            const StepArgs& a, int tid) {
+  const int gz = halo_coord(zz, a.nz, a.wall_z);
+  const size_t zoff = (size_t)gz * a.nx * a.ny;
+#pragma unroll
+  for (int k = 0; k < T::NPER; ++k) {
+    const int e = tid + k * T::NT;
+    if (e < T::PL) {
+      const int hy = e / T::TXH, hx = e - hy * T::TXH;
+      const int gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
+      const int gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
+      v[k] = phi[zoff + (size_t)gy * a.nx + gx];
+    }
+  }
+}
+
+template <class T, class R>
+__device__ __forceinline__ void commit_plane(R* __restrict__ ring, int slot, const R (&v)[T::NPER], int tid) {
+  R* dst = ring + slot * T::PL;
+#pragma unroll
+  for (int k = 0; k < T::NPER; ++k) {
+    const int e = tid + k * T::NT;
+    if (e < T::PL) dst[e] = v[k];
+  }
+}
+
+__device__ __forceinline__ int plane_slot(int zz, int npl) { return (zz + 8 * npl) % npl; }
 
 __device__ __forceinline__ int ring_slot(int zc, int dz, int npl) {
   int s = zc + dz;
@@ -259,25 +307,44 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
   using R = typename Storage<S>::real;
   __shared__ R ring[T::NPL * T::PL];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + T::TX * ty;
-  const int x0 = blockIdx.x * T::TX, y0 = blockIdx.y * T::TY;
-  const int z0 = blockIdx.z * a.z_per_block;
+  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
+  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
+  const int zb = t / txy;
+  const uint32_t r = t - zb * txy;
+  const int tyi = r / a.tiles_x, txi = r - tyi * a.tiles_x;
+  const int x0 = txi * T::TX, y0 = tyi * T::TY;
+  const int z0 = zb * a.z_per_block;
   const int z1 = min(z0 + a.z_per_block, a.nz);
   const int x = x0 + tx, y = y0 + ty;
   const bool valid_xy = x < a.nx && y < a.ny;
 
-  // preload planes z0 - RZ .. z0 + RZ - 1; plane zz lives in slot (zz + NPL) % NPL
-  for (int dz = -T::RZ; dz < T::RZ; ++dz)
-    load_plane<T>(ring, (z0 + dz + T::NPL * 4) % T::NPL, z0 + dz, phi, x0, y0, a, tid);
+  // stage planes z0 - RZ .. z0 + RZ; plane zz lives in slot plane_slot(zz)
+  for (int dz = -T::RZ; dz <= T::RZ; ++dz)
+    load_plane<T>(ring, plane_slot(z0 + dz, T::NPL), z0 + dz, phi, x0, y0, a, tid);
+  __syncthreads();
 
   const R omega = (R)a.omega, guo = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
   const R hshift = (R)a.half_rho0, phiI = (R)a.phi_I;
   const int c0 = (ty + T::RAD) * T::TXH + (tx + T::RAD);
 
   for (int z = z0; z < z1; ++z) {
-    const int zc = (z + T::NPL * 4) % T::NPL;
-    load_plane<T>(ring, ring_slot(zc, T::RZ, T::NPL), z + T::RZ, phi, x0, y0, a, tid);
-    __syncthreads();
+    // prefetch the plane the next iteration needs into registers; it goes to
+    // the spare ring slot at the end of this iteration (one barrier per plane)
+    const bool more = T::RZ && z + 1 < z1;
+    R nxt[T::NPER];
+    if (more) fetch_plane<T>(nxt, z + 1 + T::RZ, phi, x0, y0, a, tid);
+    const int zc = plane_slot(z, T::NPL);
     if (valid_xy) {
+      // ---- issue the pull of both colours first (shifted by w_i rho0/2 per
+      // colour) so that its latency overlaps the stencil work below
+      const Nbr n = make_nbr(x, y, z, a);
+      R va[L::Q], vb[L::Q];
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const uint32_t e = pull_index<L, I>(n, a.N);
+        va[I] = Storage<S>::template load<I, L>(fin + e, hshift);
+        vb[I] = Storage<S>::template load<I, L>(fin + a.QN + e, hshift);
+      });
       const int p0 = zc * T::PL;
       constexpr int dz1 = T::RZ ? 1 : 0;   // 2D: a single plane
       const int pm = ring_slot(zc, -dz1, T::NPL) * T::PL;
@@ -324,17 +391,13 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
           }
         }
       }
-      // ---- pull the populations (shifted by w_i rho0/2 per colour)
-      const Nbr n = make_nbr(x, y, z, a);
+      // ---- moments of the pulled populations
       R d[L::Q];  // d_i = f_i - w_i rho0, total over both colours
       R sa = 0, sb = 0;
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        const uint32_t e = pull_index<L, I>(n, a.N);
-        const R va = Storage<S>::template load<I, L>(fin + e, hshift);
-        const R vb = Storage<S>::template load<I, L>(fin + a.QN + e, hshift);
-        sa += va; sb += vb;
-        d[I] = va + vb;
+        sa += va[I]; sb += vb[I];
+        d[I] = va[I] + vb[I];
       });
       R jx = 0, jy = 0, jz = 0, drho = 0;
       static_for<0, L::Q>([&](auto ic) {
@@ -395,6 +458,7 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
         fo.flags[n.site] = flag ? 1 : 0;
       }
     }
+    if (more) commit_plane<T>(ring, plane_slot(z + 1 + T::RZ, T::NPL), nxt, tid);
     __syncthreads();
   }
 }
