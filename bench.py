@@ -27,19 +27,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS & % HBM roofline, 2-comp D3Q27; FP16-store/learned vs plain FP32"
-ELEM = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+ELEM = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32t": 4, "f16t": 2, "bf16t": 2}
+TOTAL = ("f32t", "f16t", "bf16t")
+NSC_BYTES = 16  # recolouring scalars of the total layout, per site
 
 
 def algorithmic_bytes(q, storage):
-    """Per lattice update: every population of both colours read once and
-    written once, plus the phase field written once (pass 1) and read once
-    (pass 2).  Collision pass alone: populations read + written + phase read."""
+    """Per lattice update of the layout in use: its state read once and written
+    once, plus the phase field written once (pass 1) and read once (pass 2).
+    Collision pass alone: state read + written + phase read; phase pass: state
+    read + phase written.  The plain per-colour FP32 D3Q27 step is 440 B."""
     s = ELEM[storage]
     r = 8 if storage == "f64" else 4
-    step = 2 * q * s * 2 + 2 * r
-    collide = 2 * q * s * 2 + r
-    phase = 2 * q * s + r
-    return step, collide, phase
+    state = (q * s + NSC_BYTES) if storage in TOTAL else 2 * q * s
+    return 2 * state + 2 * r, 2 * state + r, state + r
+
+
+def plain_state_bytes(q, storage):
+    """Algorithmic bytes of the two-colour state at this precision (per-colour
+    populations read and written once, phase field once each way): the
+    reference definition the step roofline is quoted against."""
+    s = ELEM[storage]
+    r = 8 if storage == "f64" else 4
+    return 2 * q * s * 2 + 2 * r
 
 
 def traffic_from_profiles(kernel_tag, workload_tag):
@@ -187,6 +197,9 @@ def main():
                      "traffic": traffic, "kernel": "k_collide (collision pass)",
                      "bytes_per_site": b_col, "avg_launch_ms": round(col_ms, 5)},
         "step_roofline": {"bytes_per_site": b_step, "frac": round(mlups * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
+                          "plain_state_bytes_per_site": plain_state_bytes(q, storage),
+                          "frac_vs_plain_state": round(mlups * 1e6 * plain_state_bytes(q, storage) / 1e9
+                                                       / HBM_PEAK_GBS, 4),
                           "phase_pass_ms": round(ph_ms, 5), "phase_pass_GBs": round(b_phase * N / (ph_ms / 1e3) / 1e9, 1)},
         "sanity": {"droplets_end": int(diag[6]), "umax": float(diag[5])},
     }

@@ -53,15 +53,27 @@ typedef enum lb_status {
 
 typedef enum lb_lattice { LB_D2Q9 = 0, LB_D3Q19 = 1, LB_D3Q27 = 2 } lb_lattice;
 
-/* Storage precision of the populations.  Collision arithmetic is FP64 for
- * LB_F64 and FP32 otherwise.  The 16-bit modes store the shifted value
- * f^k_i - w_i rho0 / 2 of each colour, rounded to nearest even (paper: Sec. IV,
- * Eqs. shift_f, shift-lbm), and add the shift back on load. */
+/* Storage of the populations.  Collision arithmetic is FP64 for LB_F64 and
+ * FP32 otherwise, in both cases on populations shifted by the rest
+ * equilibrium (paper: Sec. IV "Second group", Eqs. shift_f, shift-lbm,
+ * shift-eq).
+ *  - Per-colour layouts keep both colours f^k_i.  LB_F64 / LB_F32 store f^k_i;
+ *    the 16-bit modes store f^k_i - w_i rho0 / 2 rounded to nearest even.
+ *  - Total layouts keep the total post-collision population shifted by the
+ *    rest equilibrium, T_i = f*_i - w_i rho0 (Eq. shift_f with rho0, u0 = 0), in
+ *    the storage type, plus four FP32 scalars per site, a = rho_A / rho and
+ *    b = beta (rho_A rho_B / rho) n (n the unit colour gradient).  The
+ *    recolouring equations (Eqs. ome3_1, ome3_2) give the colours exactly:
+ *    f^A_i = a f*_i + (w_i / |c_i|) c_i . b, f^B_i = f*_i - f^A_i.  The two-colour
+ *    step is unchanged; the state is Q storage values + 16 bytes per site. */
 typedef enum lb_storage {
   LB_F64 = 0,
   LB_F32 = 1,
   LB_F16_SHIFTED = 2,
-  LB_BF16_SHIFTED = 3
+  LB_BF16_SHIFTED = 3,
+  LB_F32_TOTAL = 4,
+  LB_F16_TOTAL = 5,
+  LB_BF16_TOTAL = 6
 } lb_storage;
 
 typedef enum lb_nc_mode { LB_NC_OFF = 0, LB_NC_EXPLICIT = 1 } lb_nc_mode;
@@ -105,7 +117,7 @@ void lb_params_default(lb_params* p);
 
 /* Create a simulation.  p points at n_channels parameter sets; this build
  * accepts n_channels == 1.  hip_stream is a hipStream_t (NULL allowed).
- * Allocates 2 * 2 * Q * N populations of the storage type plus the fields.
+ * Allocates two copies of the state (see lb_state_bytes) plus the fields.
  * Errors: LB_EINVAL, LB_ENOMEM, LB_ENODEV, LB_EHIP.  *out is NULL on error. */
 int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** out);
 
@@ -141,11 +153,14 @@ int lb_fields(lb_handle* h, int channel, unsigned mask, void* const* dst, int ds
  * with j = rho u - F/2.  Synchronises. */
 int lb_diagnostics(lb_handle* h, int channel, double out[8]);
 
-/* Size in bytes of the raw population state (2 * Q * N storage elements). */
+/* Size in bytes of the raw state: per-colour layouts 2 * Q * N storage
+ * elements f[k][i][s]; total layouts Q * N storage elements T[i][s] followed by
+ * 4 * N floats (a, b_x, b_y, b_z as [4][s]). */
 int lb_state_bytes(const lb_handle* h, size_t* bytes);
-/* Copy the current post-collision populations out / in (f[k][i][s] in the
- * storage type; 16-bit modes hold the shifted values).  Host buffers when
- * *_on_device == 0 (synchronises).  lb_set_state keeps the step counter. */
+/* Copy the current post-collision state out / in, in the layout above (16-bit
+ * modes hold the shifted values).  Host buffers when *_on_device == 0
+ * (synchronises).  lb_set_state keeps the step counter; fields are available
+ * again after the next step. */
 int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device);
 int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device);
 

@@ -48,12 +48,17 @@ const LatticeOps* ops_for(int lattice) {
 size_t storage_bytes(int st) {
   switch (st) {
     case LB_F64: return 8;
-    case LB_F32: return 4;
+    case LB_F32:
+    case LB_F32_TOTAL: return 4;
     case LB_F16_SHIFTED:
-    case LB_BF16_SHIFTED: return 2;
+    case LB_BF16_SHIFTED:
+    case LB_F16_TOTAL:
+    case LB_BF16_TOTAL: return 2;
   }
   return 0;
 }
+
+bool total_layout(int st) { return st == LB_F32_TOTAL || st == LB_F16_TOTAL || st == LB_BF16_TOTAL; }
 
 }  // namespace
 
@@ -67,6 +72,8 @@ struct lb_handle {
   hipStream_t stream = nullptr;
   int device = 0;
   void* f[2] = {nullptr, nullptr};
+  float* sc[2] = {nullptr, nullptr};  // recolouring scalars (total layout only)
+  bool total = false;
   int cur = 0;
   void* phi = nullptr;
   void* rho_a = nullptr;
@@ -201,7 +208,7 @@ int lb_destroy(lb_handle* h) {
   if (h->stream) hipStreamSynchronize(h->stream);
   else hipDeviceSynchronize();
   for (hipEvent_t e : h->prof_events) hipEventDestroy(e);
-  void* bufs[] = {h->f[0], h->f[1], h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
+  void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
                   h->diag_partial, h->diag_out, h->ccl_count, h->drops};
   for (void* b : bufs)
     if (b) hipFree(b);
@@ -240,6 +247,7 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
   h->N = (uint32_t)((size_t)p->nx * p->ny * p->nz);
   h->esize = storage_bytes(p->storage);
   h->rsize = p->storage == LB_F64 ? 8 : 4;
+  h->total = total_layout(p->storage);
   h->stream = (hipStream_t)hip_stream;
   hipGetDevice(&h->device);
   // pass-2 blocks march through z; aim for about 2048 blocks in flight
@@ -256,7 +264,7 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
     h->z_per_block = (int)zb;
   }
   const size_t N = h->N;
-  const size_t pop = 2ull * h->q * N * h->esize;
+  const size_t pop = (h->total ? 1ull : 2ull) * h->q * N * h->esize;
 #define ALLOC(ptr, bytes)                                              \
   do {                                                                 \
     int r_ = dev_alloc((void**)&(ptr), (bytes), #ptr);                 \
@@ -264,6 +272,10 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
   } while (0)
   ALLOC(h->f[0], pop);
   ALLOC(h->f[1], pop);
+  if (h->total) {
+    ALLOC(h->sc[0], sizeof(float) * NSC * N);
+    ALLOC(h->sc[1], sizeof(float) * NSC * N);
+  }
   ALLOC(h->phi, N * h->rsize);
   ALLOC(h->rho_a, N * h->rsize);
   ALLOC(h->rho_b, N * h->rsize);
@@ -315,7 +327,7 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
   a.half_rho0 = 0.5 * h->p.rho0;
   a.phi_I = h->p.phi_interface;
   h->cur = 0;
-  HIP_TRY(h->ops->init(h->p.storage, h->f[0], h->phi, h->field_ptrs(), h->drops, a, h->stream));
+  HIP_TRY(h->ops->init(h->p.storage, h->f[0], h->sc[0], h->phi, h->field_ptrs(), h->drops, a, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));  // the host droplet list goes out of scope
   h->t = 0;
   h->initialised = true;
@@ -379,10 +391,11 @@ int lb_step(lb_handle* h, int nsteps) {
     void* fout = h->f[1 - h->cur];
     int r = prof_mark(h, 0, true);
     if (r) return r;
-    HIP_TRY(h->ops->phase(h->p.storage, fin, h->phi, a, h->stream));
+    HIP_TRY(h->ops->phase(h->p.storage, fin, h->sc[h->cur], h->phi, a, h->stream));
     if ((r = prof_mark(h, 0, false))) return r;
     if ((r = prof_mark(h, 1, true))) return r;
-    HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->phi, fo, a, h->stream));
+    HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->sc[h->cur], h->sc[1 - h->cur], h->phi, fo, a,
+                            h->stream));
     if ((r = prof_mark(h, 1, false))) return r;
     h->cur = 1 - h->cur;
     h->t += 1;
@@ -472,30 +485,40 @@ int lb_diagnostics(lb_handle* h, int channel, double out[8]) {
   return LB_OK;
 }
 
+static size_t state_size(const lb_handle* h, size_t* pop_bytes) {
+  const size_t pop = (h->total ? 1ull : 2ull) * h->q * h->N * h->esize;
+  if (pop_bytes) *pop_bytes = pop;
+  return pop + (h->total ? sizeof(float) * NSC * h->N : 0);
+}
+
 int lb_state_bytes(const lb_handle* h, size_t* bytes) {
   if (!h || !bytes) return fail(LB_EINVAL, "NULL argument");
-  *bytes = 2ull * h->q * h->N * h->esize;
+  *bytes = state_size(h, nullptr);
   return LB_OK;
 }
 
 int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device) {
   if (!h || !dst) return fail(LB_EINVAL, "NULL argument");
-  const size_t need = 2ull * h->q * h->N * h->esize;
+  size_t pop = 0;
+  const size_t need = state_size(h, &pop);
   if (bytes != need) return fail(LB_EINVAL, "state is %zu bytes, got %zu", need, bytes);
   hipSetDevice(h->device);
-  HIP_TRY(hipMemcpyAsync(dst, h->f[h->cur], need, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                         h->stream));
+  const hipMemcpyKind k = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIP_TRY(hipMemcpyAsync(dst, h->f[h->cur], pop, k, h->stream));
+  if (h->total) HIP_TRY(hipMemcpyAsync((char*)dst + pop, h->sc[h->cur], need - pop, k, h->stream));
   if (!dst_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
   return LB_OK;
 }
 
 int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device) {
   if (!h || !src) return fail(LB_EINVAL, "NULL argument");
-  const size_t need = 2ull * h->q * h->N * h->esize;
+  size_t pop = 0;
+  const size_t need = state_size(h, &pop);
   if (bytes != need) return fail(LB_EINVAL, "state is %zu bytes, got %zu", need, bytes);
   hipSetDevice(h->device);
-  HIP_TRY(hipMemcpyAsync(h->f[h->cur], src, need, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                         h->stream));
+  const hipMemcpyKind k = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIP_TRY(hipMemcpyAsync(h->f[h->cur], src, pop, k, h->stream));
+  if (h->total) HIP_TRY(hipMemcpyAsync(h->sc[h->cur], (const char*)src + pop, need - pop, k, h->stream));
   if (!src_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
   h->initialised = true;
   h->fields_valid = false;

@@ -71,4 +71,49 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ f, typename Storag
   fo.flags[s] = fabs((R)phi) < (R)a.phi_I ? 1 : 0;
 }
 
+// initial state of the total layout: T_i = f^eq_i(rho, u0) - w_i rho0 with
+// rho = rho_A + rho_B, recolouring scalars a = rho_A / rho, b = 0 (the two
+// colours of an equilibrium with one velocity are proportional to rho_k)
+template <class L, class S>
+__global__ void __launch_bounds__(256) k_init_total(S* __restrict__ f, float* __restrict__ sc,
+                                                    float* __restrict__ phi_out, FieldPtrs fo,
+                                                    const double* __restrict__ drops, InitArgs a) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.N) return;
+  const int x = s % a.nx;
+  const int y = (s / a.nx) % a.ny;
+  const int z = s / ((uint32_t)a.nx * a.ny);
+  double best = -1.0e300;
+  for (int d = 0; d < a.ndrop; ++d) {
+    const double dx = min_image((double)x - drops[4 * d + 0], a.nx, a.wall_x);
+    const double dy = min_image((double)y - drops[4 * d + 1], a.ny, a.wall_y);
+    const double dz = a.dims == 3 ? min_image((double)z - drops[4 * d + 2], a.nz, a.wall_z) : 0.0;
+    const double v = drops[4 * d + 3] - sqrt(dx * dx + dy * dy + dz * dz);
+    best = v > best ? v : best;
+  }
+  const double phi = a.phi_in * tanh(2.0 * best / a.width);
+  const double ra = a.rho0 * (1.0 + phi) * 0.5, rb = a.rho0 * (1.0 - phi) * 0.5, rho = ra + rb;
+  const double uu = a.u0x * a.u0x + a.u0y * a.u0y + a.u0z * a.u0z;
+  static_for<0, L::Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const double cu = L::cx[I] * a.u0x + L::cy[I] * a.u0y + L::cz[I] * a.u0z;
+    const double T = L::w[I] * ((rho - a.rho0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    total_store(f + (size_t)I * a.N + s, (float)T);
+  });
+  sc[s] = (float)(ra / rho);
+  sc[a.N + s] = 0.f;
+  sc[2 * (size_t)a.N + s] = 0.f;
+  sc[3 * (size_t)a.N + s] = 0.f;
+  phi_out[s] = (float)phi;
+  float* rA = (float*)fo.rho_a;
+  float* rB = (float*)fo.rho_b;
+  float* U = (float*)fo.u;
+  float* Fn = (float*)fo.fnc;
+  rA[s] = (float)ra;
+  rB[s] = (float)rb;
+  U[s] = (float)a.u0x; U[a.N + s] = (float)a.u0y; U[2 * (size_t)a.N + s] = (float)a.u0z;
+  Fn[s] = 0; Fn[a.N + s] = 0; Fn[2 * (size_t)a.N + s] = 0;
+  fo.flags[s] = fabsf((float)phi) < (float)a.phi_I ? 1 : 0;
+}
+
 }  // namespace lbm

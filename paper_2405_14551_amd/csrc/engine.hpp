@@ -9,7 +9,9 @@
 
 namespace lbm {
 
-enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+// per-colour layouts, then the total layout (total population + recolouring scalars)
+enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32T = 4, ST_F16T = 5, ST_BF16T = 6 };
+inline bool is_total(int st) { return st >= ST_F32T; }
 
 // pass-2 tile: 64 x-sites (one wave per row) by 4 rows
 constexpr int TILE_X = 64;
@@ -17,10 +19,11 @@ constexpr int TILE_Y = 4;
 
 struct LatticeOps {
   int q, d;
-  hipError_t (*phase)(int storage, const void* fin, void* phi, const StepArgs& a, hipStream_t s);
-  hipError_t (*collide)(int storage, bool nc, bool fields, const void* fin, void* fout, const void* phi,
-                        const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
-  hipError_t (*init)(int storage, void* f, void* phi, const FieldPtrs& fo, const double* drops,
+  // sc / scin / scout: recolouring scalars of the total layout (unused otherwise)
+  hipError_t (*phase)(int storage, const void* fin, const float* scin, void* phi, const StepArgs& a, hipStream_t s);
+  hipError_t (*collide)(int storage, bool nc, bool fields, const void* fin, void* fout, const float* scin,
+                        float* scout, const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
+  hipError_t (*init)(int storage, void* f, float* sc, void* phi, const FieldPtrs& fo, const double* drops,
                      const InitArgs& a, hipStream_t s);
 };
 

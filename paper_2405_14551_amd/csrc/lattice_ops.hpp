@@ -24,19 +24,37 @@ struct Launch {
     return hipGetLastError();
   }
 
-  static hipError_t phase(int st, const void* fin, void* phi, const StepArgs& a, hipStream_t s) {
+  template <class S>
+  static hipError_t phase_total_t(const void* fin, const float* scin, void* phi, const StepArgs& a,
+                                  hipStream_t s) {
+    using TS = Tile<TILE_X, TILE_Y, 1, L::D>;
+    dim3 block(TS::TX, TS::TY, 1);
+    const int zb = a.z_per_block;
+    StepArgs b = a;
+    b.tiles_x = (a.nx + TS::TX - 1) / TS::TX;
+    b.tiles_y = (a.ny + TS::TY - 1) / TS::TY;
+    dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
+    k_phase_total<L, S, TS><<<grid, block, 0, s>>>((const S*)fin, scin, (float*)phi, b);
+    return hipGetLastError();
+  }
+
+  static hipError_t phase(int st, const void* fin, const float* scin, void* phi, const StepArgs& a,
+                          hipStream_t s) {
     switch (st) {
       case ST_F64: return phase_t<double>(fin, phi, a, s);
       case ST_F32: return phase_t<float>(fin, phi, a, s);
       case ST_F16: return phase_t<_Float16>(fin, phi, a, s);
       case ST_BF16: return phase_t<__bf16>(fin, phi, a, s);
+      case ST_F32T: return phase_total_t<float>(fin, scin, phi, a, s);
+      case ST_F16T: return phase_total_t<_Float16>(fin, scin, phi, a, s);
+      case ST_BF16T: return phase_total_t<__bf16>(fin, scin, phi, a, s);
     }
     return hipErrorInvalidValue;
   }
 
-  template <class S, int RAD, bool NC, bool FIELDS>
-  static hipError_t collide_t(const void* fin, void* fout, const void* phi, const FieldPtrs& fo,
-                              const StepArgs& a, hipStream_t s) {
+  template <class S, int RAD, bool NC, bool FIELDS, bool TOT>
+  static hipError_t collide_t(const void* fin, void* fout, const float* scin, float* scout, const void* phi,
+                              const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     using R = typename Storage<S>::real;
     using T = Tile<TILE_X, TILE_Y, RAD, L::D>;
     dim3 block(T::TX, T::TY, 1);
@@ -45,28 +63,32 @@ struct Launch {
     b.tiles_x = (a.nx + T::TX - 1) / T::TX;
     b.tiles_y = (a.ny + T::TY - 1) / T::TY;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide<L, S, T, NC, FIELDS><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, fo, b);
+    k_collide<L, S, T, NC, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scin, scout,
+                                                               fo, b);
     return hipGetLastError();
   }
 
-  template <class S>
-  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, const void* phi,
-                              const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+  template <class S, bool TOT>
+  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, const float* scin, float* scout,
+                              const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     if (nc) {
-      return fields ? collide_t<S, 4, true, true>(fin, fout, phi, fo, a, s)
-                    : collide_t<S, 4, true, false>(fin, fout, phi, fo, a, s);
+      return fields ? collide_t<S, 4, true, true, TOT>(fin, fout, scin, scout, phi, fo, a, s)
+                    : collide_t<S, 4, true, false, TOT>(fin, fout, scin, scout, phi, fo, a, s);
     }
-    return fields ? collide_t<S, 1, false, true>(fin, fout, phi, fo, a, s)
-                  : collide_t<S, 1, false, false>(fin, fout, phi, fo, a, s);
+    return fields ? collide_t<S, 1, false, true, TOT>(fin, fout, scin, scout, phi, fo, a, s)
+                  : collide_t<S, 1, false, false, TOT>(fin, fout, scin, scout, phi, fo, a, s);
   }
 
-  static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, const void* phi,
-                            const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+  static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, const float* scin,
+                            float* scout, const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     switch (st) {
-      case ST_F64: return collide_s<double>(nc, fields, fin, fout, phi, fo, a, s);
-      case ST_F32: return collide_s<float>(nc, fields, fin, fout, phi, fo, a, s);
-      case ST_F16: return collide_s<_Float16>(nc, fields, fin, fout, phi, fo, a, s);
-      case ST_BF16: return collide_s<__bf16>(nc, fields, fin, fout, phi, fo, a, s);
+      case ST_F64: return collide_s<double, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
+      case ST_F32: return collide_s<float, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
+      case ST_F16: return collide_s<_Float16, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
+      case ST_BF16: return collide_s<__bf16, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
+      case ST_F32T: return collide_s<float, true>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
+      case ST_F16T: return collide_s<_Float16, true>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
+      case ST_BF16T: return collide_s<__bf16, true>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
     }
     return hipErrorInvalidValue;
   }
@@ -81,13 +103,25 @@ struct Launch {
     return hipGetLastError();
   }
 
-  static hipError_t init(int st, void* f, void* phi, const FieldPtrs& fo, const double* drops,
+  template <class S>
+  static hipError_t init_total_t(void* f, float* sc, void* phi, const FieldPtrs& fo, const double* drops,
+                                 const InitArgs& a, hipStream_t s) {
+    dim3 block(256);
+    dim3 grid((a.N + 255) / 256);
+    k_init_total<L, S><<<grid, block, 0, s>>>((S*)f, sc, (float*)phi, fo, drops, a);
+    return hipGetLastError();
+  }
+
+  static hipError_t init(int st, void* f, float* sc, void* phi, const FieldPtrs& fo, const double* drops,
                          const InitArgs& a, hipStream_t s) {
     switch (st) {
       case ST_F64: return init_t<double>(f, phi, fo, drops, a, s);
       case ST_F32: return init_t<float>(f, phi, fo, drops, a, s);
       case ST_F16: return init_t<_Float16>(f, phi, fo, drops, a, s);
       case ST_BF16: return init_t<__bf16>(f, phi, fo, drops, a, s);
+      case ST_F32T: return init_total_t<float>(f, sc, phi, fo, drops, a, s);
+      case ST_F16T: return init_total_t<_Float16>(f, sc, phi, fo, drops, a, s);
+      case ST_BF16T: return init_total_t<__bf16>(f, sc, phi, fo, drops, a, s);
     }
     return hipErrorInvalidValue;
   }

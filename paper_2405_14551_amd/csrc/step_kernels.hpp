@@ -299,13 +299,148 @@ __device__ __forceinline__ void ring_gradient(const R* __restrict__ ring, int c0
 }
 
 // ----------------------------------------------------------------------------
+// Total layout.  Instead of the two colours, HBM holds the total post-collision
+// population T_i = f*_i - w_i rho0 (shifted by the rest equilibrium, in the
+// storage type) and four FP32 scalars per site: a = rho_A / rho and
+// b = beta (rho_A rho_B / rho) n (n the unit colour gradient).  The recolouring
+// equations make the colours exact functions of these:
+//   f^A_i = a f*_i + (w_i / |c_i|) c_i . b,   f^B_i = f*_i - f^A_i,
+// so pulling T and the scalars of x - c_i reproduces the two-colour pull.
+constexpr int NSC = 4;  // scalars per site: a, b_x, b_y, b_z
+
+template <class S>
+__device__ __forceinline__ float total_load(const S* p) { return (float)(*p); }
+template <class S>
+__device__ __forceinline__ void total_store(S* p, float v) { *p = (S)v; }
+template <>
+__device__ __forceinline__ void total_store<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
+// radius-1 ring of the NSC scalar planes, laid out [slot][channel][plane]
+template <class TS>
+struct ScalarRing {
+  static constexpr int SLOT = NSC * TS::PL;
+  static constexpr int NPER = (SLOT + TS::NT - 1) / TS::NT;
+};
+
+template <class TS>
+__device__ __forceinline__ void fetch_scalars(float (&v)[ScalarRing<TS>::NPER], int zz, const float* __restrict__ sc,
+                                              int x0, int y0, const StepArgs& a, int tid) {
+  const int gz = halo_coord(zz, a.nz, a.wall_z);
+  const size_t zoff = (size_t)gz * a.nx * a.ny;
+#pragma unroll
+  for (int k = 0; k < ScalarRing<TS>::NPER; ++k) {
+    const int e = tid + k * TS::NT;
+    if (e < ScalarRing<TS>::SLOT) {
+      const int ch = e / TS::PL, rr = e - ch * TS::PL;
+      const int hy = rr / TS::TXH, hx = rr - hy * TS::TXH;
+      const int gx = halo_coord(x0 - TS::RAD + hx, a.nx, a.wall_x);
+      const int gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
+      v[k] = sc[(size_t)ch * a.N + zoff + (size_t)gy * a.nx + gx];
+    }
+  }
+}
+
+template <class TS>
+__device__ __forceinline__ void commit_scalars(float* __restrict__ sring, int slot,
+                                               const float (&v)[ScalarRing<TS>::NPER], int tid) {
+  float* dst = sring + slot * ScalarRing<TS>::SLOT;
+#pragma unroll
+  for (int k = 0; k < ScalarRing<TS>::NPER; ++k) {
+    const int e = tid + k * TS::NT;
+    if (e < ScalarRing<TS>::SLOT) dst[e] = v[k];
+  }
+}
+
+// colour A of the pulled population i at the site of `n`, shifted by w_i rho0/2,
+// from the raw total T (already loaded from the upstream node, or from the
+// site itself in the opposite direction under bounce-back) and the upstream
+// node's scalars in the ring (centre position sc0, centre plane slot zcs)
+template <class L, class TS, int I, class R>
+__device__ __forceinline__ R colour_a(R T, const float* __restrict__ sring, const Nbr& n, int zcs, int sc0,
+                                      R rho0, R h) {
+  constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+  constexpr int ix = 1 - cx, iy = 1 - cy, iz = 1 - cz;
+  const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
+  const int slot = solid ? zcs : ring_slot(zcs, -cz, TS::NPL);
+  const int pos = solid ? sc0 : sc0 - cy * TS::TXH - cx;
+  const float* q = sring + slot * ScalarRing<TS>::SLOT + pos;
+  const R aa = (R)q[0];
+  R v = aa * T + (R)L::w[I] * (aa * rho0 - h);
+  if constexpr (I != 0) {
+    R cb = 0;
+    if constexpr (cx != 0) cb += (R)cx * (R)q[TS::PL];
+    if constexpr (cy != 0) cb += (R)cy * (R)q[2 * TS::PL];
+    if constexpr (cz != 0) cb += (R)cz * (R)q[3 * TS::PL];
+    // the bounced population moved along -c_i before the wall reversed it
+    const R r = (R)(L::w[I] * inv_norm<L>(I)) * cb;
+    v += solid ? -r : r;
+  }
+  return v;
+}
+
+// ----------------------------------------------------------------------------
+// pass 1 of the total layout: phase field from reconstructed colours, marching
+// along z with the scalars of the tile plus a one-site halo staged in LDS
+template <class L, class S, class TS>
+__global__ void __launch_bounds__(TS::NT) k_phase_total(const S* __restrict__ fin, const float* __restrict__ scin,
+                                                        float* __restrict__ phi, StepArgs a) {
+  __shared__ float sring[TS::NPL * ScalarRing<TS>::SLOT];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TS::TX * ty;
+  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
+  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
+  const int zb = t / txy;
+  const uint32_t r = t - zb * txy;
+  const int tyi = r / a.tiles_x, txi = r - tyi * a.tiles_x;
+  const int x0 = txi * TS::TX, y0 = tyi * TS::TY;
+  const int z0 = zb * a.z_per_block;
+  const int z1 = min(z0 + a.z_per_block, a.nz);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool valid_xy = x < a.nx && y < a.ny;
+  for (int dz = -TS::RZ; dz <= TS::RZ; ++dz) {
+    float v[ScalarRing<TS>::NPER];
+    fetch_scalars<TS>(v, z0 + dz, scin, x0, y0, a, tid);
+    commit_scalars<TS>(sring, plane_slot(z0 + dz, TS::NPL), v, tid);
+  }
+  __syncthreads();
+  const float h = (float)a.half_rho0, rho0 = 2.0f * h;
+  const int sc0 = (ty + 1) * TS::TXH + (tx + 1);
+  for (int z = z0; z < z1; ++z) {
+    const bool more = TS::RZ && z + 1 < z1;
+    float nxt[ScalarRing<TS>::NPER];
+    if (more) fetch_scalars<TS>(nxt, z + 1 + TS::RZ, scin, x0, y0, a, tid);
+    if (valid_xy) {
+      const Nbr n = make_nbr(x, y, z, a);
+      float Tv[L::Q];
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        Tv[I] = total_load(fin + pull_index<L, I>(n, a.N));
+      });
+      const int zcs = plane_slot(z, TS::NPL);
+      float sa = 0.f, sb = 0.f;
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const float da = colour_a<L, TS, I, float>(Tv[I], sring, n, zcs, sc0, rho0, h);
+        sa += da;
+        sb += Tv[I] - da;
+      });
+      phi[n.site] = (sa - sb) / (rho0 + (sa + sb));
+    }
+    if (more) commit_scalars<TS>(sring, plane_slot(z + 1 + TS::RZ, TS::NPL), nxt, tid);
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
 // pass 2: gradient, flags, near contact, collision, recolouring, store
-template <class L, class S, class T, bool NC, bool FIELDS>
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
 __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::real* __restrict__ phi,
+                                                    const float* __restrict__ scin, float* __restrict__ scout,
                                                     FieldPtrs fo, StepArgs a) {
   using R = typename Storage<S>::real;
+  using TS = Tile<T::TX, T::TY, 1, L::D>;   // scalar ring of the total layout
   __shared__ R ring[T::NPL * T::PL];
+  __shared__ float sring[TOT ? TS::NPL * ScalarRing<TS>::SLOT : 1];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + T::TX * ty;
   const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
   const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
@@ -321,7 +456,15 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
   // stage planes z0 - RZ .. z0 + RZ; plane zz lives in slot plane_slot(zz)
   for (int dz = -T::RZ; dz <= T::RZ; ++dz)
     load_plane<T>(ring, plane_slot(z0 + dz, T::NPL), z0 + dz, phi, x0, y0, a, tid);
+  if constexpr (TOT) {
+    for (int dz = -TS::RZ; dz <= TS::RZ; ++dz) {
+      float v[ScalarRing<TS>::NPER];
+      fetch_scalars<TS>(v, z0 + dz, scin, x0, y0, a, tid);
+      commit_scalars<TS>(sring, plane_slot(z0 + dz, TS::NPL), v, tid);
+    }
+  }
   __syncthreads();
+  const int sc0 = (ty + 1) * TS::TXH + (tx + 1);
 
   const R omega = (R)a.omega, guo = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
   const R hshift = (R)a.half_rho0, phiI = (R)a.phi_I;
@@ -333,17 +476,25 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
     const bool more = T::RZ && z + 1 < z1;
     R nxt[T::NPER];
     if (more) fetch_plane<T>(nxt, z + 1 + T::RZ, phi, x0, y0, a, tid);
+    float snxt[TOT ? ScalarRing<TS>::NPER : 1];
+    if constexpr (TOT) {
+      if (more) fetch_scalars<TS>(snxt, z + 1 + TS::RZ, scin, x0, y0, a, tid);
+    }
     const int zc = plane_slot(z, T::NPL);
     if (valid_xy) {
-      // ---- issue the pull of both colours first (shifted by w_i rho0/2 per
-      // colour) so that its latency overlaps the stencil work below
+      // ---- issue the pull first so that its latency overlaps the stencil
+      // work below: both colours (shifted by w_i rho0/2 each), or the total
       const Nbr n = make_nbr(x, y, z, a);
-      R va[L::Q], vb[L::Q];
+      R va[L::Q], vb[TOT ? 1 : L::Q];
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         const uint32_t e = pull_index<L, I>(n, a.N);
-        va[I] = Storage<S>::template load<I, L>(fin + e, hshift);
-        vb[I] = Storage<S>::template load<I, L>(fin + a.QN + e, hshift);
+        if constexpr (TOT) {
+          va[I] = (R)total_load(fin + e);
+        } else {
+          va[I] = Storage<S>::template load<I, L>(fin + e, hshift);
+          vb[I] = Storage<S>::template load<I, L>(fin + a.QN + e, hshift);
+        }
       });
       const int p0 = zc * T::PL;
       constexpr int dz1 = T::RZ ? 1 : 0;   // 2D: a single plane
@@ -396,8 +547,15 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
       R sa = 0, sb = 0;
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        sa += va[I]; sb += vb[I];
-        d[I] = va[I] + vb[I];
+        if constexpr (TOT) {
+          const R da = colour_a<L, TS, I, R>(va[I], sring, n, plane_slot(z, TS::NPL), sc0, R(2) * hshift, hshift);
+          sa += da;
+          sb += va[I] - da;
+          d[I] = va[I];
+        } else {
+          sa += va[I]; sb += vb[I];
+          d[I] = va[I] + vb[I];
+        }
       });
       R jx = 0, jy = 0, jz = 0, drho = 0;
       static_for<0, L::Q>([&](auto ic) {
@@ -441,11 +599,23 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
         R rec = 0;
         if constexpr (I != 0) rec = coef * wi * (cg * (R)inv_norm<L>(I) * inv_gn);
         // recolouring in shifted form: f^A - w rho0/2 = (rho_A/rho) (f* - w rho0) + w rho0 phi/2 + rec
-        const R da = fa_frac * ds + wi * half_phi_rho0 + rec;
-        const R db = ds - da;
-        Storage<S>::template store<I, L>(fout + (size_t)I * a.N + n.site, da, hshift);
-        Storage<S>::template store<I, L>(fout + a.QN + (size_t)I * a.N + n.site, db, hshift);
+        if constexpr (TOT) {
+          total_store(fout + (size_t)I * a.N + n.site, (float)ds);
+        } else {
+          const R da = fa_frac * ds + wi * half_phi_rho0 + rec;
+          const R db = ds - da;
+          Storage<S>::template store<I, L>(fout + (size_t)I * a.N + n.site, da, hshift);
+          Storage<S>::template store<I, L>(fout + a.QN + (size_t)I * a.N + n.site, db, hshift);
+        }
       });
+      if constexpr (TOT) {
+        // recolouring scalars of this site for the next pull
+        const R bs = coef * inv_gn;
+        __builtin_nontemporal_store((float)fa_frac, scout + n.site);
+        __builtin_nontemporal_store((float)(bs * gx), scout + a.N + n.site);
+        __builtin_nontemporal_store((float)(bs * gy), scout + 2 * (size_t)a.N + n.site);
+        __builtin_nontemporal_store((float)(bs * gz), scout + 3 * (size_t)a.N + n.site);
+      }
       if constexpr (FIELDS) {
         R* rA = (R*)fo.rho_a;
         R* rB = (R*)fo.rho_b;
@@ -459,6 +629,9 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
       }
     }
     if (more) commit_plane<T>(ring, plane_slot(z + 1 + T::RZ, T::NPL), nxt, tid);
+    if constexpr (TOT) {
+      if (more) commit_scalars<TS>(sring, plane_slot(z + 1 + TS::RZ, TS::NPL), snxt, tid);
+    }
     __syncthreads();
   }
 }

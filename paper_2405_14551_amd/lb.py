@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(PKG, "liblbmi.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENUMERIC, LB_ENODEV, LB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 LATTICE = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
-STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32t": 4, "f16t": 5, "bf16t": 6}
+TOTAL_LAYOUTS = ("f32t", "f16t", "bf16t")
 NC_MODE = {"off": 0, "explicit": 1}
 FIELD_BITS = {"rho_a": 0, "rho_b": 1, "phi": 2, "u": 3, "f_nc": 4, "flags": 5, "labels": 6}
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
@@ -157,7 +158,9 @@ class Simulation:
         self.h = h
         self.real = torch.float64 if storage == "f64" else torch.float32
         self.state_dtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
-                            "bf16": torch.bfloat16}[storage]
+                            "bf16": torch.bfloat16, "f32t": torch.float32, "f16t": torch.float16,
+                            "bf16t": torch.bfloat16}[storage]
+        self.total = storage in TOTAL_LAYOUTS
 
     # -------------------------------------------------------------- lifetime
     def close(self):
@@ -246,15 +249,32 @@ class Simulation:
         return v.value
 
     def get_state(self):
-        """Post-collision populations as a device tensor (2, q, nz, ny, nx) of the storage type."""
+        """Post-collision state on the device.  Per-colour layouts: a tensor
+        (2, q, nz, ny, nx) of the storage type.  Total layouts: a uint8 tensor
+        of the raw bytes (use ``split_total_state``)."""
         nx, ny, nz = self.shape
-        t = self.torch.empty((2, self.q, nz, ny, nx), dtype=self.state_dtype, device=self.device)
+        if self.total:
+            t = self.torch.empty((self.state_bytes(),), dtype=self.torch.uint8, device=self.device)
+        else:
+            t = self.torch.empty((2, self.q, nz, ny, nx), dtype=self.state_dtype, device=self.device)
         check(lib().lb_get_state(self.h, ctypes.c_void_p(t.data_ptr()), self.state_bytes(), 1))
         self.stream.synchronize()
         return t
 
+    def split_total_state(self, raw):
+        """(T (q, nz, ny, nx) in the storage type, scalars (4, nz, ny, nx) float32)
+        views of a total-layout state."""
+        nx, ny, nz = self.shape
+        n = self.q * nx * ny * nz * self.torch.tensor([], dtype=self.state_dtype).element_size()
+        T = raw[:n].view(self.state_dtype).view(self.q, nz, ny, nx)
+        sc = raw[n:].view(self.torch.float32).view(4, nz, ny, nx)
+        return T, sc
+
     def set_state(self, t):
-        t = t.to(device=self.device, dtype=self.state_dtype).contiguous()
+        if self.total:
+            t = t.to(device=self.device).contiguous().view(self.torch.uint8).reshape(-1)
+        else:
+            t = t.to(device=self.device, dtype=self.state_dtype).contiguous()
         if t.numel() * t.element_size() != self.state_bytes():
             raise ValueError("state has the wrong size")
         self.stream.synchronize()

@@ -301,3 +301,98 @@ def test_mass_conservation_gpu():
         assert abs(d1[0] - d0[0]) / d0[0] < tol
         assert abs(d1[1] - d0[1]) / d0[1] < tol
         sim.close()
+
+
+# --------------------------------------------------------------- total layout
+def total_to_colours(sim, raw, rho0=1.0):
+    """Colours of a total-layout state by the layout's definition:
+    f* = T + w rho0, f^A = a f* + (w / |c|) c . b, f^B = f* - f^A."""
+    T, sc = sim.split_total_state(raw)
+    T = T.double().cpu().numpy()
+    sc = sc.double().cpu().numpy()
+    from oracle.lattice import make_lattice
+    L = make_lattice(sim.lattice)
+    q = L.q
+    w = L.w.reshape(q, 1, 1, 1)
+    inv = np.where(L.cnorm > 0, 1.0 / np.where(L.cnorm > 0, L.cnorm, 1.0), 0.0).reshape(q, 1, 1, 1)
+    fstar = T + w * rho0
+    cb = np.einsum("ia,a...->i...", L.c.astype(float), sc[1:4])
+    fA = sc[0][None] * fstar + w * inv * cb
+    return fA, fstar - fA
+
+
+def test_total_layout_init_and_fp32_parity_100_steps():
+    shape = (40, 32, 32)
+    kw = dict(lattice="D3Q27", storage="f32t", nc="explicit", shape=shape, walls=(0, 0, 0),
+              u0=(0.02, 0.0, 0.0), body_force=(1e-6, 0.0, 0.0))
+    cen = np.array([[11.13, 15.77, 16.21], [29.61, 16.19, 15.83]])
+    say("case total-layout f32 parity")
+    sim = lb.Simulation(**kw).init_droplets(cen, [7.5, 7.5])
+    orc = OracleSim(oparams(kw, np.float32)).init_droplets(cen, [7.5, 7.5])
+    fA, fB = total_to_colours(sim, sim.get_state())
+    assert rel(fA, orc.fA) < 1e-7 and rel(fB, orc.fB) < 1e-7
+    sim.step(100)
+    orc.step(100)
+    g = gpu_fields(sim)
+    o = orc.fields()
+    umax = np.abs(o["u"]).max()
+    errs = {k: rel(g[k], o[k]) for k in ("rho_a", "rho_b")}
+    errs["u"] = np.abs(g["u"] - o["u"]).max() / umax
+    fA, fB = total_to_colours(sim, sim.get_state())
+    errs["fA"], errs["fB"] = rel(fA, orc.fA), rel(fB, orc.fB)
+    say(f"  total f32 errors {errs}")
+    for k, e in errs.items():
+        assert e < 1e-5, (k, e)
+    sim.close()
+
+
+def test_total_layout_full_size_sampled_sites():
+    """The channel workload in the FP32 total layout: one GPU step from a
+    developed state against the oracle's windowed step on the colours the
+    layout defines."""
+    w = W.channel_3d(storage="f32t")
+    kw, cen, rad = W.sim_kwargs(w)
+    say("case total-layout channel full size")
+    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    sim.step(30)
+    sA, sB = total_to_colours(sim, sim.get_state())
+    sim.step(1)
+    g = gpu_fields(sim, ("f_nc", "flags"))
+    nA, nB = total_to_colours(sim, sim.get_state())
+    nx, ny, nz = kw["shape"]
+    rng = np.random.default_rng(6)
+    sites = []
+    fnc_sites = np.argwhere(np.abs(g["f_nc"]).sum(0) > 0)
+    assert len(fnc_sites) > 0
+    for j in rng.choice(len(fnc_sites), size=min(16, len(fnc_sites)), replace=False):
+        z, y, x = fnc_sites[j]
+        sites.append((x, y, z))
+    sites += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (63, 3, 7), (64, 4, 8), (200, 1, 1)]
+    for _ in range(8):
+        sites.append((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    p = oparams(kw, np.float32)
+    worst = 0.0
+    for (x, y, z) in sites:
+        a, b, _ = step_window(p, sA, sB, (x, y, z))
+        e = max(np.abs(nA[:, z, y, x] - a).max(), np.abs(nB[:, z, y, x] - b).max()) / np.abs(a + b).max()
+        worst = max(worst, e)
+        assert e < 2e-6, ((x, y, z), e)
+    say(f"  total layout: sampled {len(sites)} sites, worst rel err {worst:.2e}")
+    sim.close()
+
+
+def test_total_layout_checkpoint_roundtrip():
+    w = W.channel_3d(storage="f16t", shape=(64, 40, 32), count=6, radius=6.0)
+    kw, cen, rad = W.sim_kwargs(w)
+    say("case total-layout checkpoint")
+    s1 = lb.Simulation(**kw).init_droplets(cen, rad)
+    s1.step(10)
+    mid = s1.get_state().clone()
+    s1.step(10)
+    end1 = s1.get_state()
+    s2 = lb.Simulation(**kw)
+    s2.set_state(mid)
+    s2.step(10)
+    assert torch.equal(end1, s2.get_state())
+    s1.close()
+    s2.close()
