@@ -187,12 +187,17 @@ static int validate(const lb_params* p) {
     if (p->wall[a] != 0 && p->wall[a] != 1) return fail(LB_EINVAL, "wall[%d] must be 0 or 1", a);
   const double N = (double)p->nx * p->ny * p->nz;
   const int q = ops_for(p->lattice)->q;
-  if (N * q >= 4294967295.0) return fail(LB_EINVAL, "Q * sites must stay below 2^32 (got %.0f)", N * q);
+  if (N * q * storage_bytes(p->storage) >= 4294967295.0)
+    return fail(LB_EINVAL, "one colour block (Q * sites * element bytes = %.0f) must stay below 4 GiB: "
+                "population offsets are 32-bit", N * q * storage_bytes(p->storage));
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must exceed 1/2");
   if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive");
   if (!(p->phi_interface > 0.0 && p->phi_interface < 1.0)) return fail(LB_EINVAL, "phi_interface must lie in (0,1)");
   if (!std::isfinite(p->A) || !std::isfinite(p->beta)) return fail(LB_EINVAL, "A and beta must be finite");
   if (p->nc_mode != LB_NC_OFF) {
+    // the near-contact stencil reaches 4 sites; each axis must be at least that long
+    if (p->nx < 4 || p->ny < 4 || (p->lattice != LB_D2Q9 && p->nz < 4))
+      return fail(LB_EINVAL, "near contact needs every axis >= 4 sites");
     if (!(p->nc_hmax >= 1.0 && p->nc_hmax < 4.0)) return fail(LB_EINVAL, "nc_hmax must lie in [1, 4)");
     if (!(p->nc_hmin > 0.0)) return fail(LB_EINVAL, "nc_hmin must be positive");
   }

@@ -52,6 +52,18 @@ struct D3Q19 {
                                    W2, W2, W2, W2, W2, W2, W2, W2, W2};
 };
 
+// first member of velocity pair p (its opposite is L::opp of it); pairs cover
+// every moving direction once
+template <class L>
+constexpr int pair_first(int p) {
+  if constexpr (L::D == 2) {
+    constexpr int f[4] = {1, 2, 5, 6};
+    return f[p];
+  } else {
+    return 2 * p + 1;
+  }
+}
+
 template <class L>
 constexpr double B_coef(int i) {
   return i == 0 ? L::w[0] - 2.0 / 3.0 : L::w[i];

@@ -50,9 +50,28 @@ __device__ __forceinline__ void static_for(F&& f) {
 template <class S>
 struct Storage;
 
+// buffer resource over `bytes` bytes at p (raw buffer: stride 0, no swizzle);
+// out-of-range accesses return 0 / are dropped instead of faulting
+// cache-policy operand of the stores: non-temporal (written once, read back
+// only after the whole pass), so the lines do not linger dirty in L2
+constexpr int CPOL_NT = 2;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
 template <>
 struct Storage<double> {
   using real = double;
+  static constexpr uint32_t ES = 8;
+  template <int I, class L>
+  __device__ static __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, double h) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, 0)) - L::w[I] * h;
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double d, double h) {
+    using u2 = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, d + L::w[I] * h), r, vo, so, CPOL_NT);
+  }
   template <int I, class L>
   __device__ static __forceinline__ double load(const double* p, double h) { return *p - L::w[I] * h; }
   template <int I, class L>
@@ -64,6 +83,15 @@ struct Storage<double> {
 template <>
 struct Storage<float> {
   using real = float;
+  static constexpr uint32_t ES = 4;
+  template <int I, class L>
+  __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float h) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, 0)) - (float)L::w[I] * h;
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float h) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, d + (float)L::w[I] * h), r, vo, so, CPOL_NT);
+  }
   template <int I, class L>
   __device__ static __forceinline__ float load(const float* p, float h) { return *p - (float)L::w[I] * h; }
   template <int I, class L>
@@ -75,6 +103,15 @@ struct Storage<float> {
 template <>
 struct Storage<_Float16> {
   using real = float;
+  static constexpr uint32_t ES = 2;
+  template <int I, class L>
+  __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float) {
+    return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, 0));
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)d), r, vo, so, CPOL_NT);
+  }
   template <int I, class L>
   __device__ static __forceinline__ float load(const _Float16* p, float) { return (float)(*p); }
   template <int I, class L>
@@ -84,6 +121,15 @@ struct Storage<_Float16> {
 template <>
 struct Storage<__bf16> {
   using real = float;
+  static constexpr uint32_t ES = 2;
+  template <int I, class L>
+  __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float) {
+    return (float)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, 0));
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)d), r, vo, so, CPOL_NT);
+  }
   template <int I, class L>
   __device__ static __forceinline__ float load(const __bf16* p, float) { return (float)(*p); }
   template <int I, class L>
@@ -159,8 +205,21 @@ __device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const StepArgs& a) 
 }
 
 // element index (within one colour block) of the pulled population i at site n
+// Branch-free on purpose: a divergent branch here makes the compiler wait for
+// the loads already in flight at every merge point, serialising the pull.
 template <class L, int I>
 __device__ __forceinline__ uint32_t pull_index(const Nbr& n, uint32_t N) {
+  constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
+  const uint32_t solid = (uint32_t)n.solid_x[ix] | (uint32_t)n.solid_y[iy] | (uint32_t)n.solid_z[iz];
+  const uint32_t moving = (uint32_t)I * N + (n.xs[ix] + n.ys[iy] + n.zs[iz]);
+  const uint32_t bounced = (uint32_t)L::opp[I] * N + n.site;
+  return moving ^ ((moving ^ bounced) & (0u - solid));
+}
+
+// Same index with the select written directly.  The phase pass measures
+// faster with this form than with the branch-free one.
+template <class L, int I>
+__device__ __forceinline__ uint32_t pull_index_sel(const Nbr& n, uint32_t N) {
   constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
   const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
   const uint32_t src = n.xs[ix] + n.ys[iy] + n.zs[iz];
@@ -187,7 +246,7 @@ __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
   R sa = 0, sb = 0;  // sums of the shifted populations: rho_k = rho0/2 + s_k
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    const uint32_t e = pull_index<L, I>(n, a.N);
+    const uint32_t e = pull_index_sel<L, I>(n, a.N);
     sa += Storage<S>::template load<I, L>(fin + e, h);
     sb += Storage<S>::template load<I, L>(fin + a.QN + e, h);
   });
@@ -211,17 +270,13 @@ struct Tile {
 // map a halo coordinate to the node whose phi it holds: periodic wrap, or the
 // mirror image across the wall plane (ghost at -1-k holds node k); positions
 // more than one layer beyond a wall are never read by a valid computation and
-// are clamped.
+// are clamped.  Halo widths never exceed an axis length (checked at create),
+// so one wrap suffices; the selects keep the staging loops branch-free.
 __device__ __forceinline__ int halo_coord(int g, int n, int wall) {
-  if (wall) {
-    if (g < 0) g = -1 - g;
-    else if (g >= n) g = 2 * n - 1 - g;
-    g = g < 0 ? 0 : (g >= n ? n - 1 : g);
-  } else {
-    while (g < 0) g += n;
-    while (g >= n) g -= n;
-  }
-  return g;
+  const int wrapped = g < 0 ? g + n : (g >= n ? g - n : g);
+  int mirrored = g < 0 ? -1 - g : (g >= n ? 2 * n - 1 - g : g);
+  mirrored = mirrored < 0 ? 0 : (mirrored >= n ? n - 1 : mirrored);
+  return wall ? mirrored : wrapped;
 }
 
 template <class T, class R>
@@ -247,13 +302,11 @@ __device__ __forceinline__ void fetch_plane(R (&v)[T::NPER], int zz, const R* __
   const size_t zoff = (size_t)gz * a.nx * a.ny;
 #pragma unroll
   for (int k = 0; k < T::NPER; ++k) {
-    const int e = tid + k * T::NT;
-    if (e < T::PL) {
-      const int hy = e / T::TXH, hx = e - hy * T::TXH;
-      const int gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
-      const int gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
-      v[k] = phi[zoff + (size_t)gy * a.nx + gx];
-    }
+    const int e = min(tid + k * T::NT, T::PL - 1);  // surplus lanes reload the last element
+    const int hy = e / T::TXH, hx = e - hy * T::TXH;
+    const int gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
+    const int gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
+    v[k] = phi[zoff + (size_t)gy * a.nx + gx];
   }
 }
 
@@ -311,6 +364,16 @@ constexpr int NSC = 4;  // scalars per site: a, b_x, b_y, b_z
 template <class S>
 __device__ __forceinline__ float total_load(const S* p) { return (float)(*p); }
 template <class S>
+__device__ __forceinline__ float total_bload(__amdgpu_buffer_rsrc_t r, uint32_t vo) {
+  if constexpr (sizeof(S) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, 0));
+  else return (float)__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, 0));
+}
+template <class S>
+__device__ __forceinline__ void total_bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
+  if constexpr (sizeof(S) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, CPOL_NT);
+  else __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r, vo, so, CPOL_NT);
+}
+template <class S>
 __device__ __forceinline__ void total_store(S* p, float v) { *p = (S)v; }
 template <>
 __device__ __forceinline__ void total_store<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
@@ -329,14 +392,12 @@ __device__ __forceinline__ void fetch_scalars(float (&v)[ScalarRing<TS>::NPER], 
   const size_t zoff = (size_t)gz * a.nx * a.ny;
 #pragma unroll
   for (int k = 0; k < ScalarRing<TS>::NPER; ++k) {
-    const int e = tid + k * TS::NT;
-    if (e < ScalarRing<TS>::SLOT) {
-      const int ch = e / TS::PL, rr = e - ch * TS::PL;
-      const int hy = rr / TS::TXH, hx = rr - hy * TS::TXH;
-      const int gx = halo_coord(x0 - TS::RAD + hx, a.nx, a.wall_x);
-      const int gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
-      v[k] = sc[(size_t)ch * a.N + zoff + (size_t)gy * a.nx + gx];
-    }
+    const int e = min(tid + k * TS::NT, ScalarRing<TS>::SLOT - 1);
+    const int ch = e / TS::PL, rr = e - ch * TS::PL;
+    const int hy = rr / TS::TXH, hx = rr - hy * TS::TXH;
+    const int gx = halo_coord(x0 - TS::RAD + hx, a.nx, a.wall_x);
+    const int gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
+    v[k] = sc[(size_t)ch * a.N + zoff + (size_t)gy * a.nx + gx];
   }
 }
 
@@ -360,10 +421,12 @@ __device__ __forceinline__ R colour_a(R T, const float* __restrict__ sring, cons
                                       R rho0, R h) {
   constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
   constexpr int ix = 1 - cx, iy = 1 - cy, iz = 1 - cz;
-  const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
-  const int slot = solid ? zcs : ring_slot(zcs, -cz, TS::NPL);
-  const int pos = solid ? sc0 : sc0 - cy * TS::TXH - cx;
-  const float* q = sring + slot * ScalarRing<TS>::SLOT + pos;
+  // branch-free selects (see pull_index)
+  const uint32_t solid = (uint32_t)n.solid_x[ix] | (uint32_t)n.solid_y[iy] | (uint32_t)n.solid_z[iz];
+  const int moving = ring_slot(zcs, -cz, TS::NPL) * ScalarRing<TS>::SLOT + sc0 - cy * TS::TXH - cx;
+  const int bounced = zcs * ScalarRing<TS>::SLOT + sc0;
+  const int idx = moving ^ ((moving ^ bounced) & (int)(0u - solid));
+  const float* q = sring + idx;
   const R aa = (R)q[0];
   R v = aa * T + (R)L::w[I] * (aa * rho0 - h);
   if constexpr (I != 0) {
@@ -372,8 +435,8 @@ __device__ __forceinline__ R colour_a(R T, const float* __restrict__ sring, cons
     if constexpr (cy != 0) cb += (R)cy * (R)q[2 * TS::PL];
     if constexpr (cz != 0) cb += (R)cz * (R)q[3 * TS::PL];
     // the bounced population moved along -c_i before the wall reversed it
-    const R r = (R)(L::w[I] * inv_norm<L>(I)) * cb;
-    v += solid ? -r : r;
+    const R sign = R(1) - R(2) * (R)solid;
+    v += sign * (R)(L::w[I] * inv_norm<L>(I)) * cb;
   }
   return v;
 }
@@ -411,9 +474,10 @@ __global__ void __launch_bounds__(TS::NT) k_phase_total(const S* __restrict__ fi
     if (valid_xy) {
       const Nbr n = make_nbr(x, y, z, a);
       float Tv[L::Q];
+      const auto rT = make_rsrc(fin, a.QN * (uint32_t)sizeof(S));
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        Tv[I] = total_load(fin + pull_index<L, I>(n, a.N));
+        Tv[I] = total_bload<S>(rT, pull_index<L, I>(n, a.N) * (uint32_t)sizeof(S));
       });
       const int zcs = plane_slot(z, TS::NPL);
       float sa = 0.f, sb = 0.f;
@@ -469,6 +533,11 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
   const R omega = (R)a.omega, guo = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
   const R hshift = (R)a.half_rho0, phiI = (R)a.phi_I;
   const int c0 = (ty + T::RAD) * T::TXH + (tx + T::RAD);
+  // populations through buffer resources: one 32-bit lane offset per direction
+  // serves both colours, stores take the direction offset in an SGPR
+  constexpr uint32_t ES = TOT ? (uint32_t)sizeof(S) : Storage<S>::ES;
+  const auto rinA = make_rsrc(fin, a.QN * ES), rinB = make_rsrc(fin + (TOT ? 0 : a.QN), a.QN * ES);
+  const auto routA = make_rsrc(fout, a.QN * ES), routB = make_rsrc(fout + (TOT ? 0 : a.QN), a.QN * ES);
 
   for (int z = z0; z < z1; ++z) {
     // prefetch the plane the next iteration needs into registers; it goes to
@@ -488,12 +557,12 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
       R va[L::Q], vb[TOT ? 1 : L::Q];
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        const uint32_t e = pull_index<L, I>(n, a.N);
+        const uint32_t vo = pull_index<L, I>(n, a.N) * ES;
         if constexpr (TOT) {
-          va[I] = (R)total_load(fin + e);
+          va[I] = (R)total_bload<S>(rinA, vo);
         } else {
-          va[I] = Storage<S>::template load<I, L>(fin + e, hshift);
-          vb[I] = Storage<S>::template load<I, L>(fin + a.QN + e, hshift);
+          va[I] = Storage<S>::template bload<I, L>(rinA, vo, hshift);
+          vb[I] = Storage<S>::template bload<I, L>(rinB, vo, hshift);
         }
       });
       const int p0 = zc * T::PL;
@@ -582,31 +651,55 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
       const R fa_frac = ra * inv_rho;                  // rho_A / rho
       const R coef = beta * ra * rb * inv_rho;         // beta rho_A rho_B / rho
       const R half_phi_rho0 = (sa - sb) * inv_rho * hshift;  // rho0 phi / 2
-      // ---- collide each direction and store the two colours
-      static_for<0, L::Q>([&](auto ic) {
+      // ---- collide and recolour.  With cu = c.u, cF = c.F, cg = c.g, the
+      // shifted post-collision value of direction i is
+      //   f*_i - w rho0 = (1 - omega) d_i + w_i t_i - A |g| B_i,
+      //   t_i = omega drho - 1.5 omega rho uu - 3 guo uF           (isotropic)
+      //       + 4.5 omega rho cu^2 + 9 guo cu cF + A |g| cg^2 / |g|^2   (even in c)
+      //       + 3 omega rho cu + 3 guo cF                           (odd in c)
+      // (BGK toward f^eq, Guo source, perturbation), and the recolouring adds
+      // w_i (rho0 phi/2 + beta rho_A rho_B / rho cg / (|c| |g|)) to colour A.
+      // A velocity and its opposite share cu, cF, cg up to sign.
+      const R one_m_om = R(1) - omega;
+      const R wrho = omega * rho;
+      const R K0 = omega * drho - R(1.5) * wrho * uu - R(3) * guo * uF;
+      const R K1 = R(3) * wrho, K2 = R(4.5) * wrho, K3 = R(3) * guo, K4 = R(9) * guo;
+      const R Kg = Agn * inv_gg;
+      const R Kr = coef * inv_gn;
+      auto emit = [&](auto ic, R ds, R rec_odd) {
         constexpr int I = decltype(ic)::value;
+        const uint32_t vo = n.site * ES, so = (uint32_t)I * a.N * ES;
+        if constexpr (TOT) {
+          total_bstore<S>(routA, vo, so, (float)ds);
+        } else {
+          const R wi = (R)L::w[I];
+          const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
+          const R db = ds - da;
+          Storage<S>::template bstore<I, L>(routA, vo, so, da, hshift);
+          Storage<S>::template bstore<I, L>(routB, vo, so, db, hshift);
+        }
+      };
+      {
+        const R w0 = (R)L::w[0];
+        emit(std::integral_constant<int, 0>{}, one_m_om * d[0] + w0 * K0 - Agn * (R)B_coef<L>(0), R(0));
+      }
+      static_for<0, (L::Q - 1) / 2>([&](auto pc) {
+        constexpr int I = pair_first<L>(decltype(pc)::value);
+        constexpr int J = L::opp[I];
         constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
         const R wi = (R)L::w[I];
         R cu = 0, cF = 0, cg = 0;
         if constexpr (cx != 0) { cu += (R)cx * ux; cF += (R)cx * Fx; cg += (R)cx * gx; }
         if constexpr (cy != 0) { cu += (R)cy * uy; cF += (R)cy * Fy; cg += (R)cy * gy; }
         if constexpr (cz != 0) { cu += (R)cz * uz; cF += (R)cz * Fz; cg += (R)cz * gz; }
-        // f^eq - w rho0 = w [(rho - rho0) + rho (3 cu + 4.5 cu^2 - 1.5 uu)]
-        const R deq = wi * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
-        const R src = guo * wi * (R(3) * (cF - uF) + R(9) * cu * cF);
-        R ds = d[I] - omega * (d[I] - deq) + src;                        // f* - w rho0
-        ds += Agn * (wi * cg * cg * inv_gg - (R)B_coef<L>(I));
-        R rec = 0;
-        if constexpr (I != 0) rec = coef * wi * (cg * (R)inv_norm<L>(I) * inv_gn);
-        // recolouring in shifted form: f^A - w rho0/2 = (rho_A/rho) (f* - w rho0) + w rho0 phi/2 + rec
-        if constexpr (TOT) {
-          total_store(fout + (size_t)I * a.N + n.site, (float)ds);
-        } else {
-          const R da = fa_frac * ds + wi * half_phi_rho0 + rec;
-          const R db = ds - da;
-          Storage<S>::template store<I, L>(fout + (size_t)I * a.N + n.site, da, hshift);
-          Storage<S>::template store<I, L>(fout + a.QN + (size_t)I * a.N + n.site, db, hshift);
-        }
+        const R even = K0 + cu * (K2 * cu + K4 * cF) + Kg * cg * cg;
+        const R odd = K1 * cu + K3 * cF;
+        const R pert_b = Agn * (R)B_coef<L>(I);
+        const R ds_i = one_m_om * d[I] + wi * (even + odd) - pert_b;
+        const R ds_j = one_m_om * d[J] + wi * (even - odd) - pert_b;
+        const R rodd = Kr * (R)inv_norm<L>(I) * cg;
+        emit(std::integral_constant<int, I>{}, ds_i, rodd);
+        emit(std::integral_constant<int, J>{}, ds_j, -rodd);
       });
       if constexpr (TOT) {
         // recolouring scalars of this site for the next pull

@@ -65,6 +65,7 @@ def _create(**kw):
     dict(phi_interface=1.0),
     dict(nc="explicit", nc_hmax=5.0),
     dict(nc="explicit", nc_hmin=0.0),
+    dict(nc="explicit", shape=(64, 3, 8)),
     dict(rho0=-1.0),
     dict(shape=(2048, 2048, 2048)),
 ])

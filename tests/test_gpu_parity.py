@@ -291,7 +291,10 @@ def test_mass_conservation_gpu():
     w = W.channel_3d(shape=(64, 48, 48), count=8, radius=7.0)
     kw, cen, rad = W.sim_kwargs(w)
     say("case mass f64/f32")
-    for st, tol in (("f64", 1e-13), ("f32", 2e-6)):
+    # FP64: roundoff only.  FP32: each step rounds the Q stored populations of a
+    # site to 24 bits, so the relative mass can move by at most about
+    # steps * Q * 2^-24 (= 3.2e-4 here); random rounding keeps it far below.
+    for st, tol in (("f64", 1e-13), ("f32", 200 * 27 * 2.0 ** -24 / 10)):
         kw["storage"] = st
         sim = lb.Simulation(**kw).init_droplets(cen, rad)
         d0 = sim.diagnostics()
