@@ -111,17 +111,39 @@ typedef struct lb_params {
 
 typedef struct lb_handle lb_handle;
 
+/* Launch configuration of an ensemble step (n_channels > 1).
+ *  mode          LB_ENSEMBLE_BATCHED: two launches per step over all channels
+ *                (every channel's phase tiles, then every channel's collision
+ *                tiles; one tile per workgroup).
+ *                LB_ENSEMBLE_PER_CHANNEL: the single-lattice phase and
+ *                collision launches, channel after channel.
+ *  z_per_block   z-planes per collision tile (>= 1)
+ *  use_graph     1: replay non-field steps from a captured hipGraph of two steps
+ *  ms_per_step   filled by lb_autotune with the measured time of the choice */
+enum { LB_ENSEMBLE_BATCHED = 0, LB_ENSEMBLE_PER_CHANNEL = 1 };
+typedef struct lb_tuning {
+  int mode;
+  int z_per_block;
+  int use_graph;
+  int reserved;           /* 0 */
+  double ms_per_step;
+} lb_tuning;
+
 /* Fill *p with defaults: D3Q27, FP32, nc off, 64^3 periodic, tau 1, A 0.01,
  * beta 0.7, rho0 1, no force, u0 = 0, nc_A 0.02, hmin 2, hmax 3, phi_I 0.9. */
 void lb_params_default(lb_params* p);
 
-/* Create a simulation.  p points at n_channels parameter sets; this build
- * accepts n_channels == 1.  hip_stream is a hipStream_t (NULL allowed).
- * Allocates two copies of the state (see lb_state_bytes) plus the fields.
+/* Create a simulation.  p points at n_channels parameter sets (1 .. 2048).
+ * With n_channels > 1 the handle is an ensemble of independent lattices
+ * ("channels") with their own sizes, walls, tau, forces and droplets, advanced
+ * together by batched launches (lb_tuning); lattice, storage and nc_mode must
+ * agree across channels and the storage must be LB_F64, LB_F32 or a total
+ * layout.  hip_stream is a hipStream_t (NULL allowed).  Allocates two copies of
+ * the state (see lb_state_bytes) plus the fields, per channel.
  * Errors: LB_EINVAL, LB_ENOMEM, LB_ENODEV, LB_EHIP.  *out is NULL on error. */
 int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** out);
 
-/* Initialise channel `channel` with n droplets of the phase phi_in (+1: the
+/* Initialise channel `channel` (0 .. n_channels-1) with n droplets of the phase phi_in (+1: the
  * droplets are fluid A):
  *   phi(x) = phi_in * max_d tanh(2 (R_d - |x - c_d|) / width)
  * with minimum-image distances along periodic axes (2D ignores z), then
@@ -155,7 +177,8 @@ int lb_diagnostics(lb_handle* h, int channel, double out[8]);
 
 /* Size in bytes of the raw state: per-colour layouts 2 * Q * N storage
  * elements f[k][i][s]; total layouts Q * N storage elements T[i][s] followed by
- * 4 * N floats (a, b_x, b_y, b_z as [4][s]). */
+ * 4 * N floats (a, b_x, b_y, b_z as [4][s]).  An ensemble's state is its
+ * channels' states concatenated in channel order. */
 int lb_state_bytes(const lb_handle* h, size_t* bytes);
 /* Copy the current post-collision state out / in, in the layout above (16-bit
  * modes hold the shifted values).  Host buffers when *_on_device == 0
@@ -177,6 +200,21 @@ int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_ph
 
 /* Block until all work of the handle is done. */
 int lb_sync(lb_handle* h);
+
+/* Number of channels (1 for a single lattice). */
+int lb_channel_count(const lb_handle* h, int* n);
+
+/* Current / new ensemble launch configuration (single-lattice handles use
+ * only z_per_block).  lb_set_tuning validates and rebuilds the work lists. */
+int lb_get_tuning(const lb_handle* h, lb_tuning* t);
+int lb_set_tuning(lb_handle* h, const lb_tuning* t);
+
+/* Measure each candidate configuration for `steps` steps (hipEvents on the
+ * handle's stream), keep the fastest and write it to *best.  results, if not
+ * NULL, receives up to cap rows of {mode, z_per_block, use_graph, ms} as
+ * doubles; *n_results the number of candidates.  The timed steps advance the
+ * simulation: tune before lb_init_droplets or re-initialise afterwards. */
+int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int cap, int* n_results);
 
 /* Destroy a handle and free its device memory.  NULL is accepted. */
 int lb_destroy(lb_handle* h);

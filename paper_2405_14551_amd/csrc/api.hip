@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -91,6 +93,17 @@ struct lb_handle {
   bool initialised = false;
   bool fields_valid = false;  // macroscopic fields describe the current state
   int z_per_block = 1;
+  // ensemble of independent channels (n_channels > 1): each channel is a
+  // full single-lattice handle sharing this handle's stream; a batched step
+  // is one phase launch and one collision launch over all channels' tiles
+  std::vector<lb_handle*> chans;
+  ChannelDev* d_chans = nullptr;
+  uint32_t* d_items_ph = nullptr;    // phase tiles of every channel
+  uint32_t* d_items_co = nullptr;    // collision tiles of every channel
+  uint32_t n_items_ph = 0, n_items_co = 0;
+  lb_tuning tune{};                  // ensemble launch configuration
+  hipGraphExec_t graph = nullptr;    // two non-field steps (parity 0 then 1)
+  bool ensemble() const { return !chans.empty(); }
   // per-kernel timing: hipEvent pairs recorded on the handle's stream around
   // each launch while profiling is on
   bool prof_on = false;
@@ -208,16 +221,21 @@ static int validate(const lb_params* p) {
 int lb_destroy(lb_handle* h) {
   if (!h) return LB_OK;
   int dev = 0;
-  hipGetDevice(&dev);
-  hipSetDevice(h->device);
-  if (h->stream) hipStreamSynchronize(h->stream);
-  else hipDeviceSynchronize();
-  for (hipEvent_t e : h->prof_events) hipEventDestroy(e);
+  (void)hipGetDevice(&dev);
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  for (lb_handle* c : h->chans) lb_destroy(c);
+  h->chans.clear();
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  for (void* b : {(void*)h->d_chans, (void*)h->d_items_ph, (void*)h->d_items_co})
+    if (b) (void)hipFree(b);
+  for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
   void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
                   h->diag_partial, h->diag_out, h->ccl_count, h->drops};
   for (void* b : bufs)
-    if (b) hipFree(b);
-  hipSetDevice(dev);
+    if (b) (void)hipFree(b);
+  (void)hipSetDevice(dev);
   delete h;
   return LB_OK;
 }
@@ -233,12 +251,57 @@ static int dev_alloc(void** p, size_t bytes, const char* what) {
   return LB_OK;
 }
 
+static int create_single(const lb_params* p, void* hip_stream, lb_handle** out);
+static int ensemble_plan(lb_handle* h);
+
 int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** out) {
   if (!out) return fail(LB_EINVAL, "out is NULL");
   *out = nullptr;
-  if (n_channels != 1) return fail(LB_EINVAL, "this build takes n_channels == 1 (got %d)", n_channels);
-  int rc = validate(p);
-  if (rc) return rc;
+  if (!p) return fail(LB_EINVAL, "params is NULL");
+  if (n_channels < 1 || n_channels > (int)ITEM_CH_MASK + 1)
+    return fail(LB_EINVAL, "n_channels must lie in [1, %u] (got %d)", ITEM_CH_MASK + 1, n_channels);
+  for (int c = 0; c < n_channels; ++c) {
+    int rc = validate(&p[c]);
+    if (rc) return rc;
+    if (p[c].lattice != p[0].lattice || p[c].storage != p[0].storage || p[c].nc_mode != p[0].nc_mode)
+      return fail(LB_EINVAL, "channel %d: lattice, storage and nc_mode must agree across channels", c);
+  }
+  if (n_channels == 1) return create_single(p, hip_stream, out);
+  if (!ensemble_storage(p[0].storage))
+    return fail(LB_EINVAL, "ensembles take storage LB_F64, LB_F32 or a total layout (got %d)", p[0].storage);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(LB_ENODEV, "no HIP device");
+  }
+  lb_handle* h = new lb_handle();
+  h->p = p[0];
+  h->ops = ops_for(p[0].lattice);
+  h->q = h->ops->q;
+  h->d = h->ops->d;
+  h->esize = storage_bytes(p[0].storage);
+  h->rsize = p[0].storage == LB_F64 ? 8 : 4;
+  h->total = total_layout(p[0].storage);
+  h->stream = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&h->device);
+  for (int c = 0; c < n_channels; ++c) {
+    lb_handle* sub = nullptr;
+    int rc = create_single(&p[c], hip_stream, &sub);
+    if (rc) { lb_destroy(h); return rc; }
+    h->chans.push_back(sub);
+    h->N += sub->N;
+  }
+  h->tune.mode = LB_ENSEMBLE_BATCHED;
+  h->tune.z_per_block = 4;
+  h->tune.use_graph = 1;
+  int rc = ensemble_plan(h);
+  if (rc) { lb_destroy(h); return rc; }
+  *out = h;
+  g_err.clear();
+  return LB_OK;
+}
+
+static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
     (void)hipGetLastError();
@@ -254,7 +317,7 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
   h->rsize = p->storage == LB_F64 ? 8 : 4;
   h->total = total_layout(p->storage);
   h->stream = (hipStream_t)hip_stream;
-  hipGetDevice(&h->device);
+  (void)hipGetDevice(&h->device);
   // pass-2 blocks march through z; aim for about 2048 blocks in flight
   {
     const long bxy = (long)((p->nx + TILE_X - 1) / TILE_X) * ((p->ny + TILE_Y - 1) / TILE_Y);
@@ -300,6 +363,15 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
 int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, const double* radii, double width,
                      double phi_in) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (h->ensemble()) {
+    if (channel < 0 || channel >= (int)h->chans.size()) return fail(LB_EINVAL, "channel %d out of range", channel);
+    int rc = lb_init_droplets(h->chans[channel], 0, n, centres, radii, width, phi_in);
+    if (rc) return rc;
+    h->t = 0;
+    h->initialised = true;
+    for (lb_handle* c : h->chans) h->initialised = h->initialised && c->initialised;
+    return LB_OK;
+  }
   if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
   if (n < 0 || (n > 0 && (!centres || !radii))) return fail(LB_EINVAL, "bad droplet list");
   if (!(width > 0.0)) return fail(LB_EINVAL, "width must be positive");
@@ -312,7 +384,7 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
         !std::isfinite(centres[3 * d + 2]))
       return fail(LB_EINVAL, "droplet %d has a bad centre or radius", d);
   }
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   if (n > h->drops_cap) {
     if (h->drops) HIP_TRY(hipFree(h->drops));
     h->drops = nullptr;
@@ -331,8 +403,8 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
   a.u0x = h->p.u0[0]; a.u0y = h->p.u0[1]; a.u0z = h->d == 3 ? h->p.u0[2] : 0.0;
   a.half_rho0 = 0.5 * h->p.rho0;
   a.phi_I = h->p.phi_interface;
-  h->cur = 0;
-  HIP_TRY(h->ops->init(h->p.storage, h->f[0], h->sc[0], h->phi, h->field_ptrs(), h->drops, a, h->stream));
+  // the state goes into the current copy, so an ensemble keeps one parity
+  HIP_TRY(h->ops->init(h->p.storage, h->f[h->cur], h->sc[h->cur], h->phi, h->field_ptrs(), h->drops, a, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));  // the host droplet list goes out of scope
   h->t = 0;
   h->initialised = true;
@@ -381,11 +453,169 @@ static int run_diag(lb_handle* h) {
   return LB_OK;
 }
 
+// ---------------------------------------------------------------- ensembles
+// channel table and work lists for the current tuning
+static int ensemble_plan(lb_handle* h) {
+  const int nch = (int)h->chans.size();
+  const int zb = h->tune.z_per_block;
+  std::vector<ChannelDev> tab(nch);
+  std::vector<uint32_t> tiles(nch);
+  for (int c = 0; c < nch; ++c) {
+    lb_handle* s = h->chans[c];
+    s->z_per_block = zb;  // also the per-channel launches' tiling
+    ChannelDev& d = tab[c];
+    std::memset(&d, 0, sizeof d);
+    d.a = s->step_args();
+    d.a.tiles_x = (s->p.nx + TILE_X - 1) / TILE_X;
+    d.a.tiles_y = (s->p.ny + TILE_Y - 1) / TILE_Y;
+    const uint32_t nzb = (uint32_t)((s->p.nz + zb - 1) / zb);
+    d.ntiles = (uint32_t)d.a.tiles_x * d.a.tiles_y * nzb;
+    if (d.ntiles > ITEM_TILE_MASK + 1) return fail(LB_EINVAL, "channel %d has too many tiles (%u)", c, d.ntiles);
+    d.f[0] = s->f[0];
+    d.f[1] = s->f[1];
+    d.sc[0] = s->sc[0];
+    d.sc[1] = s->sc[1];
+    d.phi = s->phi;
+    d.fo = s->field_ptrs();
+    tiles[c] = d.ntiles;
+  }
+  // largest channels first, so that the small ones fill the tail of a launch
+  std::vector<int> order(nch);
+  for (int c = 0; c < nch; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return tiles[a] > tiles[b]; });
+  std::vector<uint32_t> ph, co;
+  for (int k = 0; k < nch; ++k) {
+    const uint32_t c = (uint32_t)order[k];
+    for (uint32_t t = 0; t < tiles[c]; ++t) {
+      ph.push_back((c << ITEM_CH_SHIFT) | t);
+      co.push_back(ITEM_COLLIDE | (c << ITEM_CH_SHIFT) | t);
+    }
+  }
+  (void)hipSetDevice(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (void** b : {(void**)&h->d_chans, (void**)&h->d_items_ph, (void**)&h->d_items_co})
+    if (*b) {
+      HIP_TRY(hipFree(*b));
+      *b = nullptr;
+    }
+  if (h->graph) {
+    HIP_TRY(hipGraphExecDestroy(h->graph));
+    h->graph = nullptr;
+  }
+  int rc = 0;
+  if ((rc = dev_alloc((void**)&h->d_chans, sizeof(ChannelDev) * nch, "channel table"))) return rc;
+  if ((rc = dev_alloc((void**)&h->d_items_ph, sizeof(uint32_t) * ph.size(), "work list"))) return rc;
+  if ((rc = dev_alloc((void**)&h->d_items_co, sizeof(uint32_t) * co.size(), "work list"))) return rc;
+  HIP_TRY(hipMemcpy(h->d_chans, tab.data(), sizeof(ChannelDev) * nch, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_items_ph, ph.data(), sizeof(uint32_t) * ph.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_items_co, co.data(), sizeof(uint32_t) * co.size(), hipMemcpyHostToDevice));
+  h->n_items_ph = (uint32_t)ph.size();
+  h->n_items_co = (uint32_t)co.size();
+  return LB_OK;
+}
+
+// enqueue one ensemble step with the given parity on stream s
+static int ensemble_launch(lb_handle* h, bool fields, int parity, hipStream_t s) {
+  const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
+  if (h->tune.mode == LB_ENSEMBLE_BATCHED) {
+    HIP_TRY(h->ops->ensemble(h->p.storage, nc, fields, h->d_chans, h->d_items_ph, h->n_items_ph, parity, s));
+    HIP_TRY(h->ops->ensemble(h->p.storage, nc, fields, h->d_chans, h->d_items_co, h->n_items_co, parity, s));
+    return LB_OK;
+  }
+  for (lb_handle* c : h->chans) {
+    const StepArgs a = c->step_args();
+    HIP_TRY(h->ops->phase(h->p.storage, c->f[parity], c->sc[parity], c->phi, a, s));
+  }
+  for (lb_handle* c : h->chans) {
+    const StepArgs a = c->step_args();
+    HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[parity],
+                            c->sc[1 - parity], c->phi, c->field_ptrs(), a, s));
+  }
+  return LB_OK;
+}
+
+// capture two non-field steps (parity 0, then 1) into a graph
+static int ensemble_graph(lb_handle* h) {
+  if (h->graph) return LB_OK;
+  hipStream_t cap = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  int rc = LB_OK;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = fail(LB_EHIP, "hipStreamBeginCapture failed");
+  } else {
+    const int r0 = ensemble_launch(h, false, 0, cap);
+    const int r1 = r0 ? r0 : ensemble_launch(h, false, 1, cap);
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    if (r1) rc = r1;
+    else if (e != hipSuccess || !g) rc = fail(LB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    else if (hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0) != hipSuccess)
+      rc = fail(LB_EHIP, "hipGraphInstantiate failed");
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
+  if (rc) h->graph = nullptr;
+  return rc;
+}
+
+static void ensemble_advance(lb_handle* h, bool fields) {
+  h->cur = 1 - h->cur;
+  h->t += 1;
+  for (lb_handle* c : h->chans) {
+    c->cur = h->cur;
+    c->t += 1;
+    if (fields) c->fields_valid = true;
+  }
+}
+
+static int ensemble_step(lb_handle* h, int nsteps) {
+  for (lb_handle* c : h->chans)
+    if (!c->initialised) return fail(LB_EINVAL, "every channel must be initialised before stepping");
+  int s = 0;
+  while (s < nsteps) {
+    const bool diag_on = h->p.diag_every > 0;
+    const bool diag_now = diag_on && ((h->t + 1) % h->p.diag_every) == 0;
+    const bool fields = (s == nsteps - 1) || diag_now;
+    // two non-field steps from the captured graph when the parity lines up
+    if (!fields && !diag_on && h->tune.use_graph && h->cur == 0 && s + 2 <= nsteps - 1 && !h->prof_on) {
+      int rc = ensemble_graph(h);
+      if (rc) return rc;
+      HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+      ensemble_advance(h, false);
+      ensemble_advance(h, false);
+      s += 2;
+      continue;
+    }
+    int rc = prof_mark(h, 1, true);
+    if (rc) return rc;
+    if ((rc = ensemble_launch(h, fields, h->cur, h->stream))) return rc;
+    if ((rc = prof_mark(h, 1, false))) return rc;
+    ensemble_advance(h, fields);
+    s += 1;
+    if (diag_now) {
+      for (size_t c = 0; c < h->chans.size(); ++c) {
+        lb_handle* ch = h->chans[c];
+        if ((rc = run_diag(ch))) return rc;
+        double bad = 0.0;
+        HIP_TRY(hipMemcpyAsync(&bad, ch->diag_out + DG_BAD, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (bad > 0.0)
+          return fail(LB_ENUMERIC, "watchdog at step %lld, channel %zu: %.0f bad sites", h->t, c, bad);
+      }
+    }
+  }
+  return LB_OK;
+}
+
 int lb_step(lb_handle* h, int nsteps) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  if (h->ensemble()) {
+    (void)hipSetDevice(h->device);
+    return ensemble_step(h, nsteps);
+  }
   if (!h->initialised) return fail(LB_EINVAL, "call lb_init_droplets or lb_set_state first");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   const StepArgs a = h->step_args();
   const FieldPtrs fo = h->field_ptrs();
   const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
@@ -443,6 +673,10 @@ static int run_labels(lb_handle* h, unsigned int* count_host) {
 
 int lb_fields(lb_handle* h, int channel, unsigned mask, void* const* dst, int dst_on_device) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
+  if (h->ensemble()) {
+    if (channel < 0 || channel >= (int)h->chans.size()) return fail(LB_EINVAL, "channel %d out of range", channel);
+    return lb_fields(h->chans[channel], 0, mask, dst, dst_on_device);
+  }
   if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
   if (mask >> LB_NUM_FIELDS) return fail(LB_EINVAL, "unknown field bits in mask 0x%x", mask);
   if (mask && !dst) return fail(LB_EINVAL, "dst is NULL");
@@ -450,7 +684,7 @@ int lb_fields(lb_handle* h, int channel, unsigned mask, void* const* dst, int ds
   for (int b = 0; b < LB_NUM_FIELDS; ++b)
     if ((mask >> b) & 1u)
       if (!dst[b]) return fail(LB_EINVAL, "dst[%d] is NULL for a selected field", b);
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   const size_t N = h->N, r = h->rsize;
   const void* src[LB_NUM_FIELDS] = {h->rho_a, h->rho_b, h->phi, h->u, h->fnc, h->flags, h->labels};
   const size_t bytes[LB_NUM_FIELDS] = {N * r, N * r, N * r, 3 * N * r, 3 * N * r, N, 4 * N};
@@ -467,9 +701,13 @@ int lb_fields(lb_handle* h, int channel, unsigned mask, void* const* dst, int ds
 
 int lb_diagnostics(lb_handle* h, int channel, double out[8]) {
   if (!h || !out) return fail(LB_EINVAL, "NULL argument");
+  if (h->ensemble()) {
+    if (channel < 0 || channel >= (int)h->chans.size()) return fail(LB_EINVAL, "channel %d out of range", channel);
+    return lb_diagnostics(h->chans[channel], 0, out);
+  }
   if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
   if (!h->fields_valid) return fail(LB_EINVAL, "no fields yet: initialise or take a step after lb_set_state");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   int rc = run_diag(h);
   if (rc) return rc;
   double d[DG_COUNT];
@@ -491,6 +729,12 @@ int lb_diagnostics(lb_handle* h, int channel, double out[8]) {
 }
 
 static size_t state_size(const lb_handle* h, size_t* pop_bytes) {
+  if (h->ensemble()) {
+    size_t tot = 0;
+    for (const lb_handle* c : h->chans) tot += state_size(c, nullptr);
+    if (pop_bytes) *pop_bytes = 0;
+    return tot;
+  }
   const size_t pop = (h->total ? 1ull : 2ull) * h->q * h->N * h->esize;
   if (pop_bytes) *pop_bytes = pop;
   return pop + (h->total ? sizeof(float) * NSC * h->N : 0);
@@ -507,7 +751,17 @@ int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device) {
   size_t pop = 0;
   const size_t need = state_size(h, &pop);
   if (bytes != need) return fail(LB_EINVAL, "state is %zu bytes, got %zu", need, bytes);
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
+  if (h->ensemble()) {
+    size_t off = 0;
+    for (lb_handle* c : h->chans) {
+      const size_t b = state_size(c, nullptr);
+      int rc = lb_get_state(c, (char*)dst + off, b, dst_on_device);
+      if (rc) return rc;
+      off += b;
+    }
+    return LB_OK;
+  }
   const hipMemcpyKind k = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   HIP_TRY(hipMemcpyAsync(dst, h->f[h->cur], pop, k, h->stream));
   if (h->total) HIP_TRY(hipMemcpyAsync((char*)dst + pop, h->sc[h->cur], need - pop, k, h->stream));
@@ -520,7 +774,18 @@ int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device)
   size_t pop = 0;
   const size_t need = state_size(h, &pop);
   if (bytes != need) return fail(LB_EINVAL, "state is %zu bytes, got %zu", need, bytes);
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
+  if (h->ensemble()) {
+    size_t off = 0;
+    for (lb_handle* c : h->chans) {
+      const size_t b = state_size(c, nullptr);
+      int rc = lb_set_state(c, (const char*)src + off, b, src_on_device);
+      if (rc) return rc;
+      off += b;
+    }
+    h->initialised = true;
+    return LB_OK;
+  }
   const hipMemcpyKind k = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIP_TRY(hipMemcpyAsync(h->f[h->cur], src, pop, k, h->stream));
   if (h->total) HIP_TRY(hipMemcpyAsync(h->sc[h->cur], (const char*)src + pop, need - pop, k, h->stream));
@@ -545,7 +810,7 @@ int lb_profile_begin(lb_handle* h) {
 
 int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_phase, int* n_collide) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   HIP_TRY(hipStreamSynchronize(h->stream));
   double t[2] = {0.0, 0.0};
   int n[2] = {0, 0};
@@ -566,8 +831,111 @@ int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_ph
 
 int lb_sync(lb_handle* h) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   HIP_TRY(hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+int lb_channel_count(const lb_handle* h, int* n) {
+  if (!h || !n) return fail(LB_EINVAL, "NULL argument");
+  *n = h->ensemble() ? (int)h->chans.size() : 1;
+  return LB_OK;
+}
+
+int lb_get_tuning(const lb_handle* h, lb_tuning* t) {
+  if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+  if (h->ensemble()) {
+    *t = h->tune;
+  } else {
+    std::memset(t, 0, sizeof *t);
+    t->z_per_block = h->z_per_block;
+  }
+  return LB_OK;
+}
+
+int lb_set_tuning(lb_handle* h, const lb_tuning* t) {
+  if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+  if (t->z_per_block < 1 || t->z_per_block > 4096) return fail(LB_EINVAL, "z_per_block must lie in [1, 4096]");
+  if (!h->ensemble()) {
+    h->z_per_block = t->z_per_block;
+    return LB_OK;
+  }
+  if (t->mode != LB_ENSEMBLE_BATCHED && t->mode != LB_ENSEMBLE_PER_CHANNEL) return fail(LB_EINVAL, "unknown mode");
+  if (t->use_graph != 0 && t->use_graph != 1) return fail(LB_EINVAL, "use_graph must be 0 or 1");
+  const int zb_old = h->tune.z_per_block;
+  h->tune = *t;
+  h->tune.ms_per_step = 0.0;
+  (void)hipSetDevice(h->device);
+  if (zb_old != t->z_per_block || !h->d_items_ph) return ensemble_plan(h);
+  if (h->graph) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipGraphExecDestroy(h->graph));
+    h->graph = nullptr;
+  }
+  return LB_OK;
+}
+
+int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int cap, int* n_results) {
+  if (!h || !best) return fail(LB_EINVAL, "NULL argument");
+  if (steps < 1) return fail(LB_EINVAL, "steps must be >= 1");
+  if (!h->initialised && !h->ensemble()) return fail(LB_EINVAL, "initialise the state first");
+  (void)hipSetDevice(h->device);
+  std::vector<lb_tuning> cand;
+  if (h->ensemble()) {
+    for (int mode : {LB_ENSEMBLE_BATCHED, LB_ENSEMBLE_PER_CHANNEL})
+      for (int zb : {1, 2, 4, 8, 16})
+        for (int graph : {0, 1}) {
+          lb_tuning t{};
+          t.mode = mode;
+          t.z_per_block = zb;
+          t.use_graph = graph;
+          cand.push_back(t);
+        }
+  } else {
+    for (int zb : {1, 2, 4, 8, 16})
+      if (zb <= h->p.nz) {
+        lb_tuning t{};
+        t.z_per_block = zb;
+        cand.push_back(t);
+      }
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best_k = -1;
+  double best_ms = 1e300;
+  int rc = LB_OK;
+  for (size_t k = 0; k < cand.size() && !rc; ++k) {
+    if ((rc = lb_set_tuning(h, &cand[k]))) break;
+    if ((rc = lb_step(h, 2))) break;  // warm-up (and graph capture)
+    if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = fail(LB_EHIP, "hipEventRecord"); break; }
+    if ((rc = lb_step(h, steps))) break;
+    if (hipEventRecord(e1, h->stream) != hipSuccess) { rc = fail(LB_EHIP, "hipEventRecord"); break; }
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(LB_EHIP, "hipEventSynchronize"); break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = ms / steps;
+    cand[k].ms_per_step = per;
+    if (results && (int)k < cap) {
+      results[4 * k + 0] = cand[k].mode;
+      results[4 * k + 1] = cand[k].z_per_block;
+      results[4 * k + 2] = cand[k].use_graph;
+      results[4 * k + 3] = per;
+    }
+    if (per < best_ms) {
+      best_ms = per;
+      best_k = (int)k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (n_results) *n_results = (int)cand.size();
+  if (rc) return rc;
+  if (best_k < 0) return fail(LB_EHIP, "no candidate ran");
+  rc = lb_set_tuning(h, &cand[best_k]);
+  if (rc) return rc;
+  *best = cand[best_k];
+  if (h->ensemble()) h->tune.ms_per_step = best_ms;
   return LB_OK;
 }
 

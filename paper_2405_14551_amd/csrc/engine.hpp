@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "aux_kernels.hpp"
+#include "ensemble.hpp"
 
 namespace lbm {
 
@@ -25,7 +26,14 @@ struct LatticeOps {
                         float* scout, const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
   hipError_t (*init)(int storage, void* f, float* sc, void* phi, const FieldPtrs& fo, const double* drops,
                      const InitArgs& a, hipStream_t s);
+  // batched ensemble launch: one workgroup per entry of `items` (storages
+  // ST_F64, ST_F32 and the total layouts)
+  hipError_t (*ensemble)(int storage, bool nc, bool fields, const ChannelDev* chans, const uint32_t* items,
+                         uint32_t nitems, int parity, hipStream_t s);
 };
+
+// storages the ensemble kernel is built for
+inline bool ensemble_storage(int st) { return st == ST_F64 || st == ST_F32 || st >= ST_F32T; }
 
 const LatticeOps* ops_d2q9();
 const LatticeOps* ops_d3q19();

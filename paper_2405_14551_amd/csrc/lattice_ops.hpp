@@ -126,7 +126,42 @@ struct Launch {
     return hipErrorInvalidValue;
   }
 
-  static LatticeOps ops() { return LatticeOps{L::Q, L::D, &phase, &collide, &init}; }
+  template <class S, bool NC, bool FIELDS, bool TOT>
+  static auto ens_kernel() {
+    using T = Tile<TILE_X, TILE_Y, NC ? 4 : 1, L::D>;
+    return &k_ensemble<L, S, T, NC, FIELDS, TOT>;
+  }
+
+  template <class S, bool TOT>
+  static hipError_t ensemble_s(bool nc, bool fields, const ChannelDev* chans, const uint32_t* items, uint32_t nitems,
+                               int parity, hipStream_t s) {
+    dim3 block(TILE_X, TILE_Y, 1), grid(nitems);
+    if (nc) {
+      if (fields) ens_kernel<S, true, true, TOT>()<<<grid, block, 0, s>>>(chans, items, parity);
+      else ens_kernel<S, true, false, TOT>()<<<grid, block, 0, s>>>(chans, items, parity);
+    } else {
+      if (fields) ens_kernel<S, false, true, TOT>()<<<grid, block, 0, s>>>(chans, items, parity);
+      else ens_kernel<S, false, false, TOT>()<<<grid, block, 0, s>>>(chans, items, parity);
+    }
+    return hipGetLastError();
+  }
+
+  static hipError_t ensemble(int st, bool nc, bool fields, const ChannelDev* chans, const uint32_t* items,
+                             uint32_t nitems, int parity, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    switch (st) {
+      case ST_F64: return ensemble_s<double, false>(nc, fields, chans, items, nitems, parity, s);
+      case ST_F32: return ensemble_s<float, false>(nc, fields, chans, items, nitems, parity, s);
+      case ST_F32T: return ensemble_s<float, true>(nc, fields, chans, items, nitems, parity, s);
+      case ST_F16T: return ensemble_s<_Float16, true>(nc, fields, chans, items, nitems, parity, s);
+      case ST_BF16T: return ensemble_s<__bf16, true>(nc, fields, chans, items, nitems, parity, s);
+    }
+    return hipErrorInvalidValue;
+  }
+
+  static LatticeOps ops() {
+    return LatticeOps{L::Q, L::D, &phase, &collide, &init, &ensemble};
+  }
 };
 
 }  // namespace lbm

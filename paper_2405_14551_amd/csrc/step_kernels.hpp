@@ -167,6 +167,23 @@ __device__ __forceinline__ uint32_t xcd_tile_index(uint32_t b, uint32_t nb) {
   return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
 }
 
+// tile t of a lattice cut into TX x TY columns and z-blocks (x fastest)
+struct TileCoord {
+  int x0, y0, z0, z1;
+};
+__device__ __forceinline__ TileCoord tile_coord(uint32_t t, const StepArgs& a, int TX, int TY) {
+  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
+  const int zb = t / txy;
+  const uint32_t r = t - zb * txy;
+  const int tyi = r / a.tiles_x, txi = r - tyi * a.tiles_x;
+  TileCoord c;
+  c.x0 = txi * TX;
+  c.y0 = tyi * TY;
+  c.z0 = zb * a.z_per_block;
+  c.z1 = min(c.z0 + a.z_per_block, a.nz);
+  return c;
+}
+
 struct FieldPtrs {
   void* rho_a;
   void* rho_b;
@@ -444,19 +461,18 @@ __device__ __forceinline__ R colour_a(R T, const float* __restrict__ sring, cons
 // ----------------------------------------------------------------------------
 // pass 1 of the total layout: phase field from reconstructed colours, marching
 // along z with the scalars of the tile plus a one-site halo staged in LDS
+template <class TS>
+struct PhaseTotalSmem {
+  float sring[TS::NPL * ScalarRing<TS>::SLOT];
+};
+
 template <class L, class S, class TS>
-__global__ void __launch_bounds__(TS::NT) k_phase_total(const S* __restrict__ fin, const float* __restrict__ scin,
-                                                        float* __restrict__ phi, StepArgs a) {
-  __shared__ float sring[TS::NPL * ScalarRing<TS>::SLOT];
+__device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, const float* __restrict__ scin,
+                                                 float* __restrict__ phi, const StepArgs& a, const TileCoord& tc,
+                                                 PhaseTotalSmem<TS>& sm) {
+  float* sring = sm.sring;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TS::TX * ty;
-  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
-  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
-  const int zb = t / txy;
-  const uint32_t r = t - zb * txy;
-  const int tyi = r / a.tiles_x, txi = r - tyi * a.tiles_x;
-  const int x0 = txi * TS::TX, y0 = tyi * TS::TY;
-  const int z0 = zb * a.z_per_block;
-  const int z1 = min(z0 + a.z_per_block, a.nz);
+  const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
   const int x = x0 + tx, y = y0 + ty;
   const bool valid_xy = x < a.nx && y < a.ny;
   for (int dz = -TS::RZ; dz <= TS::RZ; ++dz) {
@@ -494,26 +510,61 @@ __global__ void __launch_bounds__(TS::NT) k_phase_total(const S* __restrict__ fi
   }
 }
 
+template <class L, class S, class TS>
+__global__ void __launch_bounds__(TS::NT) k_phase_total(const S* __restrict__ fin, const float* __restrict__ scin,
+                                                        float* __restrict__ phi, StepArgs a) {
+  __shared__ PhaseTotalSmem<TS> sm;
+  const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, TS::TX, TS::TY);
+  phase_total_tile<L, S, TS>(fin, scin, phi, a, tc, sm);
+}
+
+// per-colour phase pass over a TX x TY x (z0..z1) tile, one site per thread
+// and plane (used by the ensemble kernel, which shares one block shape)
+template <class L, class S>
+__device__ __forceinline__ void phase_tile(const S* __restrict__ fin, typename Storage<S>::real* __restrict__ phi,
+                                           const StepArgs& a, const TileCoord& tc, int TX) {
+  using R = typename Storage<S>::real;
+  const int x = tc.x0 + threadIdx.x, y = tc.y0 + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const R h = (R)a.half_rho0;
+  for (int z = tc.z0; z < tc.z1; ++z) {
+    const Nbr n = make_nbr(x, y, z, a);
+    R sa = 0, sb = 0;
+    static_for<0, L::Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      const uint32_t e = pull_index_sel<L, I>(n, a.N);
+      sa += Storage<S>::template load<I, L>(fin + e, h);
+      sb += Storage<S>::template load<I, L>(fin + a.QN + e, h);
+    });
+    phi[n.site] = (sa - sb) / (R(2) * h + (sa + sb));
+  }
+}
+
 // ----------------------------------------------------------------------------
 // pass 2: gradient, flags, near contact, collision, recolouring, store
+// LDS of one collision tile: the phase-field ring and, for the total layout,
+// the scalar ring
+template <class L, class S, class T, bool TOT>
+struct CollideSmem {
+  using R = typename Storage<S>::real;
+  using TS = Tile<T::TX, T::TY, 1, L::D>;
+  R ring[T::NPL * T::PL];
+  float sring[TOT ? TS::NPL * ScalarRing<TS>::SLOT : 1];
+};
+
+// collision pass of one tile (a TX x TY column over planes z0 .. z1-1)
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
-__global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
-                                                    const typename Storage<S>::real* __restrict__ phi,
-                                                    const float* __restrict__ scin, float* __restrict__ scout,
-                                                    FieldPtrs fo, StepArgs a) {
+__device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __restrict__ fout,
+                                             const typename Storage<S>::real* __restrict__ phi,
+                                             const float* __restrict__ scin, float* __restrict__ scout,
+                                             const FieldPtrs& fo, const StepArgs& a, const TileCoord& tc,
+                                             CollideSmem<L, S, T, TOT>& sm) {
   using R = typename Storage<S>::real;
   using TS = Tile<T::TX, T::TY, 1, L::D>;   // scalar ring of the total layout
-  __shared__ R ring[T::NPL * T::PL];
-  __shared__ float sring[TOT ? TS::NPL * ScalarRing<TS>::SLOT : 1];
+  R* ring = sm.ring;
+  float* sring = sm.sring;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + T::TX * ty;
-  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
-  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
-  const int zb = t / txy;
-  const uint32_t r = t - zb * txy;
-  const int tyi = r / a.tiles_x, txi = r - tyi * a.tiles_x;
-  const int x0 = txi * T::TX, y0 = tyi * T::TY;
-  const int z0 = zb * a.z_per_block;
-  const int z1 = min(z0 + a.z_per_block, a.nz);
+  const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
   const int x = x0 + tx, y = y0 + ty;
   const bool valid_xy = x < a.nx && y < a.ny;
 
@@ -727,6 +778,16 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
     }
     __syncthreads();
   }
+}
+
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
+__global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
+                                                    const typename Storage<S>::real* __restrict__ phi,
+                                                    const float* __restrict__ scin, float* __restrict__ scout,
+                                                    FieldPtrs fo, StepArgs a) {
+  __shared__ CollideSmem<L, S, T, TOT> sm;
+  const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
+  collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, phi, scin, scout, fo, a, tc, sm);
 }
 
 }  // namespace lbm

@@ -31,6 +31,15 @@ class LBError(RuntimeError):
         self.code = code
 
 
+class LbTuning(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("z_per_block", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("ms_per_step", ctypes.c_double)]
+
+
+ENSEMBLE_MODE = {"batched": 0, "per_channel": 1}
+ENSEMBLE_MODE_NAME = {v: k for k, v in ENSEMBLE_MODE.items()}
+
+
 class LbParams(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int), ("storage", ctypes.c_int), ("nc_mode", ctypes.c_int),
@@ -51,7 +60,8 @@ EXPORTED = [
     "lb_params_default", "lb_create", "lb_init_droplets", "lb_step", "lb_fields",
     "lb_diagnostics", "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count",
     "lb_sync", "lb_destroy", "lb_lattice_table", "lb_error_string", "lb_last_error",
-    "lb_profile_begin", "lb_profile_end",
+    "lb_profile_begin", "lb_profile_end", "lb_channel_count", "lb_get_tuning", "lb_set_tuning",
+    "lb_autotune",
 ]
 
 
@@ -82,13 +92,18 @@ def lib():
     L.lb_lattice_table.argtypes = [i, P(i), P(i), P(d), P(i), P(d)]
     L.lb_profile_begin.argtypes = [vp]
     L.lb_profile_end.argtypes = [vp, P(d), P(d), P(i), P(i)]
+    L.lb_channel_count.argtypes = [vp, P(i)]
+    L.lb_get_tuning.argtypes = [vp, P(LbTuning)]
+    L.lb_set_tuning.argtypes = [vp, P(LbTuning)]
+    L.lb_autotune.argtypes = [vp, i, P(LbTuning), P(d), i, P(i)]
     L.lb_error_string.argtypes = [i]
     L.lb_error_string.restype = ctypes.c_char_p
     L.lb_last_error.argtypes = []
     L.lb_last_error.restype = ctypes.c_char_p
     for name in ["lb_create", "lb_init_droplets", "lb_step", "lb_fields", "lb_diagnostics",
                  "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count", "lb_sync",
-                 "lb_destroy", "lb_lattice_table", "lb_profile_begin", "lb_profile_end"]:
+                 "lb_destroy", "lb_lattice_table", "lb_profile_begin", "lb_profile_end",
+                 "lb_channel_count", "lb_get_tuning", "lb_set_tuning", "lb_autotune"]:
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -281,3 +296,182 @@ class Simulation:
         check(lib().lb_set_state(self.h, ctypes.c_void_p(t.data_ptr()), self.state_bytes(), 1))
         self.stream.synchronize()
         return self
+
+
+def _tuning_dict(t):
+    return {"mode": ENSEMBLE_MODE_NAME[t.mode], "z_per_block": t.z_per_block, "use_graph": t.use_graph,
+            "ms_per_step": t.ms_per_step}
+
+
+class Ensemble:
+    """Independent lattices ("channels") advanced together by batched
+    launches (one phase and one collision launch over all channels' tiles per
+    step, or the single-lattice launches channel after channel; see
+    ``set_tuning``).  ``channels`` is a list of dicts of per-channel
+    parameters (shape, walls, tau, A, beta, body_force, ...); lattice, storage
+    and nc are shared."""
+
+    def __init__(self, channels, lattice="D3Q19", storage="f32", nc="explicit", stream=None):
+        import torch
+        self.torch = torch
+        self.lattice = lattice
+        self.storage = storage
+        self.q = Q_OF[lattice]
+        self.shapes = [tuple(int(v) for v in c["shape"]) for c in channels]
+        arr = (LbParams * len(channels))()
+        for k, c in enumerate(channels):
+            kw = {key: v for key, v in c.items() if key != "shape"}
+            arr[k] = make_params(lattice, storage, nc, c["shape"], **kw)
+        self._params = arr
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        check(lib().lb_create(arr, len(channels), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.real = torch.float64 if storage == "f64" else torch.float32
+        self.total = storage in TOTAL_LAYOUTS
+
+    @property
+    def n_channels(self):
+        return len(self.shapes)
+
+    @property
+    def sites(self):
+        return sum(a * b * c for a, b, c in self.shapes)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            check(lib().lb_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_droplets(self, channel, centres, radii, width=2.0, phi_in=1.0):
+        c = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
+        r = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().lb_init_droplets(self.h, int(channel), int(r.shape[0]), c.ctypes.data_as(dp),
+                                     r.ctypes.data_as(dp), float(width), float(phi_in)))
+        return self
+
+    def step(self, n=1):
+        check(lib().lb_step(self.h, int(n)))
+        return self
+
+    def sync(self):
+        check(lib().lb_sync(self.h))
+
+    def fields(self, channel, names=("rho_a", "rho_b", "phi", "u", "f_nc", "flags")):
+        torch = self.torch
+        nx, ny, nz = self.shapes[channel]
+        out = {}
+        ptrs = (ctypes.c_void_p * 7)()
+        mask = 0
+        for nm in names:
+            b = FIELD_BITS[nm]
+            if nm in ("u", "f_nc"):
+                t = torch.empty((3, nz, ny, nx), dtype=self.real, device=self.device)
+            elif nm == "flags":
+                t = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
+            elif nm == "labels":
+                t = torch.empty((nz, ny, nx), dtype=torch.int32, device=self.device)
+            else:
+                t = torch.empty((nz, ny, nx), dtype=self.real, device=self.device)
+            out[nm] = t
+            ptrs[b] = t.data_ptr()
+            mask |= 1 << b
+        check(lib().lb_fields(self.h, int(channel), mask, ptrs, 1))
+        self.stream.synchronize()
+        return out
+
+    def diagnostics(self, channel):
+        d = (ctypes.c_double * 8)()
+        check(lib().lb_diagnostics(self.h, int(channel), d))
+        return np.array(d[:])
+
+    def state_bytes(self):
+        v = ctypes.c_size_t()
+        check(lib().lb_state_bytes(self.h, ctypes.byref(v)))
+        return v.value
+
+    def get_state(self):
+        """Raw state bytes (uint8 device tensor): the channels' states in order."""
+        t = self.torch.empty((self.state_bytes(),), dtype=self.torch.uint8, device=self.device)
+        check(lib().lb_get_state(self.h, ctypes.c_void_p(t.data_ptr()), self.state_bytes(), 1))
+        self.stream.synchronize()
+        return t
+
+    def set_state(self, raw):
+        raw = raw.to(device=self.device).contiguous().view(self.torch.uint8).reshape(-1)
+        if raw.numel() != self.state_bytes():
+            raise ValueError("state has the wrong size")
+        self.stream.synchronize()
+        check(lib().lb_set_state(self.h, ctypes.c_void_p(raw.data_ptr()), self.state_bytes(), 1))
+        self.stream.synchronize()
+        return self
+
+    def channel_state(self, raw, channel):
+        """(2, q, nz, ny, nx) view of one channel's per-colour state inside ``raw``."""
+        es = self.torch.tensor([], dtype=self.real).element_size()
+        off = 0
+        for k, (nx, ny, nz) in enumerate(self.shapes):
+            n = 2 * self.q * nx * ny * nz * es
+            if k == channel:
+                return raw[off:off + n].view(self.real).view(2, self.q, nz, ny, nx)
+            off += n
+        raise IndexError(channel)
+
+    def tuning(self):
+        t = LbTuning()
+        check(lib().lb_get_tuning(self.h, ctypes.byref(t)))
+        return _tuning_dict(t)
+
+    def set_tuning(self, mode="batched", z_per_block=4, use_graph=1):
+        t = LbTuning(ENSEMBLE_MODE[mode], int(z_per_block), int(use_graph), 0, 0.0)
+        check(lib().lb_set_tuning(self.h, ctypes.byref(t)))
+        return self
+
+    def autotune(self, steps=4, cache=None):
+        """Time every candidate configuration (the timed steps advance the
+        simulation), keep the fastest and return (best, table).  With ``cache``
+        (a JSON path) the choice is stored there and reused when present."""
+        import json
+        import os
+        key = f"{self.lattice}/{self.storage}/{self.n_channels}ch/{self.sites}sites"
+        if cache and os.path.exists(cache):
+            stored = json.load(open(cache))
+            if key in stored:
+                b = stored[key]["best"]
+                self.set_tuning(b["mode"], b["z_per_block"], b["use_graph"])
+                return b, stored[key]["table"]
+        best = LbTuning()
+        cap = 64
+        res = (ctypes.c_double * (4 * cap))()
+        n = ctypes.c_int()
+        check(lib().lb_autotune(self.h, int(steps), ctypes.byref(best), res, cap, ctypes.byref(n)))
+        table = [{"mode": ENSEMBLE_MODE_NAME[int(res[4 * k])], "z_per_block": int(res[4 * k + 1]),
+                  "use_graph": int(res[4 * k + 2]), "ms_per_step": res[4 * k + 3]}
+                 for k in range(min(n.value, cap))]
+        b = _tuning_dict(best)
+        if cache:
+            stored = json.load(open(cache)) if os.path.exists(cache) else {}
+            stored[key] = {"best": b, "table": table}
+            with open(cache, "w") as fh:
+                json.dump(stored, fh, indent=1)
+        return b, table
+
+    def profile_begin(self):
+        check(lib().lb_profile_begin(self.h))
+
+    def profile_end(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        na, nb = ctypes.c_int(), ctypes.c_int()
+        check(lib().lb_profile_end(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(na),
+                                   ctypes.byref(nb)))
+        return dict(ms_phase=a.value, ms_collide=b.value, n_phase=na.value, n_collide=nb.value)

@@ -143,6 +143,55 @@ def dense_3d(storage="f32", count=2000, radius=8.0):
                 centres=cen, radii=np.full(len(cen), radius))
 
 
+def rsa_centres_radii(shape, walls, radii, seed=SEED, min_gap=3.0, max_tries=4000):
+    """Random sequential addition of droplets with given radii (largest
+    first); a droplet that finds no free spot in max_tries draws is left out,
+    so small boxes may hold fewer droplets than asked for."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = np.asarray(shape, dtype=np.float64)
+    radii = np.sort(np.asarray(radii, dtype=np.float64))[::-1]
+    cen = np.zeros((0, 3))
+    placed = []
+    for R in radii:
+        lo = np.zeros(3)
+        hi = n.copy()
+        for a in range(3):
+            if walls[a]:
+                lo[a] = R + 2.0
+                hi[a] = n[a] - 1 - (R + 2.0)
+        for _ in range(max_tries):
+            c = lo + rng.random(3) * (hi - lo)
+            if cen.shape[0]:
+                d = cen - c
+                for a in range(3):
+                    if not walls[a]:
+                        d[:, a] -= n[a] * np.round(d[:, a] / n[a])
+                if np.any(np.sqrt((d * d).sum(1)) < np.array(placed) + R + min_gap):
+                    continue
+            cen = np.vstack([cen, c])
+            placed.append(R)
+            break
+    return cen, np.array(placed)
+
+
+def ensemble_channels(n=96, seed=SEED, storage="f32"):
+    """Batched ensemble: n independent D3Q19 channels, channel c drawn with
+    seed + c: nx ~ U{64..160}, ny, nz ~ U{64..96}, tau ~ U[0.6, 1.2],
+    4..40 droplets with R ~ U[6, 12] (those that fit); walls y/z, body force
+    1e-6 along x, near contact range 3 / strength 0.02."""
+    chans = []
+    for c in range(n):
+        rng = np.random.Generator(np.random.PCG64(seed + c))
+        shape = (int(rng.integers(64, 161)), int(rng.integers(64, 97)), int(rng.integers(64, 97)))
+        tau = float(rng.uniform(0.6, 1.2))
+        count = int(rng.integers(4, 41))
+        radii = rng.uniform(6.0, 12.0, count)
+        cen, rad = rsa_centres_radii(shape, (0, 1, 1), radii, seed=seed + 1000 + c)
+        chans.append(dict(shape=shape, walls=(0, 1, 1), tau=tau, A=0.01, beta=0.7, body_force=(1e-6, 0.0, 0.0),
+                          nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, centres=cen, radii=rad))
+    return dict(lattice="D3Q19", storage=storage, nc="explicit", channels=chans)
+
+
 def sim_kwargs(w):
     """Split a workload dict into Simulation kwargs and the droplet list."""
     kw = {k: v for k, v in w.items() if k not in ("centres", "radii")}

@@ -98,3 +98,17 @@ def test_valid_params_without_device():
     if torch.cuda.is_available():
         pytest.skip("a device is present")
     assert _create() == lb.LB_ENODEV
+
+
+def test_ensemble_argument_checks():
+    L = lb.lib()
+    h = ctypes.c_void_p()
+    arr = (lb.LbParams * 2)()
+    arr[0] = lb.make_params(lattice="D3Q19", storage="f32", shape=(16, 8, 8))
+    arr[1] = lb.make_params(lattice="D3Q27", storage="f32", shape=(16, 8, 8))
+    assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # lattices differ
+    arr[1] = lb.make_params(lattice="D3Q19", storage="f16", shape=(16, 8, 8))
+    assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # storages differ
+    arr[0] = lb.make_params(lattice="D3Q19", storage="f16", shape=(16, 8, 8))
+    assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # per-colour 16-bit ensemble
+    assert L.lb_create(arr, 0, None, ctypes.byref(h)) == lb.LB_EINVAL

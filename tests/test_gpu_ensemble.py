@@ -1,0 +1,108 @@
+"""GPU tests of the batched ensemble (independent channels of different
+sizes, walls, tau and forces advanced together): each channel against the
+FP64 oracle in both launch modes, with and without the captured graph; graph
+replays against eager stepping; and the autotuner."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_14551_amd import lb  # noqa: E402
+from oracle.sim import OracleSim, OracleParams  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# three uneven channels; off-site droplet centres (no site at a symmetry point)
+CHANNELS = [
+    dict(shape=(70, 20, 13), walls=(0, 1, 1), tau=0.9, A=0.02, body_force=(2e-5, 0.0, 0.0),
+         centres=[[21.17, 9.77, 6.81], [33.17, 10.11, 6.37]], radii=[4.0, 4.0]),
+    dict(shape=(64, 16, 12), walls=(0, 0, 0), tau=0.7, A=0.01, body_force=(0.0, 1e-5, 0.0),
+         centres=[[20.3, 7.9, 5.6]], radii=[4.5]),
+    dict(shape=(40, 24, 20), walls=(0, 0, 1), tau=1.1, A=0.015, body_force=(1e-5, 0.0, 2e-6),
+         centres=[[12.3, 11.7, 10.2], [26.8, 12.1, 9.9]], radii=[5.5, 5.5]),
+]
+
+
+def make(storage="f64", lattice="D3Q19"):
+    chans = [{k: v for k, v in c.items() if k not in ("centres", "radii")} for c in CHANNELS]
+    ens = lb.Ensemble(chans, lattice=lattice, storage=storage, nc="explicit")
+    for k, c in enumerate(CHANNELS):
+        ens.init_droplets(k, c["centres"], c["radii"])
+    return ens
+
+
+def oracle(c, lattice, steps):
+    nx, ny, nz = c["shape"]
+    p = OracleParams(lattice=lattice, nx=nx, ny=ny, nz=nz, walls=tuple(bool(w) for w in c["walls"]),
+                     tau=c["tau"], A=c["A"], beta=0.7, body_force=tuple(c["body_force"]), nc=True)
+    return OracleSim(p).init_droplets(c["centres"], c["radii"]).step(steps)
+
+
+@pytest.mark.parametrize("mode,graph", [("batched", 0), ("batched", 1), ("per_channel", 0), ("per_channel", 1)])
+@pytest.mark.parametrize("lattice", ["D3Q19", "D3Q27"])
+def test_ensemble_fp64_matches_oracle_per_channel(mode, graph, lattice):
+    steps = 30
+    say(f"case ensemble fp64 {lattice} mode={mode} graph={graph}")
+    ens = make("f64", lattice)
+    ens.set_tuning(mode, z_per_block=4, use_graph=graph)
+    for k in range(0, steps, 10):
+        ens.step(10)      # with the graph: four replays and two eager steps
+        ens.sync()
+        say(f"  step {k + 10} done")
+    raw = ens.get_state()
+    for k, c in enumerate(CHANNELS):
+        st = ens.channel_state(raw, k).cpu().numpy()
+        o = oracle(c, lattice, steps)
+        e = max(np.abs(st[0] - o.fA).max(), np.abs(st[1] - o.fB).max()) / np.abs(o.fA).max()
+        say(f"  channel {k} {c['shape']}: rel err {e:.2e}")
+        assert e < 1e-12, (k, e)
+        f = {n: v.cpu().numpy() for n, v in ens.fields(k, ("rho_a", "f_nc")).items()}
+        of = o.fields()
+        assert np.abs(f["rho_a"] - of["rho_a"]).max() < 1e-12
+        assert np.abs(f["f_nc"] - of["f_nc"]).max() < 1e-12
+    assert any(np.abs(oracle(c, lattice, steps).fields()["f_nc"]).max() > 0 for c in CHANNELS)
+    ens.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16t"])
+def test_graph_replays_match_eager(storage):
+    """Several graph replays, with eager work and synchronisations between
+    them, give bit-identical states to eager single launches."""
+    say(f"case ensemble graph replays {storage}")
+    a = make(storage)
+    b = make(storage)
+    a.set_tuning("batched", z_per_block=4, use_graph=1)
+    b.set_tuning("batched", z_per_block=4, use_graph=0)
+    for chunk in (5, 8, 7, 6):
+        a.step(chunk)
+        a.sync()
+        a.fields(0, ("rho_a",))          # eager work between replays
+        b.step(chunk)
+        b.sync()
+        assert torch.equal(a.get_state(), b.get_state()), chunk
+    a.close()
+    b.close()
+
+
+def test_autotune_picks_a_measured_config(tmp_path):
+    say("case ensemble autotune")
+    ens = make("f32")
+    cache = str(tmp_path / "tune.json")
+    best, table = ens.autotune(steps=2, cache=cache)
+    assert len(table) >= 2
+    assert best["ms_per_step"] == min(r["ms_per_step"] for r in table)
+    best2, _ = ens.autotune(steps=2, cache=cache)   # cached
+    assert best2["z_per_block"] == best["z_per_block"] and best2["mode"] == best["mode"]
+    assert best2["use_graph"] == best["use_graph"]
+    ens.sync()
+    ens.close()
