@@ -70,6 +70,9 @@ class OracleParams:
     # precision in which integer-valued decisions (flag threshold, rounding of
     # scan offsets, sign tests) are taken; float32 when comparing a float32 run
     decision_dtype: type = np.float64
+    # learned closure (oracle.mlp.Closure) replacing the explicit scan at
+    # interface sites whose stencil lies in its training range; needs nc=True
+    closure: object = None
 
     def replace(self, **kw):
         return replace(self, **kw)
@@ -170,7 +173,8 @@ class OracleSim:
         self.t = 0
         self._fields = dict(rho_a=rho_a, rho_b=rho_b, phi=phi, u=u,
                             f_nc=np.zeros((3,) + self.shape),
-                            flags=flags_from_phi(phi, p.phi_interface, p.decision_dtype))
+                            flags=flags_from_phi(phi, p.phi_interface, p.decision_dtype),
+                            nc_source=np.zeros(self.shape, dtype=np.uint8))
         return self
 
     def set_state(self, fA, fB, t=0):
@@ -232,6 +236,7 @@ class OracleSim:
         F_nc = (A_h(h)/2) g(x), A_h = A for h <= h_min, A (h_min/h)^3 above."""
         p = self.p
         F = np.zeros((3,) + self.shape)
+        self._nc_source = np.zeros(self.shape, dtype=np.uint8)
         if not p.nc:
             return F
         dt = p.decision_dtype
@@ -269,6 +274,18 @@ class OracleSim:
         Ah = np.where(h <= p.nc_hmin, p.nc_A, p.nc_A * (p.nc_hmin / np.where(got, h, 1.0)) ** 3)
         Ah = np.where(got, Ah, 0.0)
         F[:, iz, iy, ix] = 0.5 * Ah * gx
+        if p.closure is not None:
+            # learned closure where the stencil is inside its training range;
+            # the explicit force above stays at the other candidates
+            from .mlp import stencil_inputs
+            X, gn32 = stencil_inputs(self, phi, g, (iz, iy, ix))
+            use = p.closure.in_range(X, gn32)
+            src = np.zeros(self.shape, dtype=np.uint8)
+            src[iz, iy, ix] = np.where(use, 1, 2)
+            self._nc_source = src
+            if use.any():
+                Fm = p.nc_A * p.closure.force_over_A(X[use])
+                F[:, iz[use], iy[use], ix[use]] = Fm.T
         return F
 
     # -------------------------------------------------------------------- step
@@ -324,7 +341,8 @@ class OracleSim:
         self.fA = (rho_a / rho) * fstar + coef * wq * cos
         self.fB = (rho_b / rho) * fstar - coef * wq * cos
         self.t += 1
-        self._fields = dict(rho_a=rho_a, rho_b=rho_b, phi=phi, u=u, f_nc=f_nc, flags=flags)
+        self._fields = dict(rho_a=rho_a, rho_b=rho_b, phi=phi, u=u, f_nc=f_nc, flags=flags,
+                            nc_source=self._nc_source)
 
     # ------------------------------------------------------------- reporting
     def fields(self):
