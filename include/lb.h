@@ -76,7 +76,10 @@ typedef enum lb_storage {
   LB_BF16_TOTAL = 6
 } lb_storage;
 
-typedef enum lb_nc_mode { LB_NC_OFF = 0, LB_NC_EXPLICIT = 1 } lb_nc_mode;
+/* Near-contact force: off; the explicit scan (Eq. near_cont_force); or the
+ * learned closure (3D lattices; storages LB_F64, LB_F32 and the total layouts)
+ * with the explicit scan at interface sites outside the closure's input range. */
+typedef enum lb_nc_mode { LB_NC_OFF = 0, LB_NC_EXPLICIT = 1, LB_NC_MLP = 2 } lb_nc_mode;
 
 /* field selection bits for lb_fields; dst[k] belongs to bit k */
 enum {
@@ -215,6 +218,70 @@ int lb_set_tuning(lb_handle* h, const lb_tuning* t);
  * doubles; *n_results the number of candidates.  The timed steps advance the
  * simulation: tune before lb_init_droplets or re-initialise afterwards. */
 int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int cap, int* n_results);
+
+/* ---- Learned near-contact closure --------------------------------------------
+ * The paper's outlook proposes learning near-contact forces from data
+ * (Sec. VI.B.3).  The closure is a perceptron trained on rows the explicit
+ * model generates:
+ *   inputs (30)  phi on the 3x3x3 neighbourhood of an interface site, offsets
+ *                (dx, dy, dz) in lexicographic order, index
+ *                (dx+1) + 3 (dy+1) + 9 (dz+1) (wall ghosts mirrored, periodic
+ *                axes wrapped), then the unit normal g/|g|
+ *   network      tanh(W1 x + b1) (64), tanh(W2 h1 + b2) (64), W3 h2 + b3 (3)
+ *   output       F_nc / (nc_A |g|); the explicit force (A_h/2) g makes this the
+ *                normal times A_h / (2 nc_A)
+ * Parameters are LB_MLP_PARAMS floats: W1 (64x30, row-major), b1 (64),
+ * W2 (64x64), b2 (64), W3 (3x64), b3 (3).  Inference (in the collision pass
+ * under LB_NC_MLP, and lb_mlp_infer) uses BF16 inputs, weights and hidden
+ * values with FP32 accumulation on the matrix cores; training is FP32.  A site
+ * uses the closure when all 30 inputs lie in [lo, hi] and |g| >= gmin (the
+ * ranges of the training rows); other interface sites get the explicit scan.
+ * With the closure, lb_fields' flags byte has bit 1 set where the network gave
+ * the force and bit 2 where the explicit scan did.
+ * Rows are LB_MLP_ROW floats: the 30 inputs, |g|, 0.  Targets are 3 floats. */
+#define LB_MLP_PARAMS 6339
+#define LB_MLP_ROW 32
+#define LB_MLP_MAX_BATCH 65536
+
+/* Training rows of the last step (which must have used LB_NC_EXPLICIT): one row
+ * per interface site with |g| > 1e-12, target F_nc / (nc_A |g|).  Rows of
+ * force-active sites come first, then force-free ones, each in site order
+ * (x fastest).  rows (cap x LB_MLP_ROW) and targets (cap x 3) are device
+ * pointers; at most cap rows are written.  *m_active / *m_free receive the
+ * full counts (host pointers).  3D lattices only.  Synchronises. */
+int lb_nc_collect(lb_handle* h, int channel, float* rows, float* targets, long long cap,
+                  long long* m_active, long long* m_free);
+
+/* Network parameters (host pointers, n == LB_MLP_PARAMS).  Setting them
+ * keeps the input ranges (initially empty: every site takes the explicit
+ * scan until lb_mlp_set_ranges or lb_mlp_train sets them). */
+int lb_mlp_set_weights(lb_handle* h, const float* theta, long long n);
+int lb_mlp_get_weights(lb_handle* h, float* theta, long long n);
+
+/* Input ranges of the closure (host pointers: lo[30], hi[30]). */
+int lb_mlp_set_ranges(lb_handle* h, const float* lo, const float* hi, float gmin);
+int lb_mlp_get_ranges(lb_handle* h, float* lo, float* hi, float* gmin);
+
+/* Train from the current parameters with Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, fresh moments) on the mean squared error of the outputs: step t
+ * (0 .. n_steps-1) uses rows order[t*batch .. (t+1)*batch).  rows (m x
+ * LB_MLP_ROW), targets (m x 3), order (n_steps x batch int32) and loss_log
+ * (n_steps floats, the batch loss before each update; may be NULL) are
+ * device pointers.  The input ranges are then set from rows [0, m).
+ * 1 <= batch <= LB_MLP_MAX_BATCH.  An order entry outside [0, m) is skipped
+ * and the call returns LB_EINVAL after the run.  Synchronises. */
+int lb_mlp_train(lb_handle* h, const float* rows, const float* targets, long long m, const int* order,
+                 int n_steps, int batch, double lr, float* loss_log);
+
+/* Loss and gradient of the mean squared error over rows [0, m) at the current
+ * parameters (1 <= m <= LB_MLP_MAX_BATCH); grad (LB_MLP_PARAMS floats) and
+ * loss (1 float) are device pointers.  Synchronises. */
+int lb_mlp_gradient(lb_handle* h, const float* rows, const float* targets, long long m, float* grad, float* loss);
+
+/* Network outputs (m x 3) for rows (m x LB_MLP_ROW), device pointers, with
+ * the BF16 matrix-core evaluation of the collision pass.  Enqueued on the
+ * handle's stream. */
+int lb_mlp_infer(lb_handle* h, const float* rows, float* out, long long m);
 
 /* Destroy a handle and free its device memory.  NULL is accepted. */
 int lb_destroy(lb_handle* h);

@@ -12,7 +12,10 @@ Network (a project choice; the paper fixes no architecture):
           lexicographic order k = (dx+1) + 3 (dy+1) + 9 (dz+1), with the
           mirrored wall ghosts of the gradient stencil, then n = g / |g|
   hidden  h1 = tanh(W1 x + b1) (64), h2 = tanh(W2 h1 + b2) (64)
-  output  y = W3 h2 + b3 (3) = F_nc / A_nc
+  output  y = W3 h2 + b3 (3) = F_nc / (A_nc |g|)
+The explicit force is (A_h/2) g, so the target is (A_h / (2 A_nc)) g/|g|: the
+normal (an input) times a magnitude in {1/2, (h_min/h)^3 / 2, 0}, and the
+closure's force is A_nc |g| y.
 Parameters are packed as [W1 (64x30 row-major), b1, W2 (64x64), b2,
 W3 (3x64), b3], 6339 values.
 
@@ -179,8 +182,8 @@ def collect(sim):
     """Training rows of the last step of ``sim`` (run with the explicit force):
     every interface site with |g| > g_eps, in site order (x fastest), split
     into force-active and force-free ones.  Returns dict with X (m, 30) FP32,
-    gnorm (m,) FP32, T (m, 3) = F_nc / A_nc (FP64), site (m,) linear index,
-    active (m,) bool."""
+    gnorm (m,) FP32, T (m, 3) = F_nc / (A_nc |g|) (FP64), site (m,) linear
+    index, active (m,) bool."""
     p = sim.p
     fl = sim.fields()
     phi, Fnc = fl["phi"], fl["f_nc"]
@@ -189,7 +192,8 @@ def collect(sim):
     cand = fl["flags"] & (gg > p.g_eps ** 2)
     iz, iy, ix = np.nonzero(cand)           # lexicographic (z, y, x) = site order
     X, gn = stencil_inputs(sim, phi, g, (iz, iy, ix))
-    T = Fnc[:, iz, iy, ix].T / p.nc_A
+    gs = g[:, iz, iy, ix]
+    T = Fnc[:, iz, iy, ix].T / p.nc_A / np.sqrt((gs * gs).sum(0))[:, None]
     site = ix + p.nx * (iy + p.ny * iz)
     active = np.abs(T).sum(1) > 0
     return dict(X=X, gnorm=gn, T=T, site=site, active=active)
@@ -216,5 +220,6 @@ class Closure:
         return (np.all((X >= self.lo) & (X <= self.hi), axis=1)
                 & (np.asarray(gnorm, dtype=np.float32) >= self.gmin))
 
-    def force_over_A(self, X):
-        return forward_bf16(self.theta, X)
+    def force(self, X, gnorm, A_nc):
+        """F_nc = A_nc |g| y (|g| in FP64)."""
+        return A_nc * np.asarray(gnorm, dtype=np.float64)[:, None] * forward_bf16(self.theta, X)

@@ -284,7 +284,7 @@ class OracleSim:
             src[iz, iy, ix] = np.where(use, 1, 2)
             self._nc_source = src
             if use.any():
-                Fm = p.nc_A * p.closure.force_over_A(X[use])
+                Fm = p.closure.force(X[use], gn[use], p.nc_A)
                 F[:, iz[use], iy[use], ix[use]] = Fm.T
         return F
 

@@ -14,6 +14,7 @@
 #include "../../include/lb.h"
 #include "diag_kernels.hpp"
 #include "engine.hpp"
+#include "mlp_kernels.hpp"
 
 using namespace lbm;
 
@@ -104,6 +105,20 @@ struct lb_handle {
   lb_tuning tune{};                  // ensemble launch configuration
   hipGraphExec_t graph = nullptr;    // two non-field steps (parity 0 then 1)
   bool ensemble() const { return !chans.empty(); }
+  // learned near-contact closure: FP32 parameters, Adam moments, training
+  // scratch, input ranges and the network in MFMA operand order
+  float* mlp_theta = nullptr;
+  float* mlp_m1 = nullptr;
+  float* mlp_m2 = nullptr;
+  float* mlp_grad = nullptr;
+  float* mlp_part = nullptr;         // partial gradients, mlp_part_cap workgroups
+  float* mlp_part_l = nullptr;
+  int mlp_part_cap = 0;
+  float* mlp_lo = nullptr;           // [32] lo, then [32] hi
+  uint32_t* mlp_bad = nullptr;
+  MlpPacked* mlp_net = nullptr;
+  float mlp_gmin = INFINITY;
+  bool mlp_weights = false;
   // per-kernel timing: hipEvent pairs recorded on the handle's stream around
   // each launch while profiling is on
   bool prof_on = false;
@@ -191,7 +206,10 @@ static int validate(const lb_params* p) {
   if (!p) return fail(LB_EINVAL, "params is NULL");
   if (!ops_for(p->lattice)) return fail(LB_EINVAL, "unknown lattice %d", p->lattice);
   if (storage_bytes(p->storage) == 0) return fail(LB_EINVAL, "unknown storage %d", p->storage);
-  if (p->nc_mode != LB_NC_OFF && p->nc_mode != LB_NC_EXPLICIT) return fail(LB_EINVAL, "unknown nc_mode %d", p->nc_mode);
+  if (p->nc_mode != LB_NC_OFF && p->nc_mode != LB_NC_EXPLICIT && p->nc_mode != LB_NC_MLP)
+    return fail(LB_EINVAL, "unknown nc_mode %d", p->nc_mode);
+  if (p->nc_mode == LB_NC_MLP && (p->lattice == LB_D2Q9 || !mlp_storage(p->storage)))
+    return fail(LB_EINVAL, "the learned closure needs a 3D lattice and storage LB_F64, LB_F32 or a total layout");
   if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return fail(LB_EINVAL, "sizes must be positive");
   if (p->lattice == LB_D2Q9 && (p->nz != 1 || p->wall[2])) return fail(LB_EINVAL, "D2Q9 needs nz == 1 and no z wall");
   if (p->lattice == LB_D2Q9 && (p->body_force[2] != 0.0 || p->u0[2] != 0.0))
@@ -232,7 +250,8 @@ int lb_destroy(lb_handle* h) {
     if (b) (void)hipFree(b);
   for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
   void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
-                  h->diag_partial, h->diag_out, h->ccl_count, h->drops};
+                  h->diag_partial, h->diag_out, h->ccl_count, h->drops, h->mlp_theta, h->mlp_m1, h->mlp_m2,
+                  h->mlp_grad, h->mlp_part, h->mlp_part_l, h->mlp_lo, h->mlp_bad, h->mlp_net};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(dev);
@@ -267,6 +286,7 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
       return fail(LB_EINVAL, "channel %d: lattice, storage and nc_mode must agree across channels", c);
   }
   if (n_channels == 1) return create_single(p, hip_stream, out);
+  if (p[0].nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "ensembles take nc_mode LB_NC_OFF or LB_NC_EXPLICIT");
   if (!ensemble_storage(p[0].storage))
     return fail(LB_EINVAL, "ensembles take storage LB_F64, LB_F32 or a total layout (got %d)", p[0].storage);
   int ndev = 0;
@@ -615,6 +635,8 @@ int lb_step(lb_handle* h, int nsteps) {
     return ensemble_step(h, nsteps);
   }
   if (!h->initialised) return fail(LB_EINVAL, "call lb_init_droplets or lb_set_state first");
+  if (h->p.nc_mode == LB_NC_MLP && !h->mlp_weights)
+    return fail(LB_EINVAL, "LB_NC_MLP needs network parameters (lb_mlp_set_weights or lb_mlp_train)");
   (void)hipSetDevice(h->device);
   const StepArgs a = h->step_args();
   const FieldPtrs fo = h->field_ptrs();
@@ -629,8 +651,12 @@ int lb_step(lb_handle* h, int nsteps) {
     HIP_TRY(h->ops->phase(h->p.storage, fin, h->sc[h->cur], h->phi, a, h->stream));
     if ((r = prof_mark(h, 0, false))) return r;
     if ((r = prof_mark(h, 1, true))) return r;
-    HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->sc[h->cur], h->sc[1 - h->cur], h->phi, fo, a,
-                            h->stream));
+    if (h->p.nc_mode == LB_NC_MLP)
+      HIP_TRY(h->ops->collide_mlp(h->p.storage, fields, fin, fout, h->sc[h->cur], h->sc[1 - h->cur], h->phi, fo, a,
+                                  h->mlp_net, h->stream));
+    else
+      HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->sc[h->cur], h->sc[1 - h->cur], h->phi, fo, a,
+                              h->stream));
     if ((r = prof_mark(h, 1, false))) return r;
     h->cur = 1 - h->cur;
     h->t += 1;
@@ -937,6 +963,283 @@ int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int c
   *best = cand[best_k];
   if (h->ensemble()) h->tune.ms_per_step = best_ms;
   return LB_OK;
+}
+
+// ------------------------------------------------------ learned closure
+static int mlp_alloc(lb_handle* h) {
+  if (h->mlp_theta) return LB_OK;
+  int rc = 0;
+  if ((rc = dev_alloc((void**)&h->mlp_theta, sizeof(float) * MLP_PARAMS, "closure parameters"))) return rc;
+  if ((rc = dev_alloc((void**)&h->mlp_m1, sizeof(float) * MLP_PARAMS, "Adam moments"))) return rc;
+  if ((rc = dev_alloc((void**)&h->mlp_m2, sizeof(float) * MLP_PARAMS, "Adam moments"))) return rc;
+  // gradient plus one float for a batch loss nobody asked for
+  if ((rc = dev_alloc((void**)&h->mlp_grad, sizeof(float) * (MLP_PARAMS + 1), "closure gradient"))) return rc;
+  if ((rc = dev_alloc((void**)&h->mlp_lo, sizeof(float) * 64, "closure ranges"))) return rc;
+  if ((rc = dev_alloc((void**)&h->mlp_bad, sizeof(uint32_t), "closure flag"))) return rc;
+  if ((rc = dev_alloc((void**)&h->mlp_net, sizeof(MlpPacked), "packed closure"))) return rc;
+  // empty ranges until set: every interface site takes the explicit scan
+  float r[64];
+  for (int k = 0; k < 32; ++k) {
+    r[k] = INFINITY;
+    r[32 + k] = -INFINITY;
+  }
+  HIP_TRY(hipMemcpy(h->mlp_lo, r, sizeof r, hipMemcpyHostToDevice));
+  h->mlp_gmin = INFINITY;
+  return LB_OK;
+}
+
+static int mlp_parts(lb_handle* h, int nparts) {
+  if (nparts <= h->mlp_part_cap) return LB_OK;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (h->mlp_part) HIP_TRY(hipFree(h->mlp_part));
+  if (h->mlp_part_l) HIP_TRY(hipFree(h->mlp_part_l));
+  h->mlp_part = nullptr;
+  h->mlp_part_l = nullptr;
+  h->mlp_part_cap = 0;
+  int rc = 0;
+  if ((rc = dev_alloc((void**)&h->mlp_part, sizeof(float) * MLP_PARAMS * (size_t)nparts, "partial gradients")))
+    return rc;
+  if ((rc = dev_alloc((void**)&h->mlp_part_l, sizeof(float) * (size_t)nparts, "partial losses"))) return rc;
+  h->mlp_part_cap = nparts;
+  return LB_OK;
+}
+
+static int mlp_pack(lb_handle* h) {
+  k_mlp_pack<<<1, 256, 0, h->stream>>>(h->mlp_theta, h->mlp_lo, h->mlp_lo + 32, h->mlp_gmin, h->mlp_net);
+  HIP_TRY(hipGetLastError());
+  return LB_OK;
+}
+
+int lb_mlp_set_weights(lb_handle* h, const float* theta, long long n) {
+  if (!h || !theta) return fail(LB_EINVAL, "NULL argument");
+  if (n != MLP_PARAMS) return fail(LB_EINVAL, "expected %d parameters, got %lld", MLP_PARAMS, n);
+  if (h->ensemble()) return fail(LB_EINVAL, "the learned closure is not available for ensembles");
+  (void)hipSetDevice(h->device);
+  int rc = mlp_alloc(h);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(h->mlp_theta, theta, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, h->stream));
+  if ((rc = mlp_pack(h))) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->mlp_weights = true;
+  return LB_OK;
+}
+
+int lb_mlp_get_weights(lb_handle* h, float* theta, long long n) {
+  if (!h || !theta) return fail(LB_EINVAL, "NULL argument");
+  if (n != MLP_PARAMS) return fail(LB_EINVAL, "expected %d parameters, got %lld", MLP_PARAMS, n);
+  if (!h->mlp_weights) return fail(LB_EINVAL, "no network parameters set");
+  (void)hipSetDevice(h->device);
+  HIP_TRY(hipMemcpyAsync(theta, h->mlp_theta, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+int lb_mlp_set_ranges(lb_handle* h, const float* lo, const float* hi, float gmin) {
+  if (!h || !lo || !hi) return fail(LB_EINVAL, "NULL argument");
+  if (h->ensemble()) return fail(LB_EINVAL, "the learned closure is not available for ensembles");
+  (void)hipSetDevice(h->device);
+  int rc = mlp_alloc(h);
+  if (rc) return rc;
+  float r[64];
+  for (int k = 0; k < 32; ++k) {
+    r[k] = k < MLP_IN ? lo[k] : INFINITY;
+    r[32 + k] = k < MLP_IN ? hi[k] : -INFINITY;
+  }
+  HIP_TRY(hipMemcpyAsync(h->mlp_lo, r, sizeof r, hipMemcpyHostToDevice, h->stream));
+  h->mlp_gmin = gmin;
+  if ((rc = mlp_pack(h))) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+int lb_mlp_get_ranges(lb_handle* h, float* lo, float* hi, float* gmin) {
+  if (!h || !lo || !hi || !gmin) return fail(LB_EINVAL, "NULL argument");
+  (void)hipSetDevice(h->device);
+  int rc = mlp_alloc(h);
+  if (rc) return rc;
+  float r[64];
+  HIP_TRY(hipMemcpyAsync(r, h->mlp_lo, sizeof r, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int k = 0; k < MLP_IN; ++k) {
+    lo[k] = r[k];
+    hi[k] = r[32 + k];
+  }
+  *gmin = h->mlp_gmin;
+  return LB_OK;
+}
+
+// forward/backward over nb rows (idx == NULL: rows 0 .. nb-1), summed into
+// mlp_grad, loss into loss_dst
+static int mlp_fwdbwd(lb_handle* h, const float* rows, const float* targets, long long m, const int* idx, int nb,
+                      float* loss_dst) {
+  const int nparts = (nb + MLP_SB - 1) / MLP_SB;
+  int rc = mlp_parts(h, nparts);
+  if (rc) return rc;
+  k_mlp_fwdbwd<<<nparts, MLP_TB, 0, h->stream>>>(
+      h->mlp_theta, rows, targets, (const int32_t*)idx, nb, m, (float)(2.0 / (3.0 * nb)), h->mlp_part,
+      h->mlp_part_l, h->mlp_bad);
+  HIP_TRY(hipGetLastError());
+  k_mlp_reduce<<<(MLP_PARAMS + 255) / 256, 256, 0, h->stream>>>(h->mlp_part, h->mlp_part_l, nparts,
+                                                               (float)(1.0 / (3.0 * nb)), h->mlp_grad, loss_dst);
+  HIP_TRY(hipGetLastError());
+  return LB_OK;
+}
+
+int lb_mlp_gradient(lb_handle* h, const float* rows, const float* targets, long long m, float* grad, float* loss) {
+  if (!h || !rows || !targets || !grad || !loss) return fail(LB_EINVAL, "NULL argument");
+  if (m < 1 || m > LB_MLP_MAX_BATCH) return fail(LB_EINVAL, "m must lie in [1, %d]", LB_MLP_MAX_BATCH);
+  if (!h->mlp_weights) return fail(LB_EINVAL, "no network parameters set");
+  (void)hipSetDevice(h->device);
+  HIP_TRY(hipMemsetAsync(h->mlp_bad, 0, sizeof(uint32_t), h->stream));
+  int rc = mlp_fwdbwd(h, rows, targets, m, nullptr, (int)m, loss);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(grad, h->mlp_grad, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+int lb_mlp_train(lb_handle* h, const float* rows, const float* targets, long long m, const int* order, int n_steps,
+                 int batch, double lr, float* loss_log) {
+  if (!h || !rows || !targets || (!order && n_steps > 0)) return fail(LB_EINVAL, "NULL argument");
+  if (m < 1) return fail(LB_EINVAL, "m must be >= 1");
+  if (n_steps < 0) return fail(LB_EINVAL, "n_steps must be >= 0");
+  if (batch < 1 || batch > LB_MLP_MAX_BATCH) return fail(LB_EINVAL, "batch must lie in [1, %d]", LB_MLP_MAX_BATCH);
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(LB_EINVAL, "lr must be positive");
+  if (!h->mlp_weights) return fail(LB_EINVAL, "set initial network parameters first (lb_mlp_set_weights)");
+  (void)hipSetDevice(h->device);
+  HIP_TRY(hipMemsetAsync(h->mlp_bad, 0, sizeof(uint32_t), h->stream));
+  HIP_TRY(hipMemsetAsync(h->mlp_m1, 0, sizeof(float) * MLP_PARAMS, h->stream));
+  HIP_TRY(hipMemsetAsync(h->mlp_m2, 0, sizeof(float) * MLP_PARAMS, h->stream));
+  double p1 = 1.0, p2 = 1.0;
+  for (int t = 0; t < n_steps; ++t) {
+    int rc = mlp_fwdbwd(h, rows, targets, m, order + (size_t)t * batch, batch,
+                        loss_log ? loss_log + t : h->mlp_grad + MLP_PARAMS);
+    if (rc) return rc;
+    p1 *= 0.9;
+    p2 *= 0.999;
+    k_mlp_adam<<<(MLP_PARAMS + 255) / 256, 256, 0, h->stream>>>(h->mlp_theta, h->mlp_m1, h->mlp_m2, h->mlp_grad,
+                                                                (float)lr, (float)(1.0 - p1), (float)(1.0 - p2));
+    HIP_TRY(hipGetLastError());
+  }
+  // input ranges of the training rows
+  const int nparts = (int)std::min<long long>(1024, (m + 7) / 8);
+  float* part = nullptr;
+  int rc = dev_alloc((void**)&part, sizeof(float) * 64 * (size_t)nparts, "range partials");
+  if (rc) return rc;
+  k_mlp_range_part<<<nparts, 256, 0, h->stream>>>(rows, m, part);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_mlp_range_final<<<1, 32, 0, h->stream>>>(part, nparts, h->mlp_lo, h->mlp_lo + 32);
+    e = hipGetLastError();
+  }
+  float r[64];
+  uint32_t bad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(r, h->mlp_lo, sizeof r, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->mlp_bad, sizeof bad, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(part);
+  if (e != hipSuccess) return fail(LB_EHIP, "closure training: %s", hipGetErrorString(e));
+  // column 30 holds |g|: its minimum is the smallest training |g|
+  h->mlp_gmin = r[MLP_IN];
+  for (int k = MLP_IN; k < 32; ++k) {
+    r[k] = INFINITY;
+    r[32 + k] = -INFINITY;
+  }
+  HIP_TRY(hipMemcpyAsync(h->mlp_lo, r, sizeof r, hipMemcpyHostToDevice, h->stream));
+  if ((rc = mlp_pack(h))) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (bad) return fail(LB_EINVAL, "order holds row indices outside [0, %lld); those rows were skipped", m);
+  return LB_OK;
+}
+
+int lb_mlp_infer(lb_handle* h, const float* rows, float* out, long long m) {
+  if (!h || (m > 0 && (!rows || !out))) return fail(LB_EINVAL, "NULL argument");
+  if (m < 0) return fail(LB_EINVAL, "m must be >= 0");
+  if (!h->mlp_weights) return fail(LB_EINVAL, "no network parameters set");
+  if (m == 0) return LB_OK;
+  (void)hipSetDevice(h->device);
+  const long long blocks = (m + 63) / 64;
+  if (blocks > 0x7fffffffLL) return fail(LB_EINVAL, "too many rows");
+  k_mlp_infer<<<(unsigned)blocks, 256, 0, h->stream>>>(h->mlp_net, rows, m, out);
+  HIP_TRY(hipGetLastError());
+  return LB_OK;
+}
+
+}  // extern "C"
+
+template <class L, class R>
+static int collect_t(lb_handle* h, float* rows, float* targets, long long cap, long long* m_active, long long* m_free) {
+  CollectArgs a{};
+  a.nx = h->p.nx; a.ny = h->p.ny; a.nz = h->p.nz;
+  a.wall_x = h->p.wall[0]; a.wall_y = h->p.wall[1]; a.wall_z = h->p.wall[2];
+  a.N = h->N;
+  a.phi_I = h->p.phi_interface;
+  a.inv_ncA = 1.0 / h->p.nc_A;
+  const uint32_t nblk = (h->N + 255) / 256;
+  uint32_t* counts = nullptr;
+  uint64_t* offs = nullptr;
+  int rc = dev_alloc((void**)&counts, sizeof(uint32_t) * 2 * nblk, "collection counts");
+  if (rc) return rc;
+  if ((rc = dev_alloc((void**)&offs, sizeof(uint64_t) * 2 * nblk, "collection offsets"))) {
+    (void)hipFree(counts);
+    return rc;
+  }
+  std::vector<uint32_t> c(2 * (size_t)nblk);
+  std::vector<uint64_t> o(2 * (size_t)nblk);
+  const R* phi = (const R*)h->phi;
+  const R* fnc = (const R*)h->fnc;
+  hipError_t e = hipSuccess;
+  k_collect_count<L, R><<<nblk, 256, 0, h->stream>>>(phi, fnc, a, counts);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(c.data(), counts, sizeof(uint32_t) * c.size(), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  uint64_t na = 0, nf = 0;
+  if (e == hipSuccess) {
+    for (uint32_t b = 0; b < nblk; ++b) na += c[2 * b];
+    uint64_t ra = 0, rf = na;
+    for (uint32_t b = 0; b < nblk; ++b) {
+      o[2 * b] = ra;
+      o[2 * b + 1] = rf;
+      ra += c[2 * b];
+      rf += c[2 * b + 1];
+    }
+    nf = rf - na;
+    e = hipMemcpyAsync(offs, o.data(), sizeof(uint64_t) * o.size(), hipMemcpyHostToDevice, h->stream);
+  }
+  if (e == hipSuccess && cap > 0) {
+    k_collect_write<L, R><<<nblk, 256, 0, h->stream>>>(phi, fnc, a, offs, cap, rows, targets);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(counts);
+  (void)hipFree(offs);
+  if (e != hipSuccess) return fail(LB_EHIP, "closure row collection: %s", hipGetErrorString(e));
+  *m_active = (long long)na;
+  *m_free = (long long)nf;
+  return LB_OK;
+}
+
+extern "C" {
+
+int lb_nc_collect(lb_handle* h, int channel, float* rows, float* targets, long long cap, long long* m_active,
+                  long long* m_free) {
+  if (!h || !m_active || !m_free) return fail(LB_EINVAL, "NULL argument");
+  if (h->ensemble()) {
+    if (channel < 0 || channel >= (int)h->chans.size()) return fail(LB_EINVAL, "channel %d out of range", channel);
+    return lb_nc_collect(h->chans[channel], 0, rows, targets, cap, m_active, m_free);
+  }
+  if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
+  if (cap < 0 || (cap > 0 && (!rows || !targets))) return fail(LB_EINVAL, "bad output buffers");
+  if (h->d != 3) return fail(LB_EINVAL, "the learned closure is 3D only");
+  if (h->p.nc_mode != LB_NC_EXPLICIT) return fail(LB_EINVAL, "collection needs a step with LB_NC_EXPLICIT");
+  if (!h->fields_valid || h->t == 0) return fail(LB_EINVAL, "take a step first: rows come from the last step");
+  (void)hipSetDevice(h->device);
+  const bool f64 = h->p.storage == LB_F64;
+  if (h->p.lattice == LB_D3Q19)
+    return f64 ? collect_t<D3Q19, double>(h, rows, targets, cap, m_active, m_free)
+               : collect_t<D3Q19, float>(h, rows, targets, cap, m_active, m_free);
+  return f64 ? collect_t<D3Q27, double>(h, rows, targets, cap, m_active, m_free)
+             : collect_t<D3Q27, float>(h, rows, targets, cap, m_active, m_free);
 }
 
 }  // extern "C"

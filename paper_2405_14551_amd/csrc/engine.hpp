@@ -30,7 +30,15 @@ struct LatticeOps {
   // ST_F64, ST_F32 and the total layouts)
   hipError_t (*ensemble)(int storage, bool nc, bool fields, const ChannelDev* chans, const uint32_t* items,
                          uint32_t nitems, int parity, hipStream_t s);
+  // collision pass with the learned near-contact closure (3D; storages
+  // ST_F64, ST_F32 and the total layouts); NULL for 2D
+  hipError_t (*collide_mlp)(int storage, bool fields, const void* fin, void* fout, const float* scin, float* scout,
+                            const void* phi, const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net,
+                            hipStream_t s);
 };
+
+// storages the learned closure is built for
+inline bool mlp_storage(int st) { return st == ST_F64 || st == ST_F32 || st >= ST_F32T; }
 
 // storages the ensemble kernel is built for
 inline bool ensemble_storage(int st) { return st == ST_F64 || st == ST_F32 || st >= ST_F32T; }

@@ -93,6 +93,43 @@ struct Launch {
     return hipErrorInvalidValue;
   }
 
+  // collision pass with the learned near-contact closure (3D lattices)
+  template <class S, bool FIELDS, bool TOT>
+  static hipError_t collide_mlp_t(const void* fin, void* fout, const float* scin, float* scout, const void* phi,
+                                  const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
+    using R = typename Storage<S>::real;
+    using T = Tile<TILE_X, TILE_Y, 4, L::D>;
+    dim3 block(T::TX, T::TY, 1);
+    const int zb = a.z_per_block;
+    StepArgs b = a;
+    b.tiles_x = (a.nx + T::TX - 1) / T::TX;
+    b.tiles_y = (a.ny + T::TY - 1) / T::TY;
+    dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
+    k_collide_mlp<L, S, T, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scin, scout,
+                                                               fo, b, net);
+    return hipGetLastError();
+  }
+
+  static hipError_t collide_mlp(int st, bool fields, const void* fin, void* fout, const float* scin, float* scout,
+                                const void* phi, const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net,
+                                hipStream_t s) {
+    if constexpr (L::D == 3) {
+#define LB_MLP_CASE(ST, TYPE, TOT)                                                          \
+  case ST:                                                                                  \
+    return fields ? collide_mlp_t<TYPE, true, TOT>(fin, fout, scin, scout, phi, fo, a, net, s) \
+                  : collide_mlp_t<TYPE, false, TOT>(fin, fout, scin, scout, phi, fo, a, net, s);
+      switch (st) {
+        LB_MLP_CASE(ST_F64, double, false)
+        LB_MLP_CASE(ST_F32, float, false)
+        LB_MLP_CASE(ST_F32T, float, true)
+        LB_MLP_CASE(ST_F16T, _Float16, true)
+        LB_MLP_CASE(ST_BF16T, __bf16, true)
+      }
+#undef LB_MLP_CASE
+    }
+    return hipErrorInvalidValue;
+  }
+
   template <class S>
   static hipError_t init_t(void* f, void* phi, const FieldPtrs& fo, const double* drops, const InitArgs& a,
                            hipStream_t s) {
@@ -160,7 +197,7 @@ struct Launch {
   }
 
   static LatticeOps ops() {
-    return LatticeOps{L::Q, L::D, &phase, &collide, &init, &ensemble};
+    return LatticeOps{L::Q, L::D, &phase, &collide, &init, &ensemble, L::D == 3 ? &collide_mlp : nullptr};
   }
 };
 

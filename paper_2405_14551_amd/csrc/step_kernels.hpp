@@ -26,6 +26,7 @@
 #include <type_traits>
 
 #include "lattice.hpp"
+#include "mlp_device.hpp"
 
 namespace lbm {
 
@@ -544,21 +545,34 @@ __device__ __forceinline__ void phase_tile(const S* __restrict__ fin, typename S
 // pass 2: gradient, flags, near contact, collision, recolouring, store
 // LDS of one collision tile: the phase-field ring and, for the total layout,
 // the scalar ring
-template <class L, class S, class T, bool TOT>
+template <class L, class S, class T, bool TOT, bool MLP = false>
 struct CollideSmem {
   using R = typename Storage<S>::real;
   using TS = Tile<T::TX, T::TY, 1, L::D>;
   R ring[T::NPL * T::PL];
   float sring[TOT ? TS::NPL * ScalarRing<TS>::SLOT : 1];
 };
+// with the learned closure: the packed network and one row queue per wave
+template <class L, class S, class T, bool TOT>
+struct CollideSmem<L, S, T, TOT, true> : CollideSmem<L, S, T, TOT, false> {
+  MlpPacked net;
+  MlpQueue queue[T::NT / 64];
+};
 
-// collision pass of one tile (a TX x TY column over planes z0 .. z1-1)
-template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
+// collision pass of one tile (a TX x TY column over planes z0 .. z1-1).
+// MLP (with NC): the learned closure gives the near-contact force at
+// interface sites whose stencil lies in its training range, the explicit scan
+// at the others; the closure runs on whole waves, so in that mode every lane
+// takes part (lanes outside the lattice compute on a clamped site and store
+// nothing).
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false>
 __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __restrict__ fout,
                                              const typename Storage<S>::real* __restrict__ phi,
                                              const float* __restrict__ scin, float* __restrict__ scout,
                                              const FieldPtrs& fo, const StepArgs& a, const TileCoord& tc,
-                                             CollideSmem<L, S, T, TOT>& sm) {
+                                             CollideSmem<L, S, T, TOT, MLP>& sm,
+                                             const MlpPacked* __restrict__ net = nullptr) {
+  static_assert(!MLP || (NC && L::D == 3), "the learned closure replaces the 3D near-contact scan");
   using R = typename Storage<S>::real;
   using TS = Tile<T::TX, T::TY, 1, L::D>;   // scalar ring of the total layout
   R* ring = sm.ring;
@@ -578,6 +592,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       commit_scalars<TS>(sring, plane_slot(z0 + dz, TS::NPL), v, tid);
     }
   }
+  if constexpr (MLP) mlp_stage(sm.net, net, tid, T::NT);
   __syncthreads();
   const int sc0 = (ty + 1) * TS::TXH + (tx + 1);
 
@@ -601,10 +616,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       if (more) fetch_scalars<TS>(snxt, z + 1 + TS::RZ, scin, x0, y0, a, tid);
     }
     const int zc = plane_slot(z, T::NPL);
-    if (valid_xy) {
+    if (MLP || valid_xy) {
       // ---- issue the pull first so that its latency overlaps the stencil
       // work below: both colours (shifted by w_i rho0/2 each), or the total
-      const Nbr n = make_nbr(x, y, z, a);
+      const Nbr n = make_nbr(MLP ? min(x, a.nx - 1) : x, MLP ? min(y, a.ny - 1) : y, z, a);
       R va[L::Q], vb[TOT ? 1 : L::Q];
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
@@ -630,8 +645,39 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       R fnx = 0, fny = 0, fnz = 0;
       // |g| <= 1e-12 counts as no gradient (rounding noise at symmetric points)
       const bool has_g = gg > R(1e-24);
+      bool use_net = false;
+      if constexpr (MLP) {
+        // learned closure: inputs phi on the 3x3x3 neighbourhood (x fastest)
+        // and g/|g| in FP32; used where all lie in the training range
+        const bool cand = valid_xy && flag && has_g;
+        float xin[MLP_IN];
+        int k = 0;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+          const int pz = ring_slot(zc, dz, T::NPL) * T::PL;
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) xin[k++] = (float)ring[pz + c0 + dy * T::TXH + dx];
+        }
+        const R gnr = sqrt(gg);
+        xin[27] = (float)(gx / gnr);
+        xin[28] = (float)(gy / gnr);
+        xin[29] = (float)(gz / gnr);
+        bool inr = cand && (float)gnr >= sm.net.gmin;
+#pragma unroll
+        for (int q = 0; q < MLP_IN; ++q) inr = inr && xin[q] >= sm.net.lo[q] && xin[q] <= sm.net.hi[q];
+        float o[3] = {0.f, 0.f, 0.f};
+        mlp_wave_apply(sm.net, sm.queue[tid >> 6], inr, xin, o);
+        use_net = inr;
+        if (inr) {
+          // the network gives the force per unit strength and |g|
+          const R sA = (R)a.nc_A * gnr;
+          fnx = sA * (R)o[0]; fny = sA * (R)o[1]; fnz = sA * (R)o[2];
+        }
+      }
       if constexpr (NC) {
-        if (flag && has_g) {
+        if (flag && has_g && (!MLP || (valid_xy && !use_net))) {
           const R inv = R(1) / sqrt(gg);
           const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
           int hit = 0;
@@ -719,6 +765,9 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       const R Kr = coef * inv_gn;
       auto emit = [&](auto ic, R ds, R rec_odd) {
         constexpr int I = decltype(ic)::value;
+        if constexpr (MLP) {
+          if (!valid_xy) return;
+        }
         const uint32_t vo = n.site * ES, so = (uint32_t)I * a.N * ES;
         if constexpr (TOT) {
           total_bstore<S>(routA, vo, so, (float)ds);
@@ -752,7 +801,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         emit(std::integral_constant<int, I>{}, ds_i, rodd);
         emit(std::integral_constant<int, J>{}, ds_j, -rodd);
       });
-      if constexpr (TOT) {
+      if (TOT && (!MLP || valid_xy)) {
         // recolouring scalars of this site for the next pull
         const R bs = coef * inv_gn;
         __builtin_nontemporal_store((float)fa_frac, scout + n.site);
@@ -760,7 +809,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         __builtin_nontemporal_store((float)(bs * gy), scout + 2 * (size_t)a.N + n.site);
         __builtin_nontemporal_store((float)(bs * gz), scout + 3 * (size_t)a.N + n.site);
       }
-      if constexpr (FIELDS) {
+      if (FIELDS && (!MLP || valid_xy)) {
         R* rA = (R*)fo.rho_a;
         R* rB = (R*)fo.rho_b;
         R* U = (R*)fo.u;
@@ -769,7 +818,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         rB[n.site] = rb;
         U[n.site] = ux; U[a.N + n.site] = uy; U[2 * (size_t)a.N + n.site] = uz;
         Fn[n.site] = fnx; Fn[a.N + n.site] = fny; Fn[2 * (size_t)a.N + n.site] = fnz;
-        fo.flags[n.site] = flag ? 1 : 0;
+        // bit 0 interface; with the closure, bit 1 force from the network,
+        // bit 2 explicit scan at an interface site outside its range
+        const bool fallback = MLP && flag && has_g && !use_net;
+        fo.flags[n.site] = (uint8_t)((flag ? 1 : 0) | (use_net ? 2 : 0) | (fallback ? 4 : 0));
       }
     }
     if (more) commit_plane<T>(ring, plane_slot(z + 1 + T::RZ, T::NPL), nxt, tid);
@@ -788,6 +840,17 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
   __shared__ CollideSmem<L, S, T, TOT> sm;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
   collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, phi, scin, scout, fo, a, tc, sm);
+}
+
+// collision pass with the learned near-contact closure
+template <class L, class S, class T, bool FIELDS, bool TOT>
+__global__ void __launch_bounds__(T::NT) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
+                                                        const typename Storage<S>::real* __restrict__ phi,
+                                                        const float* __restrict__ scin, float* __restrict__ scout,
+                                                        FieldPtrs fo, StepArgs a, const MlpPacked* __restrict__ net) {
+  __shared__ CollideSmem<L, S, T, TOT, true> sm;
+  const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
+  collide_tile<L, S, T, true, FIELDS, TOT, true>(fin, fout, phi, scin, scout, fo, a, tc, sm, net);
 }
 
 }  // namespace lbm

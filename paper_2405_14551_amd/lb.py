@@ -19,7 +19,9 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENUMERIC, LB_ENODEV, LB_EUNSUPPORTED = 
 LATTICE = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32t": 4, "f16t": 5, "bf16t": 6}
 TOTAL_LAYOUTS = ("f32t", "f16t", "bf16t")
-NC_MODE = {"off": 0, "explicit": 1}
+NC_MODE = {"off": 0, "explicit": 1, "mlp": 2}
+MLP_PARAMS = 6339
+MLP_ROW = 32
 FIELD_BITS = {"rho_a": 0, "rho_b": 1, "phi": 2, "u": 3, "f_nc": 4, "flags": 5, "labels": 6}
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 
@@ -61,7 +63,8 @@ EXPORTED = [
     "lb_diagnostics", "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count",
     "lb_sync", "lb_destroy", "lb_lattice_table", "lb_error_string", "lb_last_error",
     "lb_profile_begin", "lb_profile_end", "lb_channel_count", "lb_get_tuning", "lb_set_tuning",
-    "lb_autotune",
+    "lb_autotune", "lb_nc_collect", "lb_mlp_set_weights", "lb_mlp_get_weights", "lb_mlp_set_ranges",
+    "lb_mlp_get_ranges", "lb_mlp_train", "lb_mlp_gradient", "lb_mlp_infer",
 ]
 
 
@@ -96,6 +99,16 @@ def lib():
     L.lb_get_tuning.argtypes = [vp, P(LbTuning)]
     L.lb_set_tuning.argtypes = [vp, P(LbTuning)]
     L.lb_autotune.argtypes = [vp, i, P(LbTuning), P(d), i, P(i)]
+    ll = ctypes.c_longlong
+    fp = P(ctypes.c_float)
+    L.lb_nc_collect.argtypes = [vp, i, vp, vp, ll, P(ll), P(ll)]
+    L.lb_mlp_set_weights.argtypes = [vp, fp, ll]
+    L.lb_mlp_get_weights.argtypes = [vp, fp, ll]
+    L.lb_mlp_set_ranges.argtypes = [vp, fp, fp, ctypes.c_float]
+    L.lb_mlp_get_ranges.argtypes = [vp, fp, fp, fp]
+    L.lb_mlp_train.argtypes = [vp, vp, vp, ll, vp, i, i, d, vp]
+    L.lb_mlp_gradient.argtypes = [vp, vp, vp, ll, vp, vp]
+    L.lb_mlp_infer.argtypes = [vp, vp, vp, ll]
     L.lb_error_string.argtypes = [i]
     L.lb_error_string.restype = ctypes.c_char_p
     L.lb_last_error.argtypes = []
@@ -103,7 +116,9 @@ def lib():
     for name in ["lb_create", "lb_init_droplets", "lb_step", "lb_fields", "lb_diagnostics",
                  "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count", "lb_sync",
                  "lb_destroy", "lb_lattice_table", "lb_profile_begin", "lb_profile_end",
-                 "lb_channel_count", "lb_get_tuning", "lb_set_tuning", "lb_autotune"]:
+                 "lb_channel_count", "lb_get_tuning", "lb_set_tuning", "lb_autotune", "lb_nc_collect",
+                 "lb_mlp_set_weights", "lb_mlp_get_weights", "lb_mlp_set_ranges", "lb_mlp_get_ranges",
+                 "lb_mlp_train", "lb_mlp_gradient", "lb_mlp_infer"]:
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -296,6 +311,86 @@ class Simulation:
         check(lib().lb_set_state(self.h, ctypes.c_void_p(t.data_ptr()), self.state_bytes(), 1))
         self.stream.synchronize()
         return self
+
+    # ---------------------------------------------------- learned closure
+    def _dev_f32(self, t, cols):
+        t = self.torch.as_tensor(t).to(device=self.device, dtype=self.torch.float32).contiguous()
+        if t.dim() != 2 or t.shape[1] != cols:
+            raise ValueError(f"expected an (m, {cols}) array")
+        return t
+
+    def nc_collect(self):
+        """Training rows of the last (explicit-force) step: (rows (m, 32),
+        targets (m, 3), m_active, m_free) as float32 device tensors, active
+        rows first."""
+        L = lib()
+        na, nf = ctypes.c_longlong(), ctypes.c_longlong()
+        check(L.lb_nc_collect(self.h, 0, None, None, 0, ctypes.byref(na), ctypes.byref(nf)))
+        m = na.value + nf.value
+        rows = self.torch.empty((max(m, 1), MLP_ROW), dtype=self.torch.float32, device=self.device)
+        tg = self.torch.empty((max(m, 1), 3), dtype=self.torch.float32, device=self.device)
+        check(L.lb_nc_collect(self.h, 0, ctypes.c_void_p(rows.data_ptr()), ctypes.c_void_p(tg.data_ptr()), m,
+                              ctypes.byref(na), ctypes.byref(nf)))
+        return rows[:m], tg[:m], na.value, nf.value
+
+    def mlp_set_weights(self, theta):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(-1))
+        check(lib().lb_mlp_set_weights(self.h, th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), th.size))
+        return self
+
+    def mlp_get_weights(self):
+        th = np.empty(MLP_PARAMS, dtype=np.float32)
+        check(lib().lb_mlp_get_weights(self.h, th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), th.size))
+        return th
+
+    def mlp_set_ranges(self, lo, hi, gmin):
+        fp = ctypes.POINTER(ctypes.c_float)
+        lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float32).reshape(30))
+        hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float32).reshape(30))
+        check(lib().lb_mlp_set_ranges(self.h, lo.ctypes.data_as(fp), hi.ctypes.data_as(fp), float(gmin)))
+        return self
+
+    def mlp_get_ranges(self):
+        fp = ctypes.POINTER(ctypes.c_float)
+        lo, hi, g = np.empty(30, np.float32), np.empty(30, np.float32), np.empty(1, np.float32)
+        check(lib().lb_mlp_get_ranges(self.h, lo.ctypes.data_as(fp), hi.ctypes.data_as(fp), g.ctypes.data_as(fp)))
+        return lo, hi, g[0]
+
+    def mlp_train(self, rows, targets, order, lr=1e-3):
+        """Adam over the mini-batches order[t] (int32 (n_steps, batch) row
+        indices); returns the per-step batch losses (float32 device tensor)."""
+        torch = self.torch
+        rows = self._dev_f32(rows, MLP_ROW)
+        targets = self._dev_f32(targets, 3)
+        order = torch.as_tensor(order).to(device=self.device, dtype=torch.int32).contiguous()
+        n_steps, batch = order.shape
+        log = torch.empty(max(n_steps, 1), dtype=torch.float32, device=self.device)
+        self.stream.synchronize()
+        check(lib().lb_mlp_train(self.h, ctypes.c_void_p(rows.data_ptr()), ctypes.c_void_p(targets.data_ptr()),
+                                 rows.shape[0], ctypes.c_void_p(order.data_ptr()), n_steps, batch, float(lr),
+                                 ctypes.c_void_p(log.data_ptr())))
+        return log[:n_steps]
+
+    def mlp_gradient(self, rows, targets):
+        """(loss, gradient) of the mean squared error over all rows."""
+        torch = self.torch
+        rows = self._dev_f32(rows, MLP_ROW)
+        targets = self._dev_f32(targets, 3)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        l = torch.empty(1, dtype=torch.float32, device=self.device)
+        self.stream.synchronize()
+        check(lib().lb_mlp_gradient(self.h, ctypes.c_void_p(rows.data_ptr()), ctypes.c_void_p(targets.data_ptr()),
+                                    rows.shape[0], ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(l.data_ptr())))
+        return float(l.item()), g
+
+    def mlp_infer(self, rows):
+        rows = self._dev_f32(rows, MLP_ROW)
+        out = self.torch.empty((rows.shape[0], 3), dtype=self.torch.float32, device=self.device)
+        self.stream.synchronize()
+        check(lib().lb_mlp_infer(self.h, ctypes.c_void_p(rows.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 rows.shape[0]))
+        self.stream.synchronize()
+        return out
 
 
 def _tuning_dict(t):

@@ -134,9 +134,8 @@ def big_3d_crop(storage="f32", crop=64, seed=SEED):
     return w
 
 
-def dense_3d(storage="f32", count=2000, radius=8.0):
-    shape = (384, 384, 192)
-    cen = fcc_slab_centres(shape, radius, count)
+def dense_3d(storage="f32", count=2000, radius=8.0, shape=(384, 384, 192), seed=SEED):
+    cen = fcc_slab_centres(shape, radius, count, seed=seed)
     return dict(lattice="D3Q27", storage=storage, nc="explicit", shape=shape, walls=(0, 0, 1),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(1e-6, 0.0, 0.0),
                 nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0,
@@ -196,3 +195,30 @@ def sim_kwargs(w):
     """Split a workload dict into Simulation kwargs and the droplet list."""
     kw = {k: v for k, v in w.items() if k not in ("centres", "radii")}
     return kw, w["centres"], w["radii"]
+
+
+def closure_init_weights(seed=SEED):
+    """Initial parameters of the near-contact closure network (30-64-64-3):
+    uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot), zero biases; packed
+    as W1, b1, W2, b2, W3, b3 (float32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fan_in, fan_out in ((30, 64), (64, 64), (64, 3)):
+        lim = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-lim, lim, fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def closure_batches(n_active, n_free, n_steps, batch, seed=SEED):
+    """Mini-batch row indices for training on collected rows (active rows
+    0 .. n_active-1, force-free rows after them): each batch draws half its
+    rows from the force-active and half from the force-free rows, uniformly
+    with replacement.  int32 array (n_steps, batch)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = batch // 2
+    if n_active == 0 or n_free == 0:
+        return rng.integers(0, n_active + n_free, (n_steps, batch)).astype(np.int32)
+    a = rng.integers(0, n_active, (n_steps, half))
+    f = n_active + rng.integers(0, n_free, (n_steps, batch - half))
+    return np.concatenate([a, f], axis=1).astype(np.int32)

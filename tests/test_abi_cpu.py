@@ -68,6 +68,9 @@ def _create(**kw):
     dict(nc="explicit", shape=(64, 3, 8)),
     dict(rho0=-1.0),
     dict(shape=(2048, 2048, 2048)),
+    dict(nc="mlp", lattice="D2Q9", shape=(16, 16, 1)),      # the learned closure is 3D
+    dict(nc="mlp", storage="f16"),                          # per-colour 16-bit storage
+    dict(nc="mlp", shape=(64, 3, 8)),
 ])
 def test_invalid_params_rejected(kw):
     assert _create(**kw) == lb.LB_EINVAL
@@ -112,3 +115,17 @@ def test_ensemble_argument_checks():
     arr[0] = lb.make_params(lattice="D3Q19", storage="f16", shape=(16, 8, 8))
     assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # per-colour 16-bit ensemble
     assert L.lb_create(arr, 0, None, ctypes.byref(h)) == lb.LB_EINVAL
+    arr[0] = lb.make_params(lattice="D3Q19", storage="f32", nc="mlp", shape=(16, 8, 8))
+    arr[1] = lb.make_params(lattice="D3Q19", storage="f32", nc="mlp", shape=(16, 8, 8))
+    assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # no closure in ensembles
+
+
+def test_closure_calls_reject_null_arguments():
+    L = lb.lib()
+    na, nf = ctypes.c_longlong(), ctypes.c_longlong()
+    assert L.lb_nc_collect(None, 0, None, None, 0, ctypes.byref(na), ctypes.byref(nf)) == lb.LB_EINVAL
+    assert L.lb_mlp_set_weights(None, None, lb.MLP_PARAMS) == lb.LB_EINVAL
+    assert L.lb_mlp_get_weights(None, None, lb.MLP_PARAMS) == lb.LB_EINVAL
+    assert L.lb_mlp_train(None, None, None, 1, None, 1, 32, 1e-3, None) == lb.LB_EINVAL
+    assert L.lb_mlp_gradient(None, None, None, 1, None, None) == lb.LB_EINVAL
+    assert L.lb_mlp_infer(None, None, None, 1) == lb.LB_EINVAL
