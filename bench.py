@@ -33,13 +33,19 @@ NSC_BYTES = 16  # recolouring scalars of the total layout, per site
 
 
 def algorithmic_bytes(q, storage):
-    """Per lattice update of the layout in use: its state read once and written
-    once, plus the phase field written once (pass 1) and read once (pass 2).
-    Collision pass alone: state read + written + phase read; phase pass: state
-    read + phase written.  The plain per-colour FP32 D3Q27 step is 440 B."""
+    """Per lattice update of the layout in use: (step, collision pass, phase
+    pass).  Step: the state read once and written once, plus the phase field
+    written once (pass 1) and read once (pass 2); the plain per-colour FP32
+    D3Q27 step is 440 B.  Phase pass: state read + phase written.  Collision
+    pass: populations read + state written + phase read (per-colour: the
+    whole state both ways; total layout: the scalars are written, not read,
+    since rho_A follows from phi)."""
     s = ELEM[storage]
     r = 8 if storage == "f64" else 4
-    state = (q * s + NSC_BYTES) if storage in TOTAL else 2 * q * s
+    if storage in TOTAL:
+        state = q * s + NSC_BYTES
+        return 2 * state + 2 * r, 2 * q * s + NSC_BYTES + r, state + r
+    state = 2 * q * s
     return 2 * state + 2 * r, 2 * state + r, state + r
 
 
@@ -101,6 +107,74 @@ def cpu_baseline(seconds_target=10.0):
                       f"(host nproc {os.cpu_count()})"}
 
 
+def time_storage(kw, cen, rad, storage, steps, warmup):
+    """MLUPS and per-launch pass times of the same workload with another
+    storage layout (HIP events on the library's stream)."""
+    import torch
+    from paper_2405_14551_amd import lb
+    sim = lb.Simulation(**dict(kw, storage=storage)).init_droplets(cen, rad)
+    sim.step(warmup)
+    sim.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sim.profile_begin()
+    with torch.cuda.stream(sim.stream):
+        e0.record(sim.stream)
+        sim.step(steps)
+        e1.record(sim.stream)
+    prof = sim.profile_end()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nx, ny, nz = kw["shape"]
+    sim.close()
+    return {"MLUPS": round(nx * ny * nz * steps / (ms / 1e3) / 1e6, 1),
+            "collide_ms": round(prof["ms_collide"] / max(prof["n_collide"], 1), 5),
+            "phase_ms": round(prof["ms_phase"] / max(prof["n_phase"], 1), 5)}
+
+
+def time_closure(kw, cen, rad, steps, warmup, explicit):
+    """The learned near-contact closure on the same workload: rows collected
+    after the warm-up with the explicit force, 500 Adam steps, then the step
+    with the closure in the collision pass.  Reports its collision-pass time
+    beside the explicit one and the share of interface sites the network
+    served."""
+    import torch
+    from paper_2405_14551_amd import lb, workloads as W
+    src = lb.Simulation(**dict(kw, nc="explicit")).init_droplets(cen, rad)
+    src.step(warmup)
+    rows, tg, na, nf = src.nc_collect()
+    src.close()
+    tr = lb.Simulation(lattice=kw["lattice"], storage="f32", nc="explicit", shape=(16, 16, 16))
+    tr.mlp_set_weights(W.closure_init_weights())
+    tr.mlp_train(rows, tg, torch.from_numpy(W.closure_batches(na, nf, 500, 256)), lr=2e-3)
+    th, ranges = tr.mlp_get_weights(), tr.mlp_get_ranges()
+    tr.close()
+    sim = lb.Simulation(**dict(kw, nc="mlp"))
+    sim.mlp_set_weights(th)
+    sim.mlp_set_ranges(*ranges)
+    sim.init_droplets(cen, rad)
+    sim.step(warmup)
+    sim.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sim.profile_begin()
+    with torch.cuda.stream(sim.stream):
+        e0.record(sim.stream)
+        sim.step(steps)
+        e1.record(sim.stream)
+    prof = sim.profile_end()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    fl = sim.fields(("flags",))["flags"]
+    n_if = int(((fl & 1) > 0).sum())
+    n_net = int(((fl & 2) > 0).sum())
+    nx, ny, nz = kw["shape"]
+    sim.close()
+    col = prof["ms_collide"] / max(prof["n_collide"], 1)
+    return {"MLUPS": round(nx * ny * nz * steps / (ms / 1e3) / 1e6, 1), "collide_ms": round(col, 5),
+            "explicit_collide_ms": explicit, "collide_time_vs_explicit": round(col / explicit, 3),
+            "training_rows": {"active": na, "free": nf}, "interface_sites": n_if,
+            "network_share": round(n_net / max(n_if, 1), 4)}
+
+
 def copy_calibration(nbytes=1 << 30, reps=10):
     """A plain device-to-device copy of known size: rocprofv3 FETCH_SIZE /
     WRITE_SIZE of these launches give the counter scale (ideal: nbytes each)."""
@@ -126,6 +200,8 @@ def main():
     ap.add_argument("--workload", default="channel_3d", choices=["channel_3d", "big_3d", "dense_3d"])
     ap.add_argument("--storage", default=None, help="f32 (default), f16, bf16, f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the 16-bit storage and learned-closure variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -203,9 +279,22 @@ def main():
                           "phase_pass_ms": round(ph_ms, 5), "phase_pass_GBs": round(b_phase * N / (ph_ms / 1e3) / 1e9, 1)},
         "sanity": {"droplets_end": int(diag[6]), "umax": float(diag[5])},
     }
+    sim.close()
+    if not args.no_variants and storage == "f32":
+        # same workload: total-population layouts (FP32 / FP16 / BF16 storage,
+        # FP32 arithmetic) and the learned near-contact closure
+        vs = min(args.steps, 200)
+        var = {}
+        for st in ("f32t", "f16t", "bf16t"):
+            var[st] = time_storage(kw, cen, rad, st, vs, args.warmup)
+            var[st]["vs_plain_f32"] = round(var[st]["MLUPS"] / mlups, 3)
+            print(f"# variant {st}: {var[st]}", file=sys.stderr, flush=True)
+        if kw.get("nc") == "explicit":
+            var["closure_f32"] = time_closure(kw, cen, rad, vs, args.warmup, col_ms)
+            print(f"# variant closure: {var['closure_f32']}", file=sys.stderr, flush=True)
+        out["variants"] = var
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
-    sim.close()
     print(json.dumps(out), flush=True)
     return 0
 

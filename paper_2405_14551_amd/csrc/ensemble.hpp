@@ -57,12 +57,19 @@ __device__ __forceinline__ StepArgs uniform_args(const StepArgs& in) {
 
 // one tile item per workgroup; `items` holds only phase items or only
 // collision items
+// LDS of an ensemble workgroup: a collision tile or a total-layout phase tile
+template <class L, class S, class T, bool TOT>
+union EnsembleSmem {
+  CollideSmem<L, S, T, TOT> c;
+  PhaseTotalSmem<Tile<T::TX, T::TY, 1, L::D>> p;
+};
+
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
 __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict__ chans,
                                                      const uint32_t* __restrict__ items, int parity) {
   using R = typename Storage<S>::real;
   using TS = Tile<T::TX, T::TY, 1, L::D>;
-  __shared__ CollideSmem<L, S, T, TOT> sm;
+  __shared__ EnsembleSmem<L, S, T, TOT> sm;
   const uint32_t e = __builtin_amdgcn_readfirstlane(items[blockIdx.x]);
   const uint32_t c = (e >> ITEM_CH_SHIFT) & ITEM_CH_MASK;
   const ChannelDev* C = chans + c;
@@ -75,7 +82,7 @@ __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict
   void* phi = uniform_ptr(C->phi);
   if (!(e & ITEM_COLLIDE)) {
     if constexpr (TOT) {
-      phase_total_tile<L, S, TS>(fin, scin, (float*)phi, a, tc, *reinterpret_cast<PhaseTotalSmem<TS>*>(sm.sring));
+      phase_total_tile<L, S, TS>(fin, scin, (float*)phi, a, tc, sm.p);
     } else {
       phase_tile<L, S>(fin, (R*)phi, a, tc, T::TX);
     }
@@ -86,7 +93,7 @@ __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict
     fo.u = uniform_ptr(C->fo.u);
     fo.fnc = uniform_ptr(C->fo.fnc);
     fo.flags = uniform_ptr(C->fo.flags);
-    collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, (const R*)phi, scin, scout, fo, a, tc, sm);
+    collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, (const R*)phi, scin, scout, fo, a, tc, sm.c);
   }
 }
 

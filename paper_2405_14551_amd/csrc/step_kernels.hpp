@@ -377,6 +377,9 @@ __device__ __forceinline__ void ring_gradient(const R* __restrict__ ring, int c0
 // equations make the colours exact functions of these:
 //   f^A_i = a f*_i + (w_i / |c_i|) c_i . b,   f^B_i = f*_i - f^A_i,
 // so pulling T and the scalars of x - c_i reproduces the two-colour pull.
+// Only the phase pass needs that reconstruction: the collision pass works on
+// the total and takes rho_A = rho (1 + phi) / 2 from the phase field, which the
+// phase pass formed from the same pulled populations.
 constexpr int NSC = 4;  // scalars per site: a, b_x, b_y, b_z
 
 template <class S>
@@ -543,14 +546,11 @@ __device__ __forceinline__ void phase_tile(const S* __restrict__ fin, typename S
 
 // ----------------------------------------------------------------------------
 // pass 2: gradient, flags, near contact, collision, recolouring, store
-// LDS of one collision tile: the phase-field ring and, for the total layout,
-// the scalar ring
+// LDS of one collision tile: the phase-field ring
 template <class L, class S, class T, bool TOT, bool MLP = false>
 struct CollideSmem {
   using R = typename Storage<S>::real;
-  using TS = Tile<T::TX, T::TY, 1, L::D>;
   R ring[T::NPL * T::PL];
-  float sring[TOT ? TS::NPL * ScalarRing<TS>::SLOT : 1];
 };
 // with the learned closure: the packed network and one row queue per wave
 template <class L, class S, class T, bool TOT>
@@ -574,9 +574,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
                                              const MlpPacked* __restrict__ net = nullptr) {
   static_assert(!MLP || (NC && L::D == 3), "the learned closure replaces the 3D near-contact scan");
   using R = typename Storage<S>::real;
-  using TS = Tile<T::TX, T::TY, 1, L::D>;   // scalar ring of the total layout
   R* ring = sm.ring;
-  float* sring = sm.sring;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + T::TX * ty;
   const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
   const int x = x0 + tx, y = y0 + ty;
@@ -585,16 +583,8 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   // stage planes z0 - RZ .. z0 + RZ; plane zz lives in slot plane_slot(zz)
   for (int dz = -T::RZ; dz <= T::RZ; ++dz)
     load_plane<T>(ring, plane_slot(z0 + dz, T::NPL), z0 + dz, phi, x0, y0, a, tid);
-  if constexpr (TOT) {
-    for (int dz = -TS::RZ; dz <= TS::RZ; ++dz) {
-      float v[ScalarRing<TS>::NPER];
-      fetch_scalars<TS>(v, z0 + dz, scin, x0, y0, a, tid);
-      commit_scalars<TS>(sring, plane_slot(z0 + dz, TS::NPL), v, tid);
-    }
-  }
   if constexpr (MLP) mlp_stage(sm.net, net, tid, T::NT);
   __syncthreads();
-  const int sc0 = (ty + 1) * TS::TXH + (tx + 1);
 
   const R omega = (R)a.omega, guo = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
   const R hshift = (R)a.half_rho0, phiI = (R)a.phi_I;
@@ -611,10 +601,6 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
     const bool more = T::RZ && z + 1 < z1;
     R nxt[T::NPER];
     if (more) fetch_plane<T>(nxt, z + 1 + T::RZ, phi, x0, y0, a, tid);
-    float snxt[TOT ? ScalarRing<TS>::NPER : 1];
-    if constexpr (TOT) {
-      if (more) fetch_scalars<TS>(snxt, z + 1 + TS::RZ, scin, x0, y0, a, tid);
-    }
     const int zc = plane_slot(z, T::NPL);
     if (MLP || valid_xy) {
       // ---- issue the pull first so that its latency overlaps the stencil
@@ -714,9 +700,6 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         if constexpr (TOT) {
-          const R da = colour_a<L, TS, I, R>(va[I], sring, n, plane_slot(z, TS::NPL), sc0, R(2) * hshift, hshift);
-          sa += da;
-          sb += va[I] - da;
           d[I] = va[I];
         } else {
           sa += va[I]; sb += vb[I];
@@ -732,8 +715,15 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         if constexpr (L::cz[I] != 0) jz += (R)L::cz[I] * d[I];
       });
       const R rho0 = R(2) * hshift;
-      const R ra = hshift + sa, rb = hshift + sb;
       const R rho = rho0 + drho;
+      if constexpr (TOT) {
+        // the phase pass formed phi from these same pulled populations, so
+        // rho_A = rho (1 + phi) / 2: no colour reconstruction is needed here
+        const R rA = R(0.5) * rho * (R(1) + phic);
+        sa = rA - hshift;
+        sb = (rho - rA) - hshift;
+      }
+      const R ra = hshift + sa, rb = hshift + sb;
       const R inv_rho = R(1) / rho;
       const R Fx = (R)a.fx + fnx, Fy = (R)a.fy + fny, Fz = (R)a.fz + fnz;
       const R ux = (jx + R(0.5) * Fx) * inv_rho;
@@ -825,9 +815,6 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       }
     }
     if (more) commit_plane<T>(ring, plane_slot(z + 1 + T::RZ, T::NPL), nxt, tid);
-    if constexpr (TOT) {
-      if (more) commit_scalars<TS>(sring, plane_slot(z + 1 + TS::RZ, TS::NPL), snxt, tid);
-    }
     __syncthreads();
   }
 }
