@@ -270,7 +270,10 @@ def main():
                    "near_contact": kw["nc"], "sites": N},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_collide (collision pass)",
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_vs_algorithmic": (round(traffic / (b_col * N), 3) if traffic else None),
+                     "kernel": "k_collide (collision pass)",
                      "bytes_per_site": b_col, "avg_launch_ms": round(col_ms, 5)},
         "step_roofline": {"bytes_per_site": b_step, "frac": round(mlups * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
                           "plain_state_bytes_per_site": plain_state_bytes(q, storage),

@@ -14,9 +14,17 @@ namespace lbm {
 enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32T = 4, ST_F16T = 5, ST_BF16T = 6 };
 inline bool is_total(int st) { return st >= ST_F32T; }
 
-// pass-2 tile: 64 x-sites (one wave per row) by 4 rows
-constexpr int TILE_X = 64;
-constexpr int TILE_Y = 4;
+// pass-2 tile: 64 x-sites (one wave per row) by 4 rows unless overridden at build time
+#ifndef LB_TILE_X
+#define LB_TILE_X 64
+#endif
+#ifndef LB_TILE_Y
+#define LB_TILE_Y 4
+#endif
+// collision tile: TILE_X x TILE_Y columns of sites, one thread each
+constexpr int TILE_X = LB_TILE_X;
+constexpr int TILE_Y = LB_TILE_Y;
+static_assert(TILE_X * TILE_Y == 256 && TILE_X % 64 == 0, "a collision tile is 256 threads, whole waves per row");
 
 struct LatticeOps {
   int q, d;
