@@ -534,24 +534,33 @@ static int ensemble_plan(lb_handle* h) {
   return LB_OK;
 }
 
-// enqueue one ensemble step with the given parity on stream s
+// enqueue one ensemble step with the given parity on stream s; while
+// profiling (never under capture) the phase launches and the collision
+// launches are timed separately
 static int ensemble_launch(lb_handle* h, bool fields, int parity, hipStream_t s) {
   const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
+  int rc = 0;
+  if ((rc = prof_mark(h, 0, true))) return rc;
   if (h->tune.mode == LB_ENSEMBLE_BATCHED) {
     HIP_TRY(h->ops->ensemble(h->p.storage, nc, fields, h->d_chans, h->d_items_ph, h->n_items_ph, parity, s));
+  } else {
+    for (lb_handle* c : h->chans) {
+      const StepArgs a = c->step_args();
+      HIP_TRY(h->ops->phase(h->p.storage, c->f[parity], c->sc[parity], c->phi, a, s));
+    }
+  }
+  if ((rc = prof_mark(h, 0, false))) return rc;
+  if ((rc = prof_mark(h, 1, true))) return rc;
+  if (h->tune.mode == LB_ENSEMBLE_BATCHED) {
     HIP_TRY(h->ops->ensemble(h->p.storage, nc, fields, h->d_chans, h->d_items_co, h->n_items_co, parity, s));
-    return LB_OK;
+  } else {
+    for (lb_handle* c : h->chans) {
+      const StepArgs a = c->step_args();
+      HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[parity],
+                              c->sc[1 - parity], c->phi, c->field_ptrs(), a, s));
+    }
   }
-  for (lb_handle* c : h->chans) {
-    const StepArgs a = c->step_args();
-    HIP_TRY(h->ops->phase(h->p.storage, c->f[parity], c->sc[parity], c->phi, a, s));
-  }
-  for (lb_handle* c : h->chans) {
-    const StepArgs a = c->step_args();
-    HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[parity],
-                            c->sc[1 - parity], c->phi, c->field_ptrs(), a, s));
-  }
-  return LB_OK;
+  return prof_mark(h, 1, false);
 }
 
 // capture two non-field steps (parity 0, then 1) into a graph
@@ -606,10 +615,8 @@ static int ensemble_step(lb_handle* h, int nsteps) {
       s += 2;
       continue;
     }
-    int rc = prof_mark(h, 1, true);
+    int rc = ensemble_launch(h, fields, h->cur, h->stream);
     if (rc) return rc;
-    if ((rc = ensemble_launch(h, fields, h->cur, h->stream))) return rc;
-    if ((rc = prof_mark(h, 1, false))) return rc;
     ensemble_advance(h, fields);
     s += 1;
     if (diag_now) {
