@@ -410,8 +410,10 @@ def step_window(params: OracleParams, fA, fB, site, radius=6):
     gradient at the near-contact scan points: 3 + 1 + 1), so with radius >= 6
     the window's own boundary (periodic wrap on periodic axes, a wall on
     walled axes, which coincides with the true wall where the window reaches
-    it) cannot influence the centre.  Returns (fA_site (q,), fB_site (q,),
-    fields dict at the site)."""
+    it) cannot influence the centre.  fA and fB may also be callables that
+    take the window's index arrays (iz, iy, ix) and return the window
+    (q, len(iz), len(iy), len(ix)), for states too large to hold on the host.
+    Returns (fA_site (q,), fB_site (q,), fields dict at the site)."""
     p = params
     n = (p.nx, p.ny, p.nz)
     lat = make_lattice(p.lattice)
@@ -439,10 +441,13 @@ def step_window(params: OracleParams, fA, fB, site, radius=6):
             centre.append(radius)
             walls.append(False)
     ix, iy, iz = idx
-    sub = np.ix_(np.arange(fA.shape[0]), iz, iy, ix)
+    if callable(fA):
+        wA, wB = fA(iz, iy, ix), fB(iz, iy, ix)
+    else:
+        sub = np.ix_(np.arange(fA.shape[0]), iz, iy, ix)
+        wA, wB = np.asarray(fA)[sub], np.asarray(fB)[sub]
     wp = p.replace(nx=len(ix), ny=len(iy), nz=len(iz), walls=tuple(walls))
-    sim = OracleSim(wp).set_state(np.asarray(fA)[sub].astype(np.float64),
-                                  np.asarray(fB)[sub].astype(np.float64))
+    sim = OracleSim(wp).set_state(np.asarray(wA, dtype=np.float64), np.asarray(wB, dtype=np.float64))
     sim.step()
     cx, cy, cz = centre
     fl = sim.fields()

@@ -131,7 +131,7 @@ struct lb_handle {
     a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
     a.wall_x = p.wall[0]; a.wall_y = p.wall[1]; a.wall_z = p.wall[2];
     a.N = N;
-    a.QN = (uint32_t)q * N;
+    a.QN = (uint64_t)q * N;
     a.omega = 1.0 / p.tau;
     a.guo = 1.0 - 0.5 / p.tau;
     a.A = p.A;
@@ -217,10 +217,14 @@ static int validate(const lb_params* p) {
   for (int a = 0; a < 3; ++a)
     if (p->wall[a] != 0 && p->wall[a] != 1) return fail(LB_EINVAL, "wall[%d] must be 0 or 1", a);
   const double N = (double)p->nx * p->ny * p->nz;
-  const int q = ops_for(p->lattice)->q;
-  if (N * q * storage_bytes(p->storage) >= 4294967295.0)
-    return fail(LB_EINVAL, "one colour block (Q * sites * element bytes = %.0f) must stay below 4 GiB: "
-                "population offsets are 32-bit", N * q * storage_bytes(p->storage));
+  // a pulled population is addressed within the planes of its velocity pair
+  // {i, opp(i)} with a 32-bit byte offset: 2 planes in 3D, up to 3 in D2Q9
+  const double span = p->lattice == LB_D2Q9 ? 3.0 : 2.0;
+  if (N * span * storage_bytes(p->storage) > 4294967295.0)
+    return fail(LB_EINVAL, "%.0f sites x %d bytes: the planes of one velocity pair (%.0f bytes) must stay "
+                "below 4 GiB (32-bit lane offsets)", N, storage_bytes(p->storage),
+                N * span * storage_bytes(p->storage));
+  if (N > 2147483647.0) return fail(LB_EINVAL, "at most 2^31 - 1 sites (droplet labels are int32)");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must exceed 1/2");
   if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive");
   if (!(p->phi_interface > 0.0 && p->phi_interface < 1.0)) return fail(LB_EINVAL, "phi_interface must lie in (0,1)");
@@ -417,7 +421,7 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
   InitArgs a{};
   a.nx = h->p.nx; a.ny = h->p.ny; a.nz = h->p.nz; a.dims = h->d;
   a.wall_x = h->p.wall[0]; a.wall_y = h->p.wall[1]; a.wall_z = h->p.wall[2];
-  a.N = h->N; a.QN = (uint32_t)h->q * h->N;
+  a.N = h->N; a.QN = (uint64_t)h->q * h->N;
   a.ndrop = n;
   a.width = width; a.phi_in = phi_in; a.rho0 = h->p.rho0;
   a.u0x = h->p.u0[0]; a.u0y = h->p.u0[1]; a.u0z = h->d == 3 ? h->p.u0[2] : 0.0;

@@ -16,7 +16,8 @@ namespace lbm {
 struct InitArgs {
   int nx, ny, nz, dims;
   int wall_x, wall_y, wall_z;
-  uint32_t N, QN;
+  uint32_t N;
+  uint64_t QN;     // elements per colour block
   int ndrop;
   double width, phi_in, rho0;
   double u0x, u0y, u0z;

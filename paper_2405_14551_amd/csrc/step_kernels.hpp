@@ -143,7 +143,7 @@ struct StepArgs {
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;
   uint32_t N;        // sites
-  uint32_t QN;       // Q * N (elements per colour)
+  uint64_t QN;       // Q * N (elements per colour block)
   double omega;      // 1/tau
   double guo;        // 1 - 1/(2 tau)
   double A;          // perturbation amplitude
@@ -222,27 +222,51 @@ __device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const StepArgs& a) 
   return n;
 }
 
-// element index (within one colour block) of the pulled population i at site n
+// The pulled population i comes from plane i of the upstream site or, under
+// bounce-back, from plane opp(i) of the site itself.  Both planes of the pair
+// {i, opp(i)} are addressed from one base (the lower plane), so a lane's
+// offset stays 32-bit while the colour block can exceed 4 GiB: only the
+// pair's span (2 planes in 3D, 3 in D2Q9) must stay below 4 GiB.
+template <class L, int I>
+constexpr int pair_lo() { return I < L::opp[I] ? I : L::opp[I]; }
+template <class L, int I>
+constexpr int pair_span() { return (I < L::opp[I] ? L::opp[I] - I : I - L::opp[I]) + 1; }
+
+// element offset, from plane pair_lo, of the pulled population i at site n.
 // Branch-free on purpose: a divergent branch here makes the compiler wait for
 // the loads already in flight at every merge point, serialising the pull.
 template <class L, int I>
 __device__ __forceinline__ uint32_t pull_index(const Nbr& n, uint32_t N) {
   constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
+  constexpr uint32_t lo = pair_lo<L, I>();
   const uint32_t solid = (uint32_t)n.solid_x[ix] | (uint32_t)n.solid_y[iy] | (uint32_t)n.solid_z[iz];
-  const uint32_t moving = (uint32_t)I * N + (n.xs[ix] + n.ys[iy] + n.zs[iz]);
-  const uint32_t bounced = (uint32_t)L::opp[I] * N + n.site;
+  const uint32_t moving = (uint32_t)(I - lo) * N + (n.xs[ix] + n.ys[iy] + n.zs[iz]);
+  const uint32_t bounced = (uint32_t)(L::opp[I] - lo) * N + n.site;
   return moving ^ ((moving ^ bounced) & (0u - solid));
 }
 
-// Same index with the select written directly.  The phase pass measures
+// Same offset with the select written directly.  The phase pass measures
 // faster with this form than with the branch-free one.
 template <class L, int I>
 __device__ __forceinline__ uint32_t pull_index_sel(const Nbr& n, uint32_t N) {
   constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
+  constexpr uint32_t lo = pair_lo<L, I>();
   const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
   const uint32_t src = n.xs[ix] + n.ys[iy] + n.zs[iz];
-  return solid ? (uint32_t)L::opp[I] * N + n.site : (uint32_t)I * N + src;
+  return solid ? (uint32_t)(L::opp[I] - lo) * N + n.site : (uint32_t)(I - lo) * N + src;
 }
+
+// first plane of the pair of direction i in a block of Q planes at f
+template <class L, int I, class S>
+__device__ __forceinline__ const S* pair_base(const S* f, uint32_t N) {
+  return f + (size_t)pair_lo<L, I>() * N;
+}
+// buffer resource over the pair's planes
+template <class L, int I, class S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pair_rsrc(const S* f, uint32_t N) {
+  return make_rsrc(pair_base<L, I>(f, N), (uint32_t)pair_span<L, I>() * N * (uint32_t)sizeof(S));
+}
+
 
 // ----------------------------------------------------------------------------
 // pass 1: phase field of the post-streaming populations
@@ -262,11 +286,12 @@ __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
   const Nbr n = make_nbr(x, y, z, a);
   const R h = (R)a.half_rho0;
   R sa = 0, sb = 0;  // sums of the shifted populations: rho_k = rho0/2 + s_k
+  const S* finB = fin + a.QN;
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const uint32_t e = pull_index_sel<L, I>(n, a.N);
-    sa += Storage<S>::template load<I, L>(fin + e, h);
-    sb += Storage<S>::template load<I, L>(fin + a.QN + e, h);
+    sa += Storage<S>::template load<I, L>(pair_base<L, I>(fin, a.N) + e, h);
+    sb += Storage<S>::template load<I, L>(pair_base<L, I>(finB, a.N) + e, h);
   });
   phi[n.site] = (sa - sb) / (R(2) * h + (sa + sb));
 }
@@ -494,10 +519,9 @@ __device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, cons
     if (valid_xy) {
       const Nbr n = make_nbr(x, y, z, a);
       float Tv[L::Q];
-      const auto rT = make_rsrc(fin, a.QN * (uint32_t)sizeof(S));
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        Tv[I] = total_bload<S>(rT, pull_index<L, I>(n, a.N) * (uint32_t)sizeof(S));
+        Tv[I] = total_bload<S>(pair_rsrc<L, I>(fin, a.N), pull_index<L, I>(n, a.N) * (uint32_t)sizeof(S));
       });
       const int zcs = plane_slot(z, TS::NPL);
       float sa = 0.f, sb = 0.f;
@@ -534,11 +558,12 @@ __device__ __forceinline__ void phase_tile(const S* __restrict__ fin, typename S
   for (int z = tc.z0; z < tc.z1; ++z) {
     const Nbr n = make_nbr(x, y, z, a);
     R sa = 0, sb = 0;
+    const S* finB = fin + a.QN;
     static_for<0, L::Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       const uint32_t e = pull_index_sel<L, I>(n, a.N);
-      sa += Storage<S>::template load<I, L>(fin + e, h);
-      sb += Storage<S>::template load<I, L>(fin + a.QN + e, h);
+      sa += Storage<S>::template load<I, L>(pair_base<L, I>(fin, a.N) + e, h);
+      sb += Storage<S>::template load<I, L>(pair_base<L, I>(finB, a.N) + e, h);
     });
     phi[n.site] = (sa - sb) / (R(2) * h + (sa + sb));
   }
@@ -589,11 +614,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   const R omega = (R)a.omega, guo = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
   const R hshift = (R)a.half_rho0, phiI = (R)a.phi_I;
   const int c0 = (ty + T::RAD) * T::TXH + (tx + T::RAD);
-  // populations through buffer resources: one 32-bit lane offset per direction
-  // serves both colours, stores take the direction offset in an SGPR
-  constexpr uint32_t ES = TOT ? (uint32_t)sizeof(S) : Storage<S>::ES;
-  const auto rinA = make_rsrc(fin, a.QN * ES), rinB = make_rsrc(fin + (TOT ? 0 : a.QN), a.QN * ES);
-  const auto routA = make_rsrc(fout, a.QN * ES), routB = make_rsrc(fout + (TOT ? 0 : a.QN), a.QN * ES);
+  // populations through buffer resources over velocity pairs: one 32-bit lane
+  // offset per direction serves both colours; the bases are uniform and live
+  // in SGPRs
+  constexpr uint32_t ES = (uint32_t)sizeof(S);
 
   for (int z = z0; z < z1; ++z) {
     // prefetch the plane the next iteration needs into registers; it goes to
@@ -602,6 +626,15 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
     R nxt[T::NPER];
     if (more) fetch_plane<T>(nxt, z + 1 + T::RZ, phi, x0, y0, a, tid);
     const int zc = plane_slot(z, T::NPL);
+    // colour-block bases, opaque to the optimiser inside the loop: the ~100
+    // pair and plane descriptors derived from them are then built next to
+    // their use (a few scalar instructions each) instead of being hoisted out
+    // of the loop and spilled
+    const S* finA = fin;
+    S* foutA = fout;
+    asm volatile("" : "+s"(finA), "+s"(foutA));
+    const S* finB = finA + (TOT ? 0 : a.QN);
+    S* foutB = foutA + (TOT ? 0 : a.QN);
     if (MLP || valid_xy) {
       // ---- issue the pull first so that its latency overlaps the stencil
       // work below: both colours (shifted by w_i rho0/2 each), or the total
@@ -611,10 +644,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         constexpr int I = decltype(ic)::value;
         const uint32_t vo = pull_index<L, I>(n, a.N) * ES;
         if constexpr (TOT) {
-          va[I] = (R)total_bload<S>(rinA, vo);
+          va[I] = (R)total_bload<S>(pair_rsrc<L, I>(finA, a.N), vo);
         } else {
-          va[I] = Storage<S>::template bload<I, L>(rinA, vo, hshift);
-          vb[I] = Storage<S>::template bload<I, L>(rinB, vo, hshift);
+          va[I] = Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finA, a.N), vo, hshift);
+          vb[I] = Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), vo, hshift);
         }
       });
       const int p0 = zc * T::PL;
@@ -758,15 +791,17 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         if constexpr (MLP) {
           if (!valid_xy) return;
         }
-        const uint32_t vo = n.site * ES, so = (uint32_t)I * a.N * ES;
+        // stores go through the pair buffers too, the plane's offset in the
+        // scalar offset operand
+        const uint32_t vo = n.site * ES, so = (uint32_t)(I - pair_lo<L, I>()) * a.N * ES;
         if constexpr (TOT) {
-          total_bstore<S>(routA, vo, so, (float)ds);
+          total_bstore<S>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, (float)ds);
         } else {
           const R wi = (R)L::w[I];
           const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
           const R db = ds - da;
-          Storage<S>::template bstore<I, L>(routA, vo, so, da, hshift);
-          Storage<S>::template bstore<I, L>(routB, vo, so, db, hshift);
+          Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
+          Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
         }
       };
       {
