@@ -98,7 +98,9 @@ struct Launch {
   static hipError_t collide_mlp_t(const void* fin, void* fout, const float* scin, float* scout, const void* phi,
                                   const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
     using R = typename Storage<S>::real;
-    using T = Tile<TILE_X, TILE_Y, 4, L::D>;
+    // radius-1 phase ring: the network needs the 3x3x3 neighbourhood; the
+    // explicit scan for sites outside its range reads the phase field from memory
+    using T = Tile<TILE_X, TILE_Y, 1, L::D>;
     dim3 block(T::TX, T::TY, 1);
     const int zb = a.z_per_block;
     StepArgs b = a;

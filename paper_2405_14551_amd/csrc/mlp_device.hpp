@@ -150,9 +150,12 @@ __device__ __forceinline__ void mlp_stage(MlpPacked& dst, const MlpPacked* __res
 }
 
 // Evaluate the network for every lane with `want` set, 16 lanes at a time;
-// all 64 lanes must call it.  Returns the outputs in out[0..2] for those
-// lanes (untouched otherwise).
-__device__ __forceinline__ void mlp_wave_apply(const MlpPacked& W, MlpQueue& q, bool want, const float* xin,
+// all 64 lanes must call it.  inputs(xin) fills a lane's 30 inputs; it is
+// called only when the lane's row is queued, so the inputs are not held in
+// registers across the evaluation.  Returns the outputs in out[0..2] for
+// those lanes (untouched otherwise).
+template <class Inputs>
+__device__ __forceinline__ void mlp_wave_apply(const MlpPacked& W, MlpQueue& q, bool want, Inputs&& inputs,
                                                float* out) {
   const int lane = __lane_id();
   const uint64_t mask = __ballot(want);
@@ -160,7 +163,11 @@ __device__ __forceinline__ void mlp_wave_apply(const MlpPacked& W, MlpQueue& q, 
   const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
   for (int base = 0; base < cnt; base += 16) {
     const bool mine = want && slot >= base && slot < base + 16;
-    if (mine) mlp_queue_row(q, slot - base, xin);
+    if (mine) {
+      float xin[MLP_IN];
+      inputs(xin);
+      mlp_queue_row(q, slot - base, xin);
+    }
     wave_lds_sync();
     const f32x4 o = mlp_eval16(W, q, lane);
     wave_lds_sync();   // the queue is rewritten in the next round

@@ -267,10 +267,10 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const MlpPacked* __restrict__
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long long r = ((long long)blockIdx.x * 4 + wv) * 16 + (lane & 15);
   const bool have = lane < 16 && r < m;
-  float xin[MLP_IN];
-  for (int k = 0; k < MLP_IN; ++k) xin[k] = have ? rows[r * MLP_ROW + k] : 0.0f;
   float o[3] = {0.0f, 0.0f, 0.0f};
-  mlp_wave_apply(W, q[wv], have, xin, o);
+  mlp_wave_apply(W, q[wv], have, [&](float* xin) {
+    for (int k = 0; k < MLP_IN; ++k) xin[k] = rows[r * MLP_ROW + k];
+  }, o);
   if (have) {
     out[r * MLP_OUT + 0] = o[0];
     out[r * MLP_OUT + 1] = o[1];

@@ -394,6 +394,55 @@ __device__ __forceinline__ void ring_gradient(const R* __restrict__ ring, int c0
   });
 }
 
+// phase field at a site within one layer beyond the lattice, read from memory
+// with the ring's halo rule (periodic wrap, mirrored wall ghosts)
+template <class R>
+__device__ __forceinline__ R phi_global(const R* __restrict__ phi, int x, int y, int z, const StepArgs& a) {
+  const uint32_t gx = halo_coord(x, a.nx, a.wall_x), gy = halo_coord(y, a.ny, a.wall_y);
+  const uint32_t gz = halo_coord(z, a.nz, a.wall_z);
+  return phi[gx + (uint32_t)a.nx * (gy + (uint32_t)a.ny * gz)];
+}
+
+// colour gradient at (x, y, z) from memory, summed in the order of ring_gradient
+template <class L, class R>
+__device__ __forceinline__ void global_gradient(const R* __restrict__ phi, int x, int y, int z, const StepArgs& a,
+                                                R& gx, R& gy, R& gz) {
+  gx = 0; gy = 0; gz = 0;
+  static_for<1, L::Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+    const R v = phi_global(phi, x + cx, y + cy, z + cz, a) * (R)(3.0 * L::w[I]);
+    if constexpr (cx != 0) gx += (R)cx * v;
+    if constexpr (cy != 0) gy += (R)cy * v;
+    if constexpr (cz != 0) gz += (R)cz * v;
+  });
+}
+
+// the explicit near-contact scan (Eq. near_cont_force) on the phase field in
+// memory: the distance h of the first opposing interface along -g/|g| within
+// floor(h_max) sites, 0 if none (a wall ends the scan)
+template <class L, class R>
+__device__ __forceinline__ int nc_scan_global(const R* __restrict__ phi, int x, int y, int z, R gx, R gy, R gz, R gg,
+                                           R phiI, const StepArgs& a) {
+  const R inv = R(1) / sqrt(gg);
+  const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
+  for (int s = 1; s <= a.nc_steps; ++s) {
+    const int ox = max(-3, min(3, (int)round_half_away((R)s * mx)));
+    const int oy = max(-3, min(3, (int)round_half_away((R)s * my)));
+    const int oz = max(-3, min(3, (int)round_half_away((R)s * mz)));
+    if (a.wall_x && (x + ox < 0 || x + ox >= a.nx)) return 0;
+    if (a.wall_y && (y + oy < 0 || y + oy >= a.ny)) return 0;
+    if (a.wall_z && (z + oz < 0 || z + oz >= a.nz)) return 0;
+    const R phy = phi_global(phi, x + ox, y + oy, z + oz, a);
+    if (fabs(phy) < phiI) {
+      R hx, hy, hz;
+      global_gradient<L, R>(phi, x + ox, y + oy, z + oz, a, hx, hy, hz);
+      if (hx * gx + hy * gy + hz * gz < R(0)) return s;
+    }
+  }
+  return 0;
+}
+
 // ----------------------------------------------------------------------------
 // Total layout.  Instead of the two colours, HBM holds the total post-collision
 // population T_i = f*_i - w_i rho0 (shifted by the rest equilibrium, in the
@@ -669,25 +718,31 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         // learned closure: inputs phi on the 3x3x3 neighbourhood (x fastest)
         // and g/|g| in FP32; used where all lie in the training range
         const bool cand = valid_xy && flag && has_g;
-        float xin[MLP_IN];
-        int k = 0;
-#pragma unroll
-        for (int dz = -1; dz <= 1; ++dz) {
-          const int pz = ring_slot(zc, dz, T::NPL) * T::PL;
-#pragma unroll
-          for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) xin[k++] = (float)ring[pz + c0 + dy * T::TXH + dx];
-        }
         const R gnr = sqrt(gg);
-        xin[27] = (float)(gx / gnr);
-        xin[28] = (float)(gy / gnr);
-        xin[29] = (float)(gz / gnr);
-        bool inr = cand && (float)gnr >= sm.net.gmin;
+        auto inputs = [&](float* xin) {
+          int k = 0;
 #pragma unroll
-        for (int q = 0; q < MLP_IN; ++q) inr = inr && xin[q] >= sm.net.lo[q] && xin[q] <= sm.net.hi[q];
+          for (int dz = -1; dz <= 1; ++dz) {
+            const int pz = ring_slot(zc, dz, T::NPL) * T::PL;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+              for (int dx = -1; dx <= 1; ++dx) xin[k++] = (float)ring[pz + c0 + dy * T::TXH + dx];
+          }
+          xin[27] = (float)(gx / gnr);
+          xin[28] = (float)(gy / gnr);
+          xin[29] = (float)(gz / gnr);
+        };
+        // range test, one input at a time
+        bool inr = cand && (float)gnr >= sm.net.gmin;
+        if (inr) {
+          float xin[MLP_IN];
+          inputs(xin);
+#pragma unroll
+          for (int q = 0; q < MLP_IN; ++q) inr = inr && xin[q] >= sm.net.lo[q] && xin[q] <= sm.net.hi[q];
+        }
         float o[3] = {0.f, 0.f, 0.f};
-        mlp_wave_apply(sm.net, sm.queue[tid >> 6], inr, xin, o);
+        mlp_wave_apply(sm.net, sm.queue[tid >> 6], inr, inputs, o);
         use_net = inr;
         if (inr) {
           // the network gives the force per unit strength and |g|
@@ -697,27 +752,34 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       }
       if constexpr (NC) {
         if (flag && has_g && (!MLP || (valid_xy && !use_net))) {
-          const R inv = R(1) / sqrt(gg);
-          const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
           int hit = 0;
-          for (int s = 1; s <= a.nc_steps; ++s) {
-            // |s m| <= 3; the clamp only guards the LDS index against non-finite m
-            const int ox = max(-3, min(3, (int)round_half_away((R)s * mx)));
-            const int oy = max(-3, min(3, (int)round_half_away((R)s * my)));
-            const int oz = max(-3, min(3, (int)round_half_away((R)s * mz)));
-            if (a.wall_x && (x + ox < 0 || x + ox >= a.nx)) break;
-            if (a.wall_y && (y + oy < 0 || y + oy >= a.ny)) break;
-            if (a.wall_z && (z + oz < 0 || z + oz >= a.nz)) break;
-            const int cy0 = c0 + oy * T::TXH + ox;
-            const int py0 = ring_slot(zc, oz, T::NPL) * T::PL;
-            const R phy = ring[py0 + cy0];
-            if (fabs(phy) < phiI) {
-              const int pym = T::RZ ? ring_slot(zc, oz - 1, T::NPL) * T::PL : py0;
-              const int pyp = T::RZ ? ring_slot(zc, oz + 1, T::NPL) * T::PL : py0;
-              R hx, hy, hz;
-              ring_gradient<L, T, R>(ring, cy0, pym, py0, pyp, hx, hy, hz);
-              if (hx * gx + hy * gy + hz * gz < R(0)) { hit = s; break; }
+          if constexpr (T::RAD >= 4) {
+            const R inv = R(1) / sqrt(gg);
+            const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
+            for (int s = 1; s <= a.nc_steps; ++s) {
+              // |s m| <= 3; the clamp only guards the LDS index against non-finite m
+              const int ox = max(-3, min(3, (int)round_half_away((R)s * mx)));
+              const int oy = max(-3, min(3, (int)round_half_away((R)s * my)));
+              const int oz = max(-3, min(3, (int)round_half_away((R)s * mz)));
+              if (a.wall_x && (x + ox < 0 || x + ox >= a.nx)) break;
+              if (a.wall_y && (y + oy < 0 || y + oy >= a.ny)) break;
+              if (a.wall_z && (z + oz < 0 || z + oz >= a.nz)) break;
+              const int cy0 = c0 + oy * T::TXH + ox;
+              const int py0 = ring_slot(zc, oz, T::NPL) * T::PL;
+              const R phy = ring[py0 + cy0];
+              if (fabs(phy) < phiI) {
+                const int pym = T::RZ ? ring_slot(zc, oz - 1, T::NPL) * T::PL : py0;
+                const int pyp = T::RZ ? ring_slot(zc, oz + 1, T::NPL) * T::PL : py0;
+                R hx, hy, hz;
+                ring_gradient<L, T, R>(ring, cy0, pym, py0, pyp, hx, hy, hz);
+                if (hx * gx + hy * gy + hz * gz < R(0)) { hit = s; break; }
+              }
             }
+          } else {
+            // a radius-1 ring (the learned closure's tile): the scan reads
+            // the phase field from memory; it serves only sites outside the
+            // closure's range
+            hit = nc_scan_global<L, R>(phi, x, y, z, gx, gy, gz, gg, phiI, a);
           }
           if (hit) {
             const R h = (R)hit, hmin = (R)a.nc_hmin;
@@ -866,7 +928,7 @@ __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S*
 
 // collision pass with the learned near-contact closure
 template <class L, class S, class T, bool FIELDS, bool TOT>
-__global__ void __launch_bounds__(T::NT) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
+__global__ void __launch_bounds__(T::NT, 3) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
                                                         const typename Storage<S>::real* __restrict__ phi,
                                                         const float* __restrict__ scin, float* __restrict__ scout,
                                                         FieldPtrs fo, StepArgs a, const MlpPacked* __restrict__ net) {
