@@ -157,6 +157,34 @@ def test_fp64_random_state_one_step(lat, shape, walls):
     sim.close()
 
 
+@pytest.mark.parametrize("lat,shape,walls", [("D3Q27", (9, 7, 5), (0, 1, 1)), ("D2Q9", (5, 4, 1), (1, 0, 0))])
+def test_fp64_degenerate_cases(lat, shape, walls):
+    """Degenerate inputs: no droplets (the uniform continuous phase, phi = -1
+    everywhere, no interface); the single-fluid limit A = beta = 0 with an
+    interface present (no surface tension, no recolouring split); a lattice
+    barely larger than the near-contact stencil.  FP64 parity with the oracle
+    after 20 steps."""
+    nx, ny, nz = shape
+    d3 = lat != "D2Q9"
+    for label, kw_extra, cen, rad in [
+        ("no droplets", dict(A=0.01, beta=0.7), np.zeros((0, 3)), np.zeros(0)),
+        ("A = beta = 0", dict(A=0.0, beta=0.0), np.array([[nx / 2 + 0.3, ny / 2 - 0.2, nz / 2 + 0.1 if d3 else 0.0]]),
+         np.array([1.6])),
+    ]:
+        kw = dict(lattice=lat, storage="f64", nc="explicit", shape=shape, walls=walls, tau=0.8,
+                  body_force=(1e-4, 0, 0), u0=(0.01, 0.0, 0.0), **kw_extra)
+        say(f"case degenerate {lat} {shape}: {label}")
+        sim, orc = run_pair(kw, cen, rad, 20)
+        fA, fB = gpu_state(sim)
+        assert rel(fA, orc.fA) < 1e-12 and rel(fB, orc.fB) < 1e-12, label
+        g = gpu_fields(sim)
+        assert np.array_equal(g["flags"].astype(bool), orc.fields()["flags"]), label
+        if label == "no droplets":
+            assert not g["flags"].any() and np.all(g["phi"] < -0.999999)
+            assert np.abs(fA).max() < 1e-14      # colour A absent: only rounding of the shifted sums
+        sim.close()
+
+
 def test_laplace_case_fp64_1000_steps():
     """128x64 D2Q9 droplet R=16, 1000 FP64 steps: parity with the oracle and the
     Laplace law (within 10% of sigma/R, sigma = (4/9) A tau)."""
