@@ -477,22 +477,29 @@ __device__ __forceinline__ void total_store<float>(float* p, float v) { __builti
 template <class TS>
 struct ScalarRing {
   static constexpr int SLOT = NSC * TS::PL;
-  static constexpr int NPER = (SLOT + TS::NT - 1) / TS::NT;
+  static constexpr int NPC = (TS::PL + TS::NT - 1) / TS::NT;  // plane elements per thread and channel
+  static constexpr int NPER = NSC * NPC;
 };
 
+// one plane of the four scalar channels for the tile plus halo: each thread
+// takes NPC halo positions and loads all four channels there, each channel
+// through its own buffer (32-bit offsets for any lattice below 2^30 sites)
 template <class TS>
 __device__ __forceinline__ void fetch_scalars(float (&v)[ScalarRing<TS>::NPER], int zz, const float* __restrict__ sc,
                                               int x0, int y0, const StepArgs& a, int tid) {
-  const int gz = halo_coord(zz, a.nz, a.wall_z);
-  const size_t zoff = (size_t)gz * a.nx * a.ny;
+  const uint32_t gz = halo_coord(zz, a.nz, a.wall_z);
+  const uint32_t zoff = gz * (uint32_t)a.nx * (uint32_t)a.ny;
 #pragma unroll
-  for (int k = 0; k < ScalarRing<TS>::NPER; ++k) {
-    const int e = min(tid + k * TS::NT, ScalarRing<TS>::SLOT - 1);
-    const int ch = e / TS::PL, rr = e - ch * TS::PL;
+  for (int k = 0; k < ScalarRing<TS>::NPC; ++k) {
+    const int rr = min(tid + k * TS::NT, TS::PL - 1);
     const int hy = rr / TS::TXH, hx = rr - hy * TS::TXH;
-    const int gx = halo_coord(x0 - TS::RAD + hx, a.nx, a.wall_x);
-    const int gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
-    v[k] = sc[(size_t)ch * a.N + zoff + (size_t)gy * a.nx + gx];
+    const uint32_t gx = halo_coord(x0 - TS::RAD + hx, a.nx, a.wall_x);
+    const uint32_t gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
+    const uint32_t off = (zoff + gy * (uint32_t)a.nx + gx) * 4u;
+#pragma unroll
+    for (int ch = 0; ch < NSC; ++ch)
+      v[ch * ScalarRing<TS>::NPC + k] = __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(sc + (size_t)ch * a.N, a.N * 4u), off, 0, 0));
   }
 }
 
@@ -501,9 +508,12 @@ __device__ __forceinline__ void commit_scalars(float* __restrict__ sring, int sl
                                                const float (&v)[ScalarRing<TS>::NPER], int tid) {
   float* dst = sring + slot * ScalarRing<TS>::SLOT;
 #pragma unroll
-  for (int k = 0; k < ScalarRing<TS>::NPER; ++k) {
-    const int e = tid + k * TS::NT;
-    if (e < ScalarRing<TS>::SLOT) dst[e] = v[k];
+  for (int k = 0; k < ScalarRing<TS>::NPC; ++k) {
+    const int rr = tid + k * TS::NT;
+    if (rr < TS::PL) {
+#pragma unroll
+      for (int ch = 0; ch < NSC; ++ch) dst[ch * TS::PL + rr] = v[ch * ScalarRing<TS>::NPC + k];
+    }
   }
 }
 
@@ -530,8 +540,8 @@ __device__ __forceinline__ R colour_a(R T, const float* __restrict__ sring, cons
     if constexpr (cy != 0) cb += (R)cy * (R)q[2 * TS::PL];
     if constexpr (cz != 0) cb += (R)cz * (R)q[3 * TS::PL];
     // the bounced population moved along -c_i before the wall reversed it
-    const R sign = R(1) - R(2) * (R)solid;
-    v += sign * (R)(L::w[I] * inv_norm<L>(I)) * cb;
+    const R t = (R)(L::w[I] * inv_norm<L>(I)) * cb;
+    v += solid ? -t : t;
   }
   return v;
 }
@@ -565,12 +575,15 @@ __device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, cons
     const bool more = TS::RZ && z + 1 < z1;
     float nxt[ScalarRing<TS>::NPER];
     if (more) fetch_scalars<TS>(nxt, z + 1 + TS::RZ, scin, x0, y0, a, tid);
+    // opaque base: the pair descriptors are built next to their use
+    const S* finT = fin;
+    asm volatile("" : "+s"(finT));
     if (valid_xy) {
       const Nbr n = make_nbr(x, y, z, a);
       float Tv[L::Q];
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        Tv[I] = total_bload<S>(pair_rsrc<L, I>(fin, a.N), pull_index<L, I>(n, a.N) * (uint32_t)sizeof(S));
+        Tv[I] = total_bload<S>(pair_rsrc<L, I>(finT, a.N), pull_index<L, I>(n, a.N) * (uint32_t)sizeof(S));
       });
       const int zcs = plane_slot(z, TS::NPL);
       float sa = 0.f, sb = 0.f;
