@@ -289,9 +289,9 @@ __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
   const S* finB = fin + a.QN;
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    const uint32_t e = pull_index_sel<L, I>(n, a.N);
-    sa += Storage<S>::template load<I, L>(pair_base<L, I>(fin, a.N) + e, h);
-    sb += Storage<S>::template load<I, L>(pair_base<L, I>(finB, a.N) + e, h);
+    const uint32_t e = pull_index_sel<L, I>(n, a.N) * (uint32_t)sizeof(S);
+    sa += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(fin, a.N), e, h);
+    sb += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), e, h);
   });
   phi[n.site] = (sa - sb) / (R(2) * h + (sa + sb));
 }
@@ -322,18 +322,28 @@ __device__ __forceinline__ int halo_coord(int g, int n, int wall) {
   return wall ? mirrored : wrapped;
 }
 
+// phase value at element offset `e` (32-bit) of the field at phi
+template <class R>
+__device__ __forceinline__ R phi_bload(const R* phi, uint32_t N, uint32_t e) {
+  const auto r = make_rsrc(phi, N * (uint32_t)sizeof(R));
+  if constexpr (sizeof(R) == 8)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8u, 0, 0));
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4u, 0, 0));
+}
+
 template <class T, class R>
 __device__ __forceinline__ void load_plane(R* __restrict__ ring, int slot, int zz,
                                            const R* __restrict__ phi, int x0, int y0,
                                            const StepArgs& a, int tid) {
-  const int gz = halo_coord(zz, a.nz, a.wall_z);
-  const size_t zoff = (size_t)gz * a.nx * a.ny;
+  const uint32_t gz = halo_coord(zz, a.nz, a.wall_z);
+  const uint32_t zoff = gz * (uint32_t)a.nx * (uint32_t)a.ny;
   R* dst = ring + slot * T::PL;
   for (int e = tid; e < T::PL; e += T::NT) {
     const int hy = e / T::TXH, hx = e - hy * T::TXH;
-    const int gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
-    const int gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
-    dst[e] = phi[zoff + (size_t)gy * a.nx + gx];
+    const uint32_t gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
+    const uint32_t gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
+    dst[e] = phi_bload(phi, a.N, zoff + gy * (uint32_t)a.nx + gx);
   }
 }
 
@@ -341,15 +351,15 @@ __device__ __forceinline__ void load_plane(R* __restrict__ ring, int slot, int z
 template <class T, class R>
 __device__ __forceinline__ void fetch_plane(R (&v)[T::NPER], int zz, const R* __restrict__ phi, int x0, int y0,
                                             const StepArgs& a, int tid) {
-  const int gz = halo_coord(zz, a.nz, a.wall_z);
-  const size_t zoff = (size_t)gz * a.nx * a.ny;
+  const uint32_t gz = halo_coord(zz, a.nz, a.wall_z);
+  const uint32_t zoff = gz * (uint32_t)a.nx * (uint32_t)a.ny;
 #pragma unroll
   for (int k = 0; k < T::NPER; ++k) {
     const int e = min(tid + k * T::NT, T::PL - 1);  // surplus lanes reload the last element
     const int hy = e / T::TXH, hx = e - hy * T::TXH;
-    const int gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
-    const int gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
-    v[k] = phi[zoff + (size_t)gy * a.nx + gx];
+    const uint32_t gx = halo_coord(x0 - T::RAD + hx, a.nx, a.wall_x);
+    const uint32_t gy = halo_coord(y0 - T::RAD + hy, a.ny, a.wall_y);
+    v[k] = phi_bload(phi, a.N, zoff + gy * (uint32_t)a.nx + gx);
   }
 }
 
