@@ -245,6 +245,20 @@ __device__ __forceinline__ uint32_t pull_index(const Nbr& n, uint32_t N) {
   return moving ^ ((moving ^ bounced) & (0u - solid));
 }
 
+// the same offset for a site with no solid neighbour (no bounce-back)
+template <class L, int I>
+__device__ __forceinline__ uint32_t pull_index_open(const Nbr& n, uint32_t N) {
+  constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
+  constexpr uint32_t lo = pair_lo<L, I>();
+  return (uint32_t)(I - lo) * N + (n.xs[ix] + n.ys[iy] + n.zs[iz]);
+}
+
+// true when no lane of the wave has a solid neighbour (a wave-uniform value)
+__device__ __forceinline__ bool wave_open(const Nbr& n) {
+  const bool near = n.solid_x[0] | n.solid_x[2] | n.solid_y[0] | n.solid_y[2] | n.solid_z[0] | n.solid_z[2];
+  return __ballot(near) == 0;
+}
+
 // Same offset with the select written directly.  The phase pass measures
 // faster with this form than with the branch-free one.
 template <class L, int I>
@@ -712,16 +726,21 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       // work below: both colours (shifted by w_i rho0/2 each), or the total
       const Nbr n = make_nbr(MLP ? min(x, a.nx - 1) : x, MLP ? min(y, a.ny - 1) : y, z, a);
       R va[L::Q], vb[TOT ? 1 : L::Q];
-      static_for<0, L::Q>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        const uint32_t vo = pull_index<L, I>(n, a.N) * ES;
-        if constexpr (TOT) {
-          va[I] = (R)total_bload<S>(pair_rsrc<L, I>(finA, a.N), vo);
-        } else {
-          va[I] = Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finA, a.N), vo, hshift);
-          vb[I] = Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), vo, hshift);
-        }
-      });
+      // rows away from the walls (most of them) skip the bounce-back selects
+      auto pull = [&](auto open) {
+        static_for<0, L::Q>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          const uint32_t vo = (decltype(open)::value ? pull_index_open<L, I>(n, a.N) : pull_index<L, I>(n, a.N)) * ES;
+          if constexpr (TOT) {
+            va[I] = (R)total_bload<S>(pair_rsrc<L, I>(finA, a.N), vo);
+          } else {
+            va[I] = Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finA, a.N), vo, hshift);
+            vb[I] = Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), vo, hshift);
+          }
+        });
+      };
+      if (wave_open(n)) pull(std::true_type{});
+      else pull(std::false_type{});
       const int p0 = zc * T::PL;
       constexpr int dz1 = T::RZ ? 1 : 0;   // 2D: a single plane
       const int pm = ring_slot(zc, -dz1, T::NPL) * T::PL;
