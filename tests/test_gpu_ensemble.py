@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2405_14551_amd import lb  # noqa: E402
+from paper_2405_14551_amd import lb, workloads as W  # noqa: E402
 from oracle.sim import OracleSim, OracleParams  # noqa: E402
 
 
@@ -105,4 +105,62 @@ def test_autotune_picks_a_measured_config(tmp_path):
     assert best2["z_per_block"] == best["z_per_block"] and best2["mode"] == best["mode"]
     assert best2["use_graph"] == best["use_graph"]
     ens.sync()
+    ens.close()
+
+
+def _window(t, colour):
+    """step_window gatherer over one colour of a channel's device state view."""
+    def take(iz, iy, ix):
+        dev = t.device
+        w = t[colour][:, torch.as_tensor(iz, device=dev)][:, :, torch.as_tensor(iy, device=dev)]
+        return w[:, :, :, torch.as_tensor(ix, device=dev)].double().cpu().numpy()
+    return take
+
+
+def test_ensemble_full_size_sampled_sites():
+    """The 96-channel D3Q19 ensemble (67.5M sites, FP32, near contact) in the
+    benchmark's batched configuration: one step from a developed state
+    against the oracle's windowed step at sampled sites of several channels
+    (near-contact sites, walls, corners, the channel's last site)."""
+    from oracle.sim import step_window
+    w = W.ensemble_channels()
+    chans = w["channels"]
+    plain = [{k: v for k, v in c.items() if k not in ("centres", "radii")} for c in chans]
+    say(f"case ensemble full size: {len(chans)} channels")
+    ens = lb.Ensemble(plain, lattice="D3Q19", storage="f32", nc="explicit")
+    ens.set_tuning("batched", z_per_block=2, use_graph=1)
+    for k, c in enumerate(chans):
+        ens.init_droplets(k, c["centres"], c["radii"])
+    ens.step(6)
+    ens.sync()
+    pre = ens.get_state().clone()
+    ens.step(1)
+    ens.sync()
+    post = ens.get_state()
+    sizes = [np.prod(c["shape"]) for c in chans]
+    picks = sorted({0, len(chans) - 1, int(np.argmin(sizes)), int(np.argmax(sizes)), 37, 58})
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for k in picks:
+        c = chans[k]
+        nx, ny, nz = c["shape"]
+        fnc = ens.fields(k, ("f_nc",))["f_nc"].cpu().numpy()
+        act = np.argwhere(np.abs(fnc).sum(0) > 0)
+        sites = [(nx - 1, ny - 1, nz - 1), (0, 0, 0), (int(rng.integers(nx)), 0, int(rng.integers(nz)))]
+        for j in rng.choice(len(act), size=min(3, len(act)), replace=False):
+            z, y, x = act[j]
+            sites.append((int(x), int(y), int(z)))
+        p = OracleParams(lattice="D3Q19", nx=nx, ny=ny, nz=nz, walls=tuple(bool(v) for v in c["walls"]), tau=c["tau"],
+                         A=c["A"], beta=c["beta"], body_force=tuple(c["body_force"]), nc=True, nc_A=c["nc_A"],
+                         nc_hmin=c["nc_hmin"], nc_hmax=c["nc_hmax"], decision_dtype=np.float32)
+        sv, pv = ens.channel_state(pre, k), ens.channel_state(post, k)
+        for (x, y, z) in sites:
+            a, b, _ = step_window(p, _window(sv, 0), _window(sv, 1), (x, y, z))
+            na = pv[0, :, z, y, x].double().cpu().numpy()
+            nb = pv[1, :, z, y, x].double().cpu().numpy()
+            e = max(np.abs(na - a).max(), np.abs(nb - b).max()) / np.abs(a + b).max()
+            worst = max(worst, e)
+            assert e < 2e-6, (k, (x, y, z), e)
+    say(f"  channels {picks}: worst rel err {worst:.2e}")
+    del pre
     ens.close()

@@ -201,18 +201,22 @@ def test_step_with_closure_matches_oracle():
     sim.close()
 
 
-def closure_force_error(F, Fexp):
-    """||F - F_exp||_2 / ||F_exp||_2 over all rows and per near-contact
-    distance class of the explicit force (its magnitude per unit strength
-    and |g| is 1/2 for h <= h_min = 2, (2/3)^3/2 for h = 3, 0 without force)."""
-    mag = torch.linalg.norm(Fexp, dim=1) / torch.linalg.norm(Fexp, dim=1).clamp_min(1e-30)
-    out = {"all": float(torch.linalg.norm(F - Fexp) / torch.linalg.norm(Fexp))}
-    a = torch.linalg.norm(Fexp, dim=1) > 0
-    out["active"] = float(torch.linalg.norm(F[a] - Fexp[a]) / torch.linalg.norm(Fexp[a]))
-    out["free (|F| rms / active |F_exp| rms)"] = float(
-        torch.linalg.norm(F[~a]) / max(1, int((~a).sum())) ** 0.5
-        / (torch.linalg.norm(Fexp[a]) / max(1, int(a.sum())) ** 0.5))
-    del mag
+def closure_force_error(F, Fexp, T):
+    """||F - F_exp||_2 / ||F_exp||_2 over all rows, over force-active rows and
+    per near-contact distance class of the explicit force (its magnitude per
+    unit strength and |g| is 1/2 for h <= h_min = 2 and (2/3)^3 / 2 for h = 3);
+    and the RMS of the closure's force at force-free rows relative to the RMS
+    explicit force at active rows."""
+    mag = torch.linalg.norm(T, dim=1)
+    a = mag > 0
+    out = {"all": float(torch.linalg.norm(F - Fexp) / torch.linalg.norm(Fexp)),
+           "active": float(torch.linalg.norm(F[a] - Fexp[a]) / torch.linalg.norm(Fexp[a]))}
+    for name, lvl in (("h<=2", 0.5), ("h=3", 0.5 * (2 / 3) ** 3)):
+        m = (mag - lvl).abs() < 1e-3
+        if m.any():
+            out[name] = float(torch.linalg.norm(F[m] - Fexp[m]) / torch.linalg.norm(Fexp[m]))
+    out["free/active rms"] = float(torch.linalg.norm(F[~a]) / max(1, int((~a).sum())) ** 0.5
+                                   / (torch.linalg.norm(Fexp[a]) / max(1, int(a.sum())) ** 0.5))
     return out
 
 
@@ -232,17 +236,18 @@ def _pair3d(nc, steps, gap=3.0, R=8.0, net=None, ranges=None):
 
 
 def test_trained_closure_keeps_droplets_apart():
-    """Train on rows the explicit force generates in a dense emulsion, then
-    run two droplets 3 sites apart: without a near-contact force they merge,
-    with the explicit force or the trained closure they stay two.  The force
-    error on a held-out snapshot is reported."""
+    """Train on rows the explicit force generates in a dense emulsion (10
+    snapshots 100 steps apart), then run two droplets 3 sites apart: without
+    a near-contact force they merge, with the explicit force or the trained
+    closure they stay two.  The force error on a held-out snapshot is
+    reported per near-contact distance class."""
     say("case closure training + gain")
     w = W.dense_3d(shape=(96, 96, 64), count=1000)
     kw, cen, rad = W.sim_kwargs(w)
     sim = lb.Simulation(**kw).init_droplets(cen, rad)
     rows, tgs, nas, nfs = [], [], 0, 0
     A_parts, F_parts = [], []
-    for snap in range(6):
+    for snap in range(10):
         sim.step(100)
         r, t, na, nf = sim.nc_collect()
         A_parts.append((r[:na], t[:na]))
@@ -254,20 +259,25 @@ def test_trained_closure_keeps_droplets_apart():
     rows = torch.cat([a[0] for a in A_parts] + [f[0] for f in F_parts])
     tgs = torch.cat([a[1] for a in A_parts] + [f[1] for f in F_parts])
     say(f"  training rows: {nas} active, {nfs} free")
-    order = W.closure_batches(nas, nfs, 6000, 256)
     tr = _handle()
     tr.mlp_set_weights(W.closure_init_weights())
-    log = tr.mlp_train(rows, tgs, torch.from_numpy(order), lr=2e-3).cpu().numpy()
-    say(f"  loss {log[:50].mean():.3e} -> {log[-50:].mean():.3e}")
-    assert log[-50:].mean() < 0.5 * log[:50].mean()
+    # 20k Adam steps of 256 rows (half force-active), learning rate stepped down
+    logs = []
+    for k, (n_steps, lr) in enumerate(((12000, 2e-3), (6000, 5e-4), (2000, 1e-4))):
+        order = W.closure_batches(nas, nfs, n_steps, 256, seed=k + 1)
+        logs.append(tr.mlp_train(rows, tgs, torch.from_numpy(order), lr=lr).cpu().numpy())
+    log = np.concatenate(logs)
+    say(f"  loss {log[:50].mean():.3e} -> {log[-200:].mean():.3e}")
+    assert log[-200:].mean() < 0.2 * log[:50].mean()
     th = tr.mlp_get_weights()
     ranges = tr.mlp_get_ranges()
     r, t, na, nf = held
     pred = tr.mlp_infer(r).double()
     t = t.double()
     gn = r[:, 30:31].double()                  # F = A_nc |g| y
-    err = closure_force_error(pred * gn, t * gn)
+    err = closure_force_error(pred * gn, t * gn, t)
     say("  held-out force error " + ", ".join(f"{k} {v:.3f}" for k, v in err.items()))
+    assert err["active"] < 0.6
     tr.close()
     off = _pair3d("off", 3000)
     on = _pair3d("explicit", 3000)
