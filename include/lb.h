@@ -141,8 +141,13 @@ void lb_params_default(lb_params* p);
  * ("channels") with their own sizes, walls, tau, forces and droplets, advanced
  * together by batched launches (lb_tuning); lattice, storage and nc_mode must
  * agree across channels and the storage must be LB_F64, LB_F32 or a total
- * layout.  hip_stream is a hipStream_t (NULL allowed).  Allocates two copies of
- * the state (see lb_state_bytes) plus the fields, per channel.
+ * layout, and nc_mode LB_NC_MLP is single-lattice only.  hip_stream is a
+ * hipStream_t (NULL allowed).  Allocates two copies of the state (see
+ * lb_state_bytes) plus the fields, per channel.
+ * Size limits per lattice: sites < 2^31, and the planes of one velocity pair
+ * below 4 GiB (2 x sites x element bytes in 3D, 3 x in D2Q9): 536M sites in
+ * FP32, 268M in FP64, 1.07G in the 16-bit layouts.  Near contact needs every
+ * axis >= 4 sites.
  * Errors: LB_EINVAL, LB_ENOMEM, LB_ENODEV, LB_EHIP.  *out is NULL on error. */
 int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** out);
 

@@ -560,8 +560,8 @@ static int ensemble_launch(lb_handle* h, bool fields, int parity, hipStream_t s)
   } else {
     for (lb_handle* c : h->chans) {
       const StepArgs a = c->step_args();
-      HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[parity],
-                              c->sc[1 - parity], c->phi, c->field_ptrs(), a, s));
+      HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[1 - parity], c->phi,
+                              c->field_ptrs(), a, s));
     }
   }
   return prof_mark(h, 1, false);
@@ -663,11 +663,10 @@ int lb_step(lb_handle* h, int nsteps) {
     if ((r = prof_mark(h, 0, false))) return r;
     if ((r = prof_mark(h, 1, true))) return r;
     if (h->p.nc_mode == LB_NC_MLP)
-      HIP_TRY(h->ops->collide_mlp(h->p.storage, fields, fin, fout, h->sc[h->cur], h->sc[1 - h->cur], h->phi, fo, a,
-                                  h->mlp_net, h->stream));
+      HIP_TRY(h->ops->collide_mlp(h->p.storage, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->mlp_net,
+                                  h->stream));
     else
-      HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->sc[h->cur], h->sc[1 - h->cur], h->phi, fo, a,
-                              h->stream));
+      HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->stream));
     if ((r = prof_mark(h, 1, false))) return r;
     h->cur = 1 - h->cur;
     h->t += 1;

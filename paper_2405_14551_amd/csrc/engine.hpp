@@ -28,10 +28,11 @@ static_assert(TILE_X * TILE_Y == 256 && TILE_X % 64 == 0, "a collision tile is 2
 
 struct LatticeOps {
   int q, d;
-  // sc / scin / scout: recolouring scalars of the total layout (unused otherwise)
+  // scin / scout: recolouring scalars of the total layout (unused otherwise);
+  // the collision pass writes them but never reads them
   hipError_t (*phase)(int storage, const void* fin, const float* scin, void* phi, const StepArgs& a, hipStream_t s);
-  hipError_t (*collide)(int storage, bool nc, bool fields, const void* fin, void* fout, const float* scin,
-                        float* scout, const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
+  hipError_t (*collide)(int storage, bool nc, bool fields, const void* fin, void* fout, float* scout,
+                        const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
   hipError_t (*init)(int storage, void* f, float* sc, void* phi, const FieldPtrs& fo, const double* drops,
                      const InitArgs& a, hipStream_t s);
   // batched ensemble launch: one workgroup per entry of `items` (storages
@@ -40,9 +41,8 @@ struct LatticeOps {
                          uint32_t nitems, int parity, hipStream_t s);
   // collision pass with the learned near-contact closure (3D; storages
   // ST_F64, ST_F32 and the total layouts); NULL for 2D
-  hipError_t (*collide_mlp)(int storage, bool fields, const void* fin, void* fout, const float* scin, float* scout,
-                            const void* phi, const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net,
-                            hipStream_t s);
+  hipError_t (*collide_mlp)(int storage, bool fields, const void* fin, void* fout, float* scout, const void* phi,
+                            const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s);
 };
 
 // storages the learned closure is built for

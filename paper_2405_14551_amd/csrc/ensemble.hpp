@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict
     fo.u = uniform_ptr(C->fo.u);
     fo.fnc = uniform_ptr(C->fo.fnc);
     fo.flags = uniform_ptr(C->fo.flags);
-    collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, (const R*)phi, scin, scout, fo, a, tc, sm.c);
+    collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, (const R*)phi, scout, fo, a, tc, sm.c);
   }
 }
 

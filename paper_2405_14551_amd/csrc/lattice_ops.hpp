@@ -53,7 +53,7 @@ struct Launch {
   }
 
   template <class S, int RAD, bool NC, bool FIELDS, bool TOT>
-  static hipError_t collide_t(const void* fin, void* fout, const float* scin, float* scout, const void* phi,
+  static hipError_t collide_t(const void* fin, void* fout, float* scout, const void* phi,
                               const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     using R = typename Storage<S>::real;
     using T = Tile<TILE_X, TILE_Y, RAD, L::D>;
@@ -63,39 +63,38 @@ struct Launch {
     b.tiles_x = (a.nx + T::TX - 1) / T::TX;
     b.tiles_y = (a.ny + T::TY - 1) / T::TY;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide<L, S, T, NC, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scin, scout,
-                                                               fo, b);
+    k_collide<L, S, T, NC, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b);
     return hipGetLastError();
   }
 
   template <class S, bool TOT>
-  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, const float* scin, float* scout,
+  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, float* scout,
                               const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     if (nc) {
-      return fields ? collide_t<S, 4, true, true, TOT>(fin, fout, scin, scout, phi, fo, a, s)
-                    : collide_t<S, 4, true, false, TOT>(fin, fout, scin, scout, phi, fo, a, s);
+      return fields ? collide_t<S, 4, true, true, TOT>(fin, fout, scout, phi, fo, a, s)
+                    : collide_t<S, 4, true, false, TOT>(fin, fout, scout, phi, fo, a, s);
     }
-    return fields ? collide_t<S, 1, false, true, TOT>(fin, fout, scin, scout, phi, fo, a, s)
-                  : collide_t<S, 1, false, false, TOT>(fin, fout, scin, scout, phi, fo, a, s);
+    return fields ? collide_t<S, 1, false, true, TOT>(fin, fout, scout, phi, fo, a, s)
+                  : collide_t<S, 1, false, false, TOT>(fin, fout, scout, phi, fo, a, s);
   }
 
-  static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, const float* scin,
-                            float* scout, const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+  static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, float* scout, const void* phi,
+                            const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     switch (st) {
-      case ST_F64: return collide_s<double, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
-      case ST_F32: return collide_s<float, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
-      case ST_F16: return collide_s<_Float16, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
-      case ST_BF16: return collide_s<__bf16, false>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
-      case ST_F32T: return collide_s<float, true>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
-      case ST_F16T: return collide_s<_Float16, true>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
-      case ST_BF16T: return collide_s<__bf16, true>(nc, fields, fin, fout, scin, scout, phi, fo, a, s);
+      case ST_F64: return collide_s<double, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_F32: return collide_s<float, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_F16: return collide_s<_Float16, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_BF16: return collide_s<__bf16, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_F32T: return collide_s<float, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_F16T: return collide_s<_Float16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_BF16T: return collide_s<__bf16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
     }
     return hipErrorInvalidValue;
   }
 
   // collision pass with the learned near-contact closure (3D lattices)
   template <class S, bool FIELDS, bool TOT>
-  static hipError_t collide_mlp_t(const void* fin, void* fout, const float* scin, float* scout, const void* phi,
+  static hipError_t collide_mlp_t(const void* fin, void* fout, float* scout, const void* phi,
                                   const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
     using R = typename Storage<S>::real;
     // radius-1 phase ring: the network needs the 3x3x3 neighbourhood; the
@@ -107,19 +106,18 @@ struct Launch {
     b.tiles_x = (a.nx + T::TX - 1) / T::TX;
     b.tiles_y = (a.ny + T::TY - 1) / T::TY;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide_mlp<L, S, T, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scin, scout,
-                                                               fo, b, net);
+    k_collide_mlp<L, S, T, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b,
+                                                               net);
     return hipGetLastError();
   }
 
-  static hipError_t collide_mlp(int st, bool fields, const void* fin, void* fout, const float* scin, float* scout,
-                                const void* phi, const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net,
-                                hipStream_t s) {
+  static hipError_t collide_mlp(int st, bool fields, const void* fin, void* fout, float* scout, const void* phi,
+                                const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
     if constexpr (L::D == 3) {
 #define LB_MLP_CASE(ST, TYPE, TOT)                                                          \
   case ST:                                                                                  \
-    return fields ? collide_mlp_t<TYPE, true, TOT>(fin, fout, scin, scout, phi, fo, a, net, s) \
-                  : collide_mlp_t<TYPE, false, TOT>(fin, fout, scin, scout, phi, fo, a, net, s);
+    return fields ? collide_mlp_t<TYPE, true, TOT>(fin, fout, scout, phi, fo, a, net, s) \
+                  : collide_mlp_t<TYPE, false, TOT>(fin, fout, scout, phi, fo, a, net, s);
       switch (st) {
         LB_MLP_CASE(ST_F64, double, false)
         LB_MLP_CASE(ST_F32, float, false)

@@ -679,7 +679,7 @@ struct CollideSmem<L, S, T, TOT, true> : CollideSmem<L, S, T, TOT, false> {
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false>
 __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __restrict__ fout,
                                              const typename Storage<S>::real* __restrict__ phi,
-                                             const float* __restrict__ scin, float* __restrict__ scout,
+                                             float* __restrict__ scout,
                                              const FieldPtrs& fo, const StepArgs& a, const TileCoord& tc,
                                              CollideSmem<L, S, T, TOT, MLP>& sm,
                                              const MlpPacked* __restrict__ net = nullptr) {
@@ -961,22 +961,22 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
 __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::real* __restrict__ phi,
-                                                    const float* __restrict__ scin, float* __restrict__ scout,
+                                                    float* __restrict__ scout,
                                                     FieldPtrs fo, StepArgs a) {
   __shared__ CollideSmem<L, S, T, TOT> sm;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
-  collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, phi, scin, scout, fo, a, tc, sm);
+  collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, phi, scout, fo, a, tc, sm);
 }
 
 // collision pass with the learned near-contact closure
 template <class L, class S, class T, bool FIELDS, bool TOT>
 __global__ void __launch_bounds__(T::NT, 3) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
-                                                        const typename Storage<S>::real* __restrict__ phi,
-                                                        const float* __restrict__ scin, float* __restrict__ scout,
+                                                           const typename Storage<S>::real* __restrict__ phi,
+                                                           float* __restrict__ scout,
                                                         FieldPtrs fo, StepArgs a, const MlpPacked* __restrict__ net) {
   __shared__ CollideSmem<L, S, T, TOT, true> sm;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
-  collide_tile<L, S, T, true, FIELDS, TOT, true>(fin, fout, phi, scin, scout, fo, a, tc, sm, net);
+  collide_tile<L, S, T, true, FIELDS, TOT, true>(fin, fout, phi, scout, fo, a, tc, sm, net);
 }
 
 }  // namespace lbm
