@@ -107,12 +107,16 @@ def cpu_baseline(seconds_target=10.0):
                       f"(host nproc {os.cpu_count()})"}
 
 
-def time_storage(kw, cen, rad, storage, steps, warmup):
+def time_storage(kw, cen, rad, storage, steps, warmup, streaming="two_copies"):
     """MLUPS and per-launch pass times of the same workload with another
-    storage layout (HIP events on the library's stream)."""
+    storage layout or streaming (HIP events on the library's stream), and the
+    device memory the population state takes per site (both copies with
+    two-copy streaming)."""
     import torch
     from paper_2405_14551_amd import lb
-    sim = lb.Simulation(**dict(kw, storage=storage)).init_droplets(cen, rad)
+    sim = lb.Simulation(**dict(kw, storage=storage, streaming=streaming)).init_droplets(cen, rad)
+    copies = 1 if streaming == "in_place" else 2
+    state_per_site = copies * sim.state_bytes() / (kw["shape"][0] * kw["shape"][1] * kw["shape"][2])
     sim.step(warmup)
     sim.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -128,7 +132,8 @@ def time_storage(kw, cen, rad, storage, steps, warmup):
     sim.close()
     return {"MLUPS": round(nx * ny * nz * steps / (ms / 1e3) / 1e6, 1),
             "collide_ms": round(prof["ms_collide"] / max(prof["n_collide"], 1), 5),
-            "phase_ms": round(prof["ms_phase"] / max(prof["n_phase"], 1), 5)}
+            "phase_ms": round(prof["ms_phase"] / max(prof["n_phase"], 1), 5),
+            "state_bytes_per_site": round(state_per_site, 1)}
 
 
 def time_closure(kw, cen, rad, steps, warmup, explicit):
@@ -365,13 +370,16 @@ def main():
     sim.close()
     if not args.no_variants and storage == "f32":
         # same workload: total-population layouts (FP32 / FP16 / BF16 storage,
-        # FP32 arithmetic) and the learned near-contact closure
+        # FP32 arithmetic), in-place streaming (one copy of the state) and the
+        # learned near-contact closure
         vs = min(args.steps, 200)
         var = {}
-        for st in ("f32t", "f16t", "bf16t"):
-            var[st] = time_storage(kw, cen, rad, st, vs, args.warmup)
-            var[st]["vs_plain_f32"] = round(var[st]["MLUPS"] / mlups, 3)
-            print(f"# variant {st}: {var[st]}", file=sys.stderr, flush=True)
+        for st, mode in (("f32t", "two_copies"), ("f16t", "two_copies"), ("bf16t", "two_copies"),
+                         ("f32", "in_place"), ("f16t", "in_place")):
+            name = st if mode == "two_copies" else f"{st}_in_place"
+            var[name] = time_storage(kw, cen, rad, st, vs, args.warmup, mode)
+            var[name]["vs_plain_f32"] = round(var[name]["MLUPS"] / mlups, 3)
+            print(f"# variant {name}: {var[name]}", file=sys.stderr, flush=True)
         if kw.get("nc") == "explicit":
             var["closure_f32"] = time_closure(kw, cen, rad, vs, args.warmup, col_ms)
             print(f"# variant closure: {var['closure_f32']}", file=sys.stderr, flush=True)

@@ -81,6 +81,19 @@ typedef enum lb_storage {
  * with the explicit scan at interface sites outside the closure's input range. */
 typedef enum lb_nc_mode { LB_NC_OFF = 0, LB_NC_EXPLICIT = 1, LB_NC_MLP = 2 } lb_nc_mode;
 
+/* Streaming of the populations (paper Sec. IV.A, first group of memory
+ * strategies).
+ *  LB_STREAM_TWO_COPIES  each step pulls from one copy of the state into the
+ *                        other.
+ *  LB_STREAM_IN_PLACE    one copy, updated in place by the AA pattern: steps
+ *                        alternate between a kind that pulls from the
+ *                        neighbours and pushes back to them and a kind that
+ *                        reads and writes only the site's own slots.  Halves
+ *                        the memory of the populations (and of the total
+ *                        layouts' recolouring scalars); same bytes per step,
+ *                        same results bit for bit.  Single lattices only. */
+typedef enum lb_streaming { LB_STREAM_TWO_COPIES = 0, LB_STREAM_IN_PLACE = 1 } lb_streaming;
+
 /* field selection bits for lb_fields; dst[k] belongs to bit k */
 enum {
   LB_FIELD_RHO_A = 1u << 0,   /* real[N]                                   */
@@ -110,6 +123,7 @@ typedef struct lb_params {
   double nc_hmax;         /* scan range (sites), 1 <= nc_hmax <= 3                       */
   double phi_interface;   /* interface flag threshold phi_I in (0, 1)                    */
   int diag_every;         /* run the watchdog every this many steps inside lb_step (0 = never) */
+  int streaming;          /* lb_streaming                                                */
 } lb_params;
 
 typedef struct lb_handle lb_handle;
@@ -143,7 +157,8 @@ void lb_params_default(lb_params* p);
  * agree across channels and the storage must be LB_F64, LB_F32 or a total
  * layout, and nc_mode LB_NC_MLP is single-lattice only.  hip_stream is a
  * hipStream_t (NULL allowed).  Allocates two copies of the state (see
- * lb_state_bytes) plus the fields, per channel.
+ * lb_state_bytes), or one with LB_STREAM_IN_PLACE, plus the fields, per
+ * channel.
  * Size limits per lattice: sites < 2^31, and the planes of one velocity pair
  * below 4 GiB (2 x sites x element bytes in 3D, 3 x in D2Q9): 536M sites in
  * FP32, 268M in FP64, 1.07G in the 16-bit layouts.  Near contact needs every
@@ -191,7 +206,10 @@ int lb_state_bytes(const lb_handle* h, size_t* bytes);
 /* Copy the current post-collision state out / in, in the layout above (16-bit
  * modes hold the shifted values).  Host buffers when *_on_device == 0
  * (synchronises).  lb_set_state keeps the step counter; fields are available
- * again after the next step. */
+ * again after the next step.  With LB_STREAM_IN_PLACE the state is always
+ * given in this (canonical) layout: after an odd number of in-place steps
+ * lb_get_state gathers it from the streamed slots (to a host buffer through a
+ * one-plane staging buffer it allocates and frees). */
 int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device);
 int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device);
 

@@ -48,6 +48,15 @@ const LatticeOps* ops_for(int lattice) {
   return nullptr;
 }
 
+const InPlaceOps* inplace_for(int lattice) {
+  switch (lattice) {
+    case LB_D2Q9: return inplace_d2q9();
+    case LB_D3Q19: return inplace_d3q19();
+    case LB_D3Q27: return inplace_d3q27();
+  }
+  return nullptr;
+}
+
 size_t storage_bytes(int st) {
   switch (st) {
     case LB_F64: return 8;
@@ -78,6 +87,11 @@ struct lb_handle {
   float* sc[2] = {nullptr, nullptr};  // recolouring scalars (total layout only)
   bool total = false;
   int cur = 0;
+  // in-place streaming: one copy f[0] (and sc[0]); ip_odd says which kind of
+  // step comes next (0: even, from the canonical layout)
+  const InPlaceOps* ip = nullptr;
+  int ip_odd = 0;
+  bool in_place() const { return ip != nullptr; }
   void* phi = nullptr;
   void* rho_a = nullptr;
   void* rho_b = nullptr;
@@ -237,6 +251,8 @@ static int validate(const lb_params* p) {
     if (!(p->nc_hmin > 0.0)) return fail(LB_EINVAL, "nc_hmin must be positive");
   }
   if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
+  if (p->streaming != LB_STREAM_TWO_COPIES && p->streaming != LB_STREAM_IN_PLACE)
+    return fail(LB_EINVAL, "unknown streaming %d", p->streaming);
   return LB_OK;
 }
 
@@ -290,6 +306,9 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
       return fail(LB_EINVAL, "channel %d: lattice, storage and nc_mode must agree across channels", c);
   }
   if (n_channels == 1) return create_single(p, hip_stream, out);
+  for (int c = 0; c < n_channels; ++c)
+    if (p[c].streaming != LB_STREAM_TWO_COPIES)
+      return fail(LB_EINVAL, "channel %d: ensembles stream with two copies (LB_STREAM_TWO_COPIES)", c);
   if (p[0].nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "ensembles take nc_mode LB_NC_OFF or LB_NC_EXPLICIT");
   if (!ensemble_storage(p[0].storage))
     return fail(LB_EINVAL, "ensembles take storage LB_F64, LB_F32 or a total layout (got %d)", p[0].storage);
@@ -341,6 +360,7 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
   h->rsize = p->storage == LB_F64 ? 8 : 4;
   h->total = total_layout(p->storage);
   h->stream = (hipStream_t)hip_stream;
+  if (p->streaming == LB_STREAM_IN_PLACE) h->ip = inplace_for(p->lattice);
   (void)hipGetDevice(&h->device);
   // pass-2 blocks march through z; aim for about 2048 blocks in flight
   {
@@ -362,11 +382,14 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
     int r_ = dev_alloc((void**)&(ptr), (bytes), #ptr);                 \
     if (r_) { lb_destroy(h); return r_; }                              \
   } while (0)
+  // in place: one copy of the populations, and one of the recolouring
+  // scalars (the phase pass reads them, the collision pass rewrites them
+  // afterwards; no pass does both)
   ALLOC(h->f[0], pop);
-  ALLOC(h->f[1], pop);
+  if (!h->in_place()) ALLOC(h->f[1], pop);
   if (h->total) {
     ALLOC(h->sc[0], sizeof(float) * NSC * N);
-    ALLOC(h->sc[1], sizeof(float) * NSC * N);
+    if (!h->in_place()) ALLOC(h->sc[1], sizeof(float) * NSC * N);
   }
   ALLOC(h->phi, N * h->rsize);
   ALLOC(h->rho_a, N * h->rsize);
@@ -431,6 +454,7 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
   HIP_TRY(h->ops->init(h->p.storage, h->f[h->cur], h->sc[h->cur], h->phi, h->field_ptrs(), h->drops, a, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));  // the host droplet list goes out of scope
   h->t = 0;
+  h->ip_odd = 0;
   h->initialised = true;
   h->fields_valid = true;
   return LB_OK;
@@ -652,23 +676,39 @@ int lb_step(lb_handle* h, int nsteps) {
   const StepArgs a = h->step_args();
   const FieldPtrs fo = h->field_ptrs();
   const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
+  const bool mlp = h->p.nc_mode == LB_NC_MLP;
+  const int st = h->p.storage;
   for (int s = 0; s < nsteps; ++s) {
     const bool diag_now = h->p.diag_every > 0 && ((h->t + 1) % h->p.diag_every) == 0;
     const bool fields = (s == nsteps - 1) || diag_now;
-    void* fin = h->f[h->cur];
-    void* fout = h->f[1 - h->cur];
     int r = prof_mark(h, 0, true);
     if (r) return r;
-    HIP_TRY(h->ops->phase(h->p.storage, fin, h->sc[h->cur], h->phi, a, h->stream));
-    if ((r = prof_mark(h, 0, false))) return r;
-    if ((r = prof_mark(h, 1, true))) return r;
-    if (h->p.nc_mode == LB_NC_MLP)
-      HIP_TRY(h->ops->collide_mlp(h->p.storage, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->mlp_net,
-                                  h->stream));
-    else
-      HIP_TRY(h->ops->collide(h->p.storage, nc, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->stream));
-    if ((r = prof_mark(h, 1, false))) return r;
-    h->cur = 1 - h->cur;
+    if (h->in_place()) {
+      // one copy: even steps pull and push, odd steps work on the site's own slots
+      void* f = h->f[0];
+      float* sc = h->sc[0];
+      const int odd = h->ip_odd;
+      if (odd) HIP_TRY(h->ip->phase_odd(st, f, sc, h->phi, a, h->stream));
+      else HIP_TRY(h->ops->phase(st, f, sc, h->phi, a, h->stream));
+      if ((r = prof_mark(h, 0, false))) return r;
+      if ((r = prof_mark(h, 1, true))) return r;
+      if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, h->phi, fo, a, h->mlp_net, h->stream));
+      else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, h->phi, fo, a, h->stream));
+      if ((r = prof_mark(h, 1, false))) return r;
+      h->ip_odd = 1 - odd;
+    } else {
+      void* fin = h->f[h->cur];
+      void* fout = h->f[1 - h->cur];
+      HIP_TRY(h->ops->phase(st, fin, h->sc[h->cur], h->phi, a, h->stream));
+      if ((r = prof_mark(h, 0, false))) return r;
+      if ((r = prof_mark(h, 1, true))) return r;
+      if (mlp)
+        HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->mlp_net, h->stream));
+      else
+        HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->stream));
+      if ((r = prof_mark(h, 1, false))) return r;
+      h->cur = 1 - h->cur;
+    }
     h->t += 1;
     if (fields) h->fields_valid = true;
     if (diag_now) {
@@ -764,6 +804,36 @@ int lb_diagnostics(lb_handle* h, int channel, double out[8]) {
   return LB_OK;
 }
 
+// The populations in the canonical layout after an odd number of in-place
+// steps: gathered by colour block straight into a device destination, or
+// plane by plane through a one-plane staging buffer for a host destination.
+static int canonical_state(lb_handle* h, void* dst, int dst_on_device) {
+  const StepArgs a = h->step_args();
+  const int nblk = h->total ? 1 : 2;
+  const size_t plane = (size_t)h->N * h->esize;
+  if (dst_on_device) {
+    for (int k = 0; k < nblk; ++k)
+      HIP_TRY(h->ip->canonical(h->p.storage, (const char*)h->f[0] + k * h->q * plane, (char*)dst + k * h->q * plane,
+                               0, h->q, a, h->stream));
+    return LB_OK;
+  }
+  void* tmp = nullptr;
+  int rc = dev_alloc(&tmp, plane, "canonical staging plane");
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < nblk && e == hipSuccess; ++k)
+    for (int i = 0; i < h->q && e == hipSuccess; ++i) {
+      e = h->ip->canonical(h->p.storage, (const char*)h->f[0] + k * h->q * plane, tmp, i, i + 1, a, h->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync((char*)dst + (k * h->q + i) * plane, tmp, plane, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(LB_EHIP, "canonical state: %s", hipGetErrorString(e));
+  return LB_OK;
+}
+
 static size_t state_size(const lb_handle* h, size_t* pop_bytes) {
   if (h->ensemble()) {
     size_t tot = 0;
@@ -799,7 +869,12 @@ int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device) {
     return LB_OK;
   }
   const hipMemcpyKind k = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  HIP_TRY(hipMemcpyAsync(dst, h->f[h->cur], pop, k, h->stream));
+  if (h->in_place() && h->ip_odd) {
+    int rc = canonical_state(h, dst, dst_on_device);
+    if (rc) return rc;
+  } else {
+    HIP_TRY(hipMemcpyAsync(dst, h->f[h->cur], pop, k, h->stream));
+  }
   if (h->total) HIP_TRY(hipMemcpyAsync((char*)dst + pop, h->sc[h->cur], need - pop, k, h->stream));
   if (!dst_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
   return LB_OK;
@@ -826,6 +901,7 @@ int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device)
   HIP_TRY(hipMemcpyAsync(h->f[h->cur], src, pop, k, h->stream));
   if (h->total) HIP_TRY(hipMemcpyAsync(h->sc[h->cur], (const char*)src + pop, need - pop, k, h->stream));
   if (!src_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
+  h->ip_odd = 0;  // the state given is canonical
   h->initialised = true;
   h->fields_valid = false;
   return LB_OK;

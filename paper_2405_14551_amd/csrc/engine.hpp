@@ -45,6 +45,22 @@ struct LatticeOps {
                             const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s);
 };
 
+// One-copy (in-place) streaming: even and odd steps alternate, the even kind
+// starting from the canonical layout (step_kernels.hpp, STREAM_EVEN /
+// STREAM_ODD).  An even step's phase pass is LatticeOps::phase.
+struct InPlaceOps {
+  hipError_t (*phase_odd)(int storage, const void* f, const float* scin, void* phi, const StepArgs& a,
+                          hipStream_t s);
+  hipError_t (*collide)(int storage, int odd, bool nc, bool fields, void* f, float* scout, const void* phi,
+                        const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
+  // NULL for 2D; storages as LatticeOps::collide_mlp
+  hipError_t (*collide_mlp)(int storage, int odd, bool fields, void* f, float* scout, const void* phi,
+                            const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s);
+  // planes i0 .. i1-1 of the colour block at f, in the canonical layout, from
+  // the layout an even step leaves; out holds (i1 - i0) N elements
+  hipError_t (*canonical)(int storage, const void* f, void* out, int i0, int i1, const StepArgs& a, hipStream_t s);
+};
+
 // storages the learned closure is built for
 inline bool mlp_storage(int st) { return st == ST_F64 || st == ST_F32 || st >= ST_F32T; }
 
@@ -54,5 +70,8 @@ inline bool ensemble_storage(int st) { return st == ST_F64 || st == ST_F32 || st
 const LatticeOps* ops_d2q9();
 const LatticeOps* ops_d3q19();
 const LatticeOps* ops_d3q27();
+const InPlaceOps* inplace_d2q9();
+const InPlaceOps* inplace_d3q19();
+const InPlaceOps* inplace_d3q27();
 
 }  // namespace lbm

@@ -1,0 +1,116 @@
+// Host-side launchers of the one-copy (in-place) streaming modes for one
+// velocity set.  Included by lattice_*_inplace.hip, so that these
+// instantiations compile in parallel with the two-copy ones.
+#pragma once
+
+#include "lattice_ops.hpp"
+
+namespace lbm {
+
+template <class L>
+struct InPlaceLaunch {
+  using B = Launch<L>;
+
+  // phase pass of an odd step: the pulled populations are in the site's own
+  // reversed slots (an even step reads as two-copy streaming does)
+  static hipError_t phase_odd(int st, const void* f, const float* scin, void* phi, const StepArgs& a,
+                              hipStream_t s) {
+    switch (st) {
+      case ST_F64: return B::template phase_t<double, true>(f, phi, a, s);
+      case ST_F32: return B::template phase_t<float, true>(f, phi, a, s);
+      case ST_F16: return B::template phase_t<_Float16, true>(f, phi, a, s);
+      case ST_BF16: return B::template phase_t<__bf16, true>(f, phi, a, s);
+      case ST_F32T: return B::template phase_total_t<float, true>(f, scin, phi, a, s);
+      case ST_F16T: return B::template phase_total_t<_Float16, true>(f, scin, phi, a, s);
+      case ST_BF16T: return B::template phase_total_t<__bf16, true>(f, scin, phi, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+
+  template <class S, bool TOT, int STREAM>
+  static hipError_t collide_s(bool nc, bool fields, void* f, float* scout, const void* phi, const FieldPtrs& fo,
+                              const StepArgs& a, hipStream_t s) {
+    if (nc) {
+      return fields ? B::template collide_t<S, 4, true, true, TOT, STREAM>(f, f, scout, phi, fo, a, s)
+                    : B::template collide_t<S, 4, true, false, TOT, STREAM>(f, f, scout, phi, fo, a, s);
+    }
+    return fields ? B::template collide_t<S, 1, false, true, TOT, STREAM>(f, f, scout, phi, fo, a, s)
+                  : B::template collide_t<S, 1, false, false, TOT, STREAM>(f, f, scout, phi, fo, a, s);
+  }
+
+  template <int STREAM>
+  static hipError_t collide_k(int st, bool nc, bool fields, void* f, float* scout, const void* phi,
+                              const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+    switch (st) {
+      case ST_F64: return collide_s<double, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_F32: return collide_s<float, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_F16: return collide_s<_Float16, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_BF16: return collide_s<__bf16, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_F32T: return collide_s<float, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_F16T: return collide_s<_Float16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_BF16T: return collide_s<__bf16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+
+  static hipError_t collide(int st, int odd, bool nc, bool fields, void* f, float* scout, const void* phi,
+                            const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+    return odd ? collide_k<STREAM_ODD>(st, nc, fields, f, scout, phi, fo, a, s)
+               : collide_k<STREAM_EVEN>(st, nc, fields, f, scout, phi, fo, a, s);
+  }
+
+  template <int STREAM>
+  static hipError_t collide_mlp_k(int st, bool fields, void* f, float* scout, const void* phi, const FieldPtrs& fo,
+                                  const StepArgs& a, const MlpPacked* net, hipStream_t s) {
+    if constexpr (L::D == 3) {
+#define LB_MLP_CASE(ST, TYPE, TOT)                                                                     \
+  case ST:                                                                                             \
+    return fields ? B::template collide_mlp_t<TYPE, true, TOT, STREAM>(f, f, scout, phi, fo, a, net, s) \
+                  : B::template collide_mlp_t<TYPE, false, TOT, STREAM>(f, f, scout, phi, fo, a, net, s);
+      switch (st) {
+        LB_MLP_CASE(ST_F64, double, false)
+        LB_MLP_CASE(ST_F32, float, false)
+        LB_MLP_CASE(ST_F32T, float, true)
+        LB_MLP_CASE(ST_F16T, _Float16, true)
+        LB_MLP_CASE(ST_BF16T, __bf16, true)
+      }
+#undef LB_MLP_CASE
+    }
+    return hipErrorInvalidValue;
+  }
+
+  static hipError_t collide_mlp(int st, int odd, bool fields, void* f, float* scout, const void* phi,
+                                const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
+    return odd ? collide_mlp_k<STREAM_ODD>(st, fields, f, scout, phi, fo, a, net, s)
+               : collide_mlp_k<STREAM_EVEN>(st, fields, f, scout, phi, fo, a, net, s);
+  }
+
+  static hipError_t canonical(int st, const void* f, void* out, int i0, int i1, const StepArgs& a, hipStream_t s) {
+    if (i0 < 0 || i1 > L::Q || i0 >= i1) return hipErrorInvalidValue;
+    dim3 block(256), grid((a.N + 255) / 256);
+    switch (st) {
+      case ST_F64:
+        k_canonical<L, uint64_t><<<grid, block, 0, s>>>((const uint64_t*)f, (uint64_t*)out, i0, i1, a);
+        break;
+      case ST_F32:
+      case ST_F32T:
+        k_canonical<L, uint32_t><<<grid, block, 0, s>>>((const uint32_t*)f, (uint32_t*)out, i0, i1, a);
+        break;
+      case ST_F16:
+      case ST_BF16:
+      case ST_F16T:
+      case ST_BF16T:
+        k_canonical<L, uint16_t><<<grid, block, 0, s>>>((const uint16_t*)f, (uint16_t*)out, i0, i1, a);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+
+  static InPlaceOps ops() {
+    return InPlaceOps{&phase_odd, &collide, L::D == 3 ? &collide_mlp : nullptr, &canonical};
+  }
+};
+
+}  // namespace lbm

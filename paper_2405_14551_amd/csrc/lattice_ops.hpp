@@ -9,7 +9,10 @@ namespace lbm {
 
 template <class L>
 struct Launch {
-  template <class S>
+  // OWN / STREAM: read mode of the phase pass and streaming mode of the
+  // collision pass (step_kernels.hpp); the in-place launchers
+  // (lattice_inplace.hpp) instantiate the other modes
+  template <class S, bool OWN = false>
   static hipError_t phase_t(const void* fin, void* phi, const StepArgs& a, hipStream_t s) {
     using R = typename Storage<S>::real;
     // one block spans up to 256 consecutive x-sites of a row, so the cache
@@ -20,11 +23,11 @@ struct Launch {
     b.tiles_x = (a.nx + bx - 1) / bx;
     b.tiles_y = (a.ny + block.y - 1) / block.y;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * a.nz);
-    k_phase<L, S><<<grid, block, 0, s>>>((const S*)fin, (R*)phi, b);
+    k_phase<L, S, OWN><<<grid, block, 0, s>>>((const S*)fin, (R*)phi, b);
     return hipGetLastError();
   }
 
-  template <class S>
+  template <class S, bool OWN = false>
   static hipError_t phase_total_t(const void* fin, const float* scin, void* phi, const StepArgs& a,
                                   hipStream_t s) {
     using TS = Tile<TILE_X, TILE_Y, 1, L::D>;
@@ -34,7 +37,7 @@ struct Launch {
     b.tiles_x = (a.nx + TS::TX - 1) / TS::TX;
     b.tiles_y = (a.ny + TS::TY - 1) / TS::TY;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_phase_total<L, S, TS><<<grid, block, 0, s>>>((const S*)fin, scin, (float*)phi, b);
+    k_phase_total<L, S, TS, OWN><<<grid, block, 0, s>>>((const S*)fin, scin, (float*)phi, b);
     return hipGetLastError();
   }
 
@@ -52,7 +55,7 @@ struct Launch {
     return hipErrorInvalidValue;
   }
 
-  template <class S, int RAD, bool NC, bool FIELDS, bool TOT>
+  template <class S, int RAD, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
   static hipError_t collide_t(const void* fin, void* fout, float* scout, const void* phi,
                               const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     using R = typename Storage<S>::real;
@@ -63,7 +66,7 @@ struct Launch {
     b.tiles_x = (a.nx + T::TX - 1) / T::TX;
     b.tiles_y = (a.ny + T::TY - 1) / T::TY;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide<L, S, T, NC, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b);
+    k_collide<L, S, T, NC, FIELDS, TOT, STREAM><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b);
     return hipGetLastError();
   }
 
@@ -93,7 +96,7 @@ struct Launch {
   }
 
   // collision pass with the learned near-contact closure (3D lattices)
-  template <class S, bool FIELDS, bool TOT>
+  template <class S, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
   static hipError_t collide_mlp_t(const void* fin, void* fout, float* scout, const void* phi,
                                   const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
     using R = typename Storage<S>::real;
@@ -106,7 +109,7 @@ struct Launch {
     b.tiles_x = (a.nx + T::TX - 1) / T::TX;
     b.tiles_y = (a.ny + T::TY - 1) / T::TY;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide_mlp<L, S, T, FIELDS, TOT><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b,
+    k_collide_mlp<L, S, T, FIELDS, TOT, STREAM><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b,
                                                                net);
     return hipGetLastError();
   }

@@ -281,10 +281,35 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t pair_rsrc(const S* f, uint32_t
   return make_rsrc(pair_base<L, I>(f, N), (uint32_t)pair_span<L, I>() * N * (uint32_t)sizeof(S));
 }
 
+// ----------------------------------------------------------------------------
+// Streaming modes.  Two copies (STREAM_AB): pull from one buffer, store at the
+// site into the other.  In place, one copy (the AA pattern the paper's
+// Sec. IV.A describes, after Bailey et al.), in two alternating kinds of step:
+//  STREAM_EVEN  starts from the canonical layout (slot (i, x) holds the
+//               post-collision f_i(x)); pulls as STREAM_AB does and pushes
+//               the new f_i(x) to slot (opp(i), x + c_i), or to slot (i, x)
+//               when x + c_i is solid (the bounce-back partner);
+//  STREAM_ODD   starts from that layout, where the pulled population i of
+//               site x is in slot (opp(i), x), and stores at the site in the
+//               canonical layout.
+// In both kinds a site writes exactly the slots it read, so no two sites (and
+// no two workgroups) touch one slot in a pass, and every store of a site
+// depends on all of its loads.  The push of direction i lands where the pull
+// of opp(i) reads, so it uses pull_index of opp(i).
+enum { STREAM_AB = 0, STREAM_EVEN = 1, STREAM_ODD = 2 };
+
+// element offset, from plane pair_lo, of slot (opp(i), x): the pulled
+// population i of a STREAM_ODD pass
+template <class L, int I>
+__device__ __forceinline__ uint32_t own_reversed_index(const Nbr& n, uint32_t N) {
+  return (uint32_t)(L::opp[I] - pair_lo<L, I>()) * N + n.site;
+}
+
 
 // ----------------------------------------------------------------------------
-// pass 1: phase field of the post-streaming populations
-template <class L, class S>
+// pass 1: phase field of the post-streaming populations (OWN: read them from
+// the site's own reversed slots, the STREAM_ODD layout)
+template <class L, class S, bool OWN = false>
 __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
                                                typename Storage<S>::real* __restrict__ phi,
                                                StepArgs a) {
@@ -303,7 +328,9 @@ __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
   const S* finB = fin + a.QN;
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    const uint32_t e = pull_index_sel<L, I>(n, a.N) * (uint32_t)sizeof(S);
+    uint32_t e;
+    if constexpr (OWN) e = own_reversed_index<L, I>(n, a.N) * (uint32_t)sizeof(S);
+    else e = pull_index_sel<L, I>(n, a.N) * (uint32_t)sizeof(S);
     sa += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(fin, a.N), e, h);
     sb += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), e, h);
   });
@@ -578,7 +605,7 @@ struct PhaseTotalSmem {
   float sring[TS::NPL * ScalarRing<TS>::SLOT];
 };
 
-template <class L, class S, class TS>
+template <class L, class S, class TS, bool OWN = false>
 __device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, const float* __restrict__ scin,
                                                  float* __restrict__ phi, const StepArgs& a, const TileCoord& tc,
                                                  PhaseTotalSmem<TS>& sm) {
@@ -607,7 +634,8 @@ __device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, cons
       float Tv[L::Q];
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        Tv[I] = total_bload<S>(pair_rsrc<L, I>(finT, a.N), pull_index<L, I>(n, a.N) * (uint32_t)sizeof(S));
+        const uint32_t e = OWN ? own_reversed_index<L, I>(n, a.N) : pull_index<L, I>(n, a.N);
+        Tv[I] = total_bload<S>(pair_rsrc<L, I>(finT, a.N), e * (uint32_t)sizeof(S));
       });
       const int zcs = plane_slot(z, TS::NPL);
       float sa = 0.f, sb = 0.f;
@@ -624,12 +652,12 @@ __device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, cons
   }
 }
 
-template <class L, class S, class TS>
+template <class L, class S, class TS, bool OWN = false>
 __global__ void __launch_bounds__(TS::NT) k_phase_total(const S* __restrict__ fin, const float* __restrict__ scin,
                                                         float* __restrict__ phi, StepArgs a) {
   __shared__ PhaseTotalSmem<TS> sm;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, TS::TX, TS::TY);
-  phase_total_tile<L, S, TS>(fin, scin, phi, a, tc, sm);
+  phase_total_tile<L, S, TS, OWN>(fin, scin, phi, a, tc, sm);
 }
 
 // per-colour phase pass over a TX x TY x (z0..z1) tile, one site per thread
@@ -675,8 +703,9 @@ struct CollideSmem<L, S, T, TOT, true> : CollideSmem<L, S, T, TOT, false> {
 // interface sites whose stencil lies in its training range, the explicit scan
 // at the others; the closure runs on whole waves, so in that mode every lane
 // takes part (lanes outside the lattice compute on a clamped site and store
-// nothing).
-template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false>
+// nothing).  STREAM selects two-copy or in-place streaming (fin == fout for
+// the in-place kinds).
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false, int STREAM = STREAM_AB>
 __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __restrict__ fout,
                                              const typename Storage<S>::real* __restrict__ phi,
                                              float* __restrict__ scout,
@@ -730,7 +759,9 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       auto pull = [&](auto open) {
         static_for<0, L::Q>([&](auto ic) {
           constexpr int I = decltype(ic)::value;
-          const uint32_t vo = (decltype(open)::value ? pull_index_open<L, I>(n, a.N) : pull_index<L, I>(n, a.N)) * ES;
+          uint32_t vo;
+          if constexpr (STREAM == STREAM_ODD) vo = own_reversed_index<L, I>(n, a.N) * ES;
+          else vo = (decltype(open)::value ? pull_index_open<L, I>(n, a.N) : pull_index<L, I>(n, a.N)) * ES;
           if constexpr (TOT) {
             va[I] = (R)total_bload<S>(pair_rsrc<L, I>(finA, a.N), vo);
           } else {
@@ -739,6 +770,9 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           }
         });
       };
+      // (the odd in-place kind reads its own slots either way; it keeps the
+      // branch so that all streaming modes compile to the same code shape
+      // around the arithmetic, and the compiler fuses it alike)
       if (wave_open(n)) pull(std::true_type{});
       else pull(std::false_type{});
       const int p0 = zc * T::PL;
@@ -831,126 +865,135 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           }
         }
       }
-      // ---- moments of the pulled populations
-      R d[L::Q];  // d_i = f_i - w_i rho0, total over both colours
-      R sa = 0, sb = 0;
-      static_for<0, L::Q>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
+      // lanes outside the lattice (closure mode only) store nothing: one
+      // branch around the whole collision keeps it a single block of
+      // arithmetic, as in the other modes
+      if (!MLP || valid_xy) {
+        // ---- moments of the pulled populations
+        R d[L::Q];  // d_i = f_i - w_i rho0, total over both colours
+        R sa = 0, sb = 0;
+        static_for<0, L::Q>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          if constexpr (TOT) {
+            d[I] = va[I];
+          } else {
+            sa += va[I]; sb += vb[I];
+            d[I] = va[I] + vb[I];
+          }
+        });
+        R jx = 0, jy = 0, jz = 0, drho = 0;
+        static_for<0, L::Q>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          drho += d[I];
+          if constexpr (L::cx[I] != 0) jx += (R)L::cx[I] * d[I];
+          if constexpr (L::cy[I] != 0) jy += (R)L::cy[I] * d[I];
+          if constexpr (L::cz[I] != 0) jz += (R)L::cz[I] * d[I];
+        });
+        const R rho0 = R(2) * hshift;
+        const R rho = rho0 + drho;
         if constexpr (TOT) {
-          d[I] = va[I];
-        } else {
-          sa += va[I]; sb += vb[I];
-          d[I] = va[I] + vb[I];
+          // the phase pass formed phi from these same pulled populations, so
+          // rho_A = rho (1 + phi) / 2: no colour reconstruction is needed here
+          const R rA = R(0.5) * rho * (R(1) + phic);
+          sa = rA - hshift;
+          sb = (rho - rA) - hshift;
         }
-      });
-      R jx = 0, jy = 0, jz = 0, drho = 0;
-      static_for<0, L::Q>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        drho += d[I];
-        if constexpr (L::cx[I] != 0) jx += (R)L::cx[I] * d[I];
-        if constexpr (L::cy[I] != 0) jy += (R)L::cy[I] * d[I];
-        if constexpr (L::cz[I] != 0) jz += (R)L::cz[I] * d[I];
-      });
-      const R rho0 = R(2) * hshift;
-      const R rho = rho0 + drho;
-      if constexpr (TOT) {
-        // the phase pass formed phi from these same pulled populations, so
-        // rho_A = rho (1 + phi) / 2: no colour reconstruction is needed here
-        const R rA = R(0.5) * rho * (R(1) + phic);
-        sa = rA - hshift;
-        sb = (rho - rA) - hshift;
-      }
-      const R ra = hshift + sa, rb = hshift + sb;
-      const R inv_rho = R(1) / rho;
-      const R Fx = (R)a.fx + fnx, Fy = (R)a.fy + fny, Fz = (R)a.fz + fnz;
-      const R ux = (jx + R(0.5) * Fx) * inv_rho;
-      const R uy = (jy + R(0.5) * Fy) * inv_rho;
-      const R uz = (jz + R(0.5) * Fz) * inv_rho;
-      const R uu = ux * ux + uy * uy + uz * uz;
-      const R uF = ux * Fx + uy * Fy + uz * Fz;
-      const R gn = has_g ? sqrt(gg) : R(0);
-      const R inv_gg = has_g ? R(1) / gg : R(0);
-      const R inv_gn = has_g ? R(1) / gn : R(0);
-      const R Agn = has_g ? Aamp * gn : R(0);
-      const R fa_frac = ra * inv_rho;                  // rho_A / rho
-      const R coef = beta * ra * rb * inv_rho;         // beta rho_A rho_B / rho
-      const R half_phi_rho0 = (sa - sb) * inv_rho * hshift;  // rho0 phi / 2
-      // ---- collide and recolour.  With cu = c.u, cF = c.F, cg = c.g, the
-      // shifted post-collision value of direction i is
-      //   f*_i - w rho0 = (1 - omega) d_i + w_i t_i - A |g| B_i,
-      //   t_i = omega drho - 1.5 omega rho uu - 3 guo uF           (isotropic)
-      //       + 4.5 omega rho cu^2 + 9 guo cu cF + A |g| cg^2 / |g|^2   (even in c)
-      //       + 3 omega rho cu + 3 guo cF                           (odd in c)
-      // (BGK toward f^eq, Guo source, perturbation), and the recolouring adds
-      // w_i (rho0 phi/2 + beta rho_A rho_B / rho cg / (|c| |g|)) to colour A.
-      // A velocity and its opposite share cu, cF, cg up to sign.
-      const R one_m_om = R(1) - omega;
-      const R wrho = omega * rho;
-      const R K0 = omega * drho - R(1.5) * wrho * uu - R(3) * guo * uF;
-      const R K1 = R(3) * wrho, K2 = R(4.5) * wrho, K3 = R(3) * guo, K4 = R(9) * guo;
-      const R Kg = Agn * inv_gg;
-      const R Kr = coef * inv_gn;
-      auto emit = [&](auto ic, R ds, R rec_odd) {
-        constexpr int I = decltype(ic)::value;
-        if constexpr (MLP) {
-          if (!valid_xy) return;
+        const R ra = hshift + sa, rb = hshift + sb;
+        const R inv_rho = R(1) / rho;
+        const R Fx = (R)a.fx + fnx, Fy = (R)a.fy + fny, Fz = (R)a.fz + fnz;
+        const R ux = (jx + R(0.5) * Fx) * inv_rho;
+        const R uy = (jy + R(0.5) * Fy) * inv_rho;
+        const R uz = (jz + R(0.5) * Fz) * inv_rho;
+        const R uu = ux * ux + uy * uy + uz * uz;
+        const R uF = ux * Fx + uy * Fy + uz * Fz;
+        const R gn = has_g ? sqrt(gg) : R(0);
+        const R inv_gg = has_g ? R(1) / gg : R(0);
+        const R inv_gn = has_g ? R(1) / gn : R(0);
+        const R Agn = has_g ? Aamp * gn : R(0);
+        const R fa_frac = ra * inv_rho;                  // rho_A / rho
+        const R coef = beta * ra * rb * inv_rho;         // beta rho_A rho_B / rho
+        const R half_phi_rho0 = (sa - sb) * inv_rho * hshift;  // rho0 phi / 2
+        // ---- collide and recolour.  With cu = c.u, cF = c.F, cg = c.g, the
+        // shifted post-collision value of direction i is
+        //   f*_i - w rho0 = (1 - omega) d_i + w_i t_i - A |g| B_i,
+        //   t_i = omega drho - 1.5 omega rho uu - 3 guo uF           (isotropic)
+        //       + 4.5 omega rho cu^2 + 9 guo cu cF + A |g| cg^2 / |g|^2   (even in c)
+        //       + 3 omega rho cu + 3 guo cF                           (odd in c)
+        // (BGK toward f^eq, Guo source, perturbation), and the recolouring adds
+        // w_i (rho0 phi/2 + beta rho_A rho_B / rho cg / (|c| |g|)) to colour A.
+        // A velocity and its opposite share cu, cF, cg up to sign.
+        const R one_m_om = R(1) - omega;
+        const R wrho = omega * rho;
+        const R K0 = omega * drho - R(1.5) * wrho * uu - R(3) * guo * uF;
+        const R K1 = R(3) * wrho, K2 = R(4.5) * wrho, K3 = R(3) * guo, K4 = R(9) * guo;
+        const R Kg = Agn * inv_gg;
+        const R Kr = coef * inv_gn;
+        auto emit = [&](auto ic, R ds, R rec_odd) {
+          constexpr int I = decltype(ic)::value;
+          // stores go through the pair buffers too: at the site, the plane's
+          // offset in the scalar offset operand, or pushed (in place, even kind)
+          uint32_t vo, so;
+          if constexpr (STREAM == STREAM_EVEN) {
+            vo = pull_index<L, L::opp[I]>(n, a.N) * ES;
+            so = 0;
+          } else {
+            vo = n.site * ES;
+            so = (uint32_t)(I - pair_lo<L, I>()) * a.N * ES;
+          }
+          if constexpr (TOT) {
+            total_bstore<S>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, (float)ds);
+          } else {
+            const R wi = (R)L::w[I];
+            const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
+            const R db = ds - da;
+            Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
+            Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
+          }
+        };
+        {
+          const R w0 = (R)L::w[0];
+          emit(std::integral_constant<int, 0>{}, one_m_om * d[0] + w0 * K0 - Agn * (R)B_coef<L>(0), R(0));
         }
-        // stores go through the pair buffers too, the plane's offset in the
-        // scalar offset operand
-        const uint32_t vo = n.site * ES, so = (uint32_t)(I - pair_lo<L, I>()) * a.N * ES;
-        if constexpr (TOT) {
-          total_bstore<S>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, (float)ds);
-        } else {
+        static_for<0, (L::Q - 1) / 2>([&](auto pc) {
+          constexpr int I = pair_first<L>(decltype(pc)::value);
+          constexpr int J = L::opp[I];
+          constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
           const R wi = (R)L::w[I];
-          const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
-          const R db = ds - da;
-          Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
-          Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
+          R cu = 0, cF = 0, cg = 0;
+          if constexpr (cx != 0) { cu += (R)cx * ux; cF += (R)cx * Fx; cg += (R)cx * gx; }
+          if constexpr (cy != 0) { cu += (R)cy * uy; cF += (R)cy * Fy; cg += (R)cy * gy; }
+          if constexpr (cz != 0) { cu += (R)cz * uz; cF += (R)cz * Fz; cg += (R)cz * gz; }
+          const R even = K0 + cu * (K2 * cu + K4 * cF) + Kg * cg * cg;
+          const R odd = K1 * cu + K3 * cF;
+          const R pert_b = Agn * (R)B_coef<L>(I);
+          const R ds_i = one_m_om * d[I] + wi * (even + odd) - pert_b;
+          const R ds_j = one_m_om * d[J] + wi * (even - odd) - pert_b;
+          const R rodd = Kr * (R)inv_norm<L>(I) * cg;
+          emit(std::integral_constant<int, I>{}, ds_i, rodd);
+          emit(std::integral_constant<int, J>{}, ds_j, -rodd);
+        });
+        if (TOT) {
+          // recolouring scalars of this site for the next pull
+          const R bs = coef * inv_gn;
+          __builtin_nontemporal_store((float)fa_frac, scout + n.site);
+          __builtin_nontemporal_store((float)(bs * gx), scout + a.N + n.site);
+          __builtin_nontemporal_store((float)(bs * gy), scout + 2 * (size_t)a.N + n.site);
+          __builtin_nontemporal_store((float)(bs * gz), scout + 3 * (size_t)a.N + n.site);
         }
-      };
-      {
-        const R w0 = (R)L::w[0];
-        emit(std::integral_constant<int, 0>{}, one_m_om * d[0] + w0 * K0 - Agn * (R)B_coef<L>(0), R(0));
-      }
-      static_for<0, (L::Q - 1) / 2>([&](auto pc) {
-        constexpr int I = pair_first<L>(decltype(pc)::value);
-        constexpr int J = L::opp[I];
-        constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
-        const R wi = (R)L::w[I];
-        R cu = 0, cF = 0, cg = 0;
-        if constexpr (cx != 0) { cu += (R)cx * ux; cF += (R)cx * Fx; cg += (R)cx * gx; }
-        if constexpr (cy != 0) { cu += (R)cy * uy; cF += (R)cy * Fy; cg += (R)cy * gy; }
-        if constexpr (cz != 0) { cu += (R)cz * uz; cF += (R)cz * Fz; cg += (R)cz * gz; }
-        const R even = K0 + cu * (K2 * cu + K4 * cF) + Kg * cg * cg;
-        const R odd = K1 * cu + K3 * cF;
-        const R pert_b = Agn * (R)B_coef<L>(I);
-        const R ds_i = one_m_om * d[I] + wi * (even + odd) - pert_b;
-        const R ds_j = one_m_om * d[J] + wi * (even - odd) - pert_b;
-        const R rodd = Kr * (R)inv_norm<L>(I) * cg;
-        emit(std::integral_constant<int, I>{}, ds_i, rodd);
-        emit(std::integral_constant<int, J>{}, ds_j, -rodd);
-      });
-      if (TOT && (!MLP || valid_xy)) {
-        // recolouring scalars of this site for the next pull
-        const R bs = coef * inv_gn;
-        __builtin_nontemporal_store((float)fa_frac, scout + n.site);
-        __builtin_nontemporal_store((float)(bs * gx), scout + a.N + n.site);
-        __builtin_nontemporal_store((float)(bs * gy), scout + 2 * (size_t)a.N + n.site);
-        __builtin_nontemporal_store((float)(bs * gz), scout + 3 * (size_t)a.N + n.site);
-      }
-      if (FIELDS && (!MLP || valid_xy)) {
-        R* rA = (R*)fo.rho_a;
-        R* rB = (R*)fo.rho_b;
-        R* U = (R*)fo.u;
-        R* Fn = (R*)fo.fnc;
-        rA[n.site] = ra;
-        rB[n.site] = rb;
-        U[n.site] = ux; U[a.N + n.site] = uy; U[2 * (size_t)a.N + n.site] = uz;
-        Fn[n.site] = fnx; Fn[a.N + n.site] = fny; Fn[2 * (size_t)a.N + n.site] = fnz;
-        // bit 0 interface; with the closure, bit 1 force from the network,
-        // bit 2 explicit scan at an interface site outside its range
-        const bool fallback = MLP && flag && has_g && !use_net;
-        fo.flags[n.site] = (uint8_t)((flag ? 1 : 0) | (use_net ? 2 : 0) | (fallback ? 4 : 0));
+        if (FIELDS) {
+          R* rA = (R*)fo.rho_a;
+          R* rB = (R*)fo.rho_b;
+          R* U = (R*)fo.u;
+          R* Fn = (R*)fo.fnc;
+          rA[n.site] = ra;
+          rB[n.site] = rb;
+          U[n.site] = ux; U[a.N + n.site] = uy; U[2 * (size_t)a.N + n.site] = uz;
+          Fn[n.site] = fnx; Fn[a.N + n.site] = fny; Fn[2 * (size_t)a.N + n.site] = fnz;
+          // bit 0 interface; with the closure, bit 1 force from the network,
+          // bit 2 explicit scan at an interface site outside its range
+          const bool fallback = MLP && flag && has_g && !use_net;
+          fo.flags[n.site] = (uint8_t)((flag ? 1 : 0) | (use_net ? 2 : 0) | (fallback ? 4 : 0));
+        }
       }
     }
     if (more) commit_plane<T>(ring, plane_slot(z + 1 + T::RZ, T::NPL), nxt, tid);
@@ -958,25 +1001,45 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   }
 }
 
-template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
 __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::real* __restrict__ phi,
                                                     float* __restrict__ scout,
                                                     FieldPtrs fo, StepArgs a) {
   __shared__ CollideSmem<L, S, T, TOT> sm;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
-  collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, phi, scout, fo, a, tc, sm);
+  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM>(fin, fout, phi, scout, fo, a, tc, sm);
 }
 
 // collision pass with the learned near-contact closure
-template <class L, class S, class T, bool FIELDS, bool TOT>
+template <class L, class S, class T, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
 __global__ void __launch_bounds__(T::NT, 3) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
                                                            const typename Storage<S>::real* __restrict__ phi,
                                                            float* __restrict__ scout,
                                                         FieldPtrs fo, StepArgs a, const MlpPacked* __restrict__ net) {
   __shared__ CollideSmem<L, S, T, TOT, true> sm;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
-  collide_tile<L, S, T, true, FIELDS, TOT, true>(fin, fout, phi, scout, fo, a, tc, sm, net);
+  collide_tile<L, S, T, true, FIELDS, TOT, true, STREAM>(fin, fout, phi, scout, fo, a, tc, sm, net);
+}
+
+// The canonical layout (slot (i, x) = f_i(x)) of one colour block from the
+// layout a STREAM_EVEN pass leaves, where f_i(x) sits in the slot the pull of
+// opp(i) at x reads.  Writes planes i0 .. i1-1 to out[(i - i0) N + site];
+// E is an unsigned integer of the element's size (a bit copy).
+template <class L, class E>
+__global__ void __launch_bounds__(256) k_canonical(const E* __restrict__ f, E* __restrict__ out, int i0, int i1,
+                                                   StepArgs a) {
+  const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+  if (s >= a.N) return;
+  const uint32_t nxy = (uint32_t)a.nx * (uint32_t)a.ny;
+  const int z = s / nxy;
+  const uint32_t r = s - (uint32_t)z * nxy;
+  const int y = r / (uint32_t)a.nx, x = r - (uint32_t)y * a.nx;
+  const Nbr n = make_nbr(x, y, z, a);
+  static_for<0, L::Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    if (I >= i0 && I < i1) out[(size_t)(I - i0) * a.N + s] = pair_base<L, I>(f, a.N)[pull_index<L, L::opp[I]>(n, a.N)];
+  });
 }
 
 }  // namespace lbm

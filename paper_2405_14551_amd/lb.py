@@ -20,6 +20,7 @@ LATTICE = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32t": 4, "f16t": 5, "bf16t": 6}
 TOTAL_LAYOUTS = ("f32t", "f16t", "bf16t")
 NC_MODE = {"off": 0, "explicit": 1, "mlp": 2}
+STREAMING = {"two_copies": 0, "in_place": 1}
 MLP_PARAMS = 6339
 MLP_ROW = 32
 FIELD_BITS = {"rho_a": 0, "rho_b": 1, "phi": 2, "u": 3, "f_nc": 4, "flags": 5, "labels": 6}
@@ -53,6 +54,7 @@ class LbParams(ctypes.Structure):
         ("nc_A", ctypes.c_double), ("nc_hmin", ctypes.c_double), ("nc_hmax", ctypes.c_double),
         ("phi_interface", ctypes.c_double),
         ("diag_every", ctypes.c_int),
+        ("streaming", ctypes.c_int),
     ]
 
 
@@ -147,7 +149,8 @@ def lattice_table(name):
 
 def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), walls=(0, 0, 0),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
-                nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0):
+                nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0,
+                streaming="two_copies"):
     p = LbParams()
     lib().lb_params_default(ctypes.byref(p))
     p.lattice = LATTICE[lattice]
@@ -162,6 +165,7 @@ def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), wa
     p.nc_A, p.nc_hmin, p.nc_hmax = float(nc_A), float(nc_hmin), float(nc_hmax)
     p.phi_interface = float(phi_interface)
     p.diag_every = int(diag_every)
+    p.streaming = STREAMING[streaming]
     return p
 
 
@@ -278,11 +282,16 @@ class Simulation:
         check(lib().lb_state_bytes(self.h, ctypes.byref(v)))
         return v.value
 
-    def get_state(self):
+    def get_state(self, host=False):
         """Post-collision state on the device.  Per-colour layouts: a tensor
         (2, q, nz, ny, nx) of the storage type.  Total layouts: a uint8 tensor
-        of the raw bytes (use ``split_total_state``)."""
+        of the raw bytes (use ``split_total_state``).  host=True: the raw bytes
+        as a numpy uint8 array, copied by the library to host memory."""
         nx, ny, nz = self.shape
+        if host:
+            a = np.empty((self.state_bytes(),), dtype=np.uint8)
+            check(lib().lb_get_state(self.h, ctypes.c_void_p(a.ctypes.data), a.nbytes, 0))
+            return a
         if self.total:
             t = self.torch.empty((self.state_bytes(),), dtype=self.torch.uint8, device=self.device)
         else:

@@ -89,6 +89,9 @@ def test_bad_enum_and_null():
     p.wall[0] = 2
     assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
     p = lb.make_params()
+    p.streaming = 2
+    assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
+    p = lb.make_params()
     assert L.lb_create(ctypes.byref(p), 2, None, ctypes.byref(h)) == lb.LB_EINVAL
     assert L.lb_create(None, 1, None, ctypes.byref(h)) == lb.LB_EINVAL
     assert L.lb_destroy(None) == lb.LB_OK
@@ -118,6 +121,9 @@ def test_ensemble_argument_checks():
     arr[0] = lb.make_params(lattice="D3Q19", storage="f32", nc="mlp", shape=(16, 8, 8))
     arr[1] = lb.make_params(lattice="D3Q19", storage="f32", nc="mlp", shape=(16, 8, 8))
     assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # no closure in ensembles
+    arr[0] = lb.make_params(lattice="D3Q19", storage="f32", shape=(16, 8, 8))
+    arr[1] = lb.make_params(lattice="D3Q19", storage="f32", shape=(16, 8, 8), streaming="in_place")
+    assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # ensembles use two copies
 
 
 def test_closure_calls_reject_null_arguments():

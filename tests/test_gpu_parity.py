@@ -465,32 +465,33 @@ def _column(t, x, y, z):
     return t[:, :, z, y, x].double().cpu().numpy()
 
 
-@pytest.mark.parametrize("storage,shape", [("f32", (512, 512, 192)), ("f32t", (768, 512, 256))])
-def test_lattice_past_4GiB_colour_block_sampled_sites(storage, shape):
+@pytest.mark.parametrize("storage,shape,streaming", [("f32", (512, 512, 192), "two_copies"),
+                                                    ("f32t", (768, 512, 256), "two_copies"),
+                                                    ("f32t", (768, 512, 256), "in_place")])
+def test_lattice_past_4GiB_colour_block_sampled_sites(storage, shape, streaming):
     """Lattices whose colour block (Q x sites x element bytes) exceeds 4 GiB:
     50M sites per-colour FP32 (5.4 GB per colour) and 100M sites FP32 total
-    layout (10.9 GB of populations).  One step from a developed state against
-    the oracle's windowed step at sampled sites, many of them at site indices
-    beyond what a 32-bit byte offset from the colour block's start reaches."""
+    layout (10.9 GB of populations), the latter also streamed in place.  One
+    step from a developed state against the oracle's windowed step at sampled
+    sites, many of them at site indices beyond what a 32-bit byte offset from
+    the colour block's start reaches.  In place, two consecutive steps are
+    checked: an odd-kind one (own slots) from the state after 5 steps, which
+    the library gathers from the streamed slots, and the even-kind one after
+    it (pull and push)."""
     nx, ny, nz = shape
     n = nx * ny * nz
     w = W.channel_3d(shape=shape, count=int(64 * n / (256 * 128 * 128)), radius=10.0, storage=storage)
     kw, cen, rad = W.sim_kwargs(w)
-    say(f"case lattice past 4 GiB {storage} {shape} ({n / 1e6:.0f}M sites, {len(rad)} droplets)")
+    kw["streaming"] = streaming
+    say(f"case lattice past 4 GiB {storage} {streaming} {shape} ({n / 1e6:.0f}M sites, {len(rad)} droplets)")
     q = 27
     assert q * n * 4 > 2 ** 32
     sim = lb.Simulation(**kw).init_droplets(cen, rad)
     sim.step(5)
-    pre = sim.get_state().clone()
-    sim.step(1)
-    post = sim.get_state()
-    if storage == "f32t":
-        gA, gB = _total_window_gatherer(sim, pre, 0), _total_window_gatherer(sim, pre, 1)
-        post_cols = [_total_window_gatherer(sim, post, k) for k in (0, 1)]
-        col = lambda x, y, z: [c(np.array([z]), np.array([y]), np.array([x]))[:, 0, 0, 0] for c in post_cols]
-    else:
-        gA, gB = _window_gatherer(pre, 0), _window_gatherer(pre, 1)
-        col = lambda x, y, z: list(_column(post, x, y, z))
+    states = [sim.get_state().clone()]
+    for _ in range(2 if streaming == "in_place" else 1):
+        sim.step(1)
+        states.append(sim.get_state().clone())
     rng = np.random.default_rng(7)
     first_far = int(np.ceil(2 ** 32 / (4 * q) / (nx * ny)))      # planes past a 4 GiB byte offset
     sites = [(nx - 1, ny - 1, nz - 1), (0, 0, nz - 1), (nx - 2, 1, nz - 2), (0, 0, 0)]
@@ -499,13 +500,23 @@ def test_lattice_past_4GiB_colour_block_sampled_sites(storage, shape):
     for _ in range(4):
         sites.append((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
     p = oparams(kw, np.float32)
-    worst = 0.0
-    for (x, y, z) in sites:
-        a, b, _ = step_window(p, gA, gB, (x, y, z))
-        na, nb = col(x, y, z)
-        e = max(np.abs(na - a).max(), np.abs(nb - b).max()) / np.abs(a + b).max()
-        worst = max(worst, e)
-        assert e < 2e-6, ((x, y, z), e)
-    say(f"  sampled {len(sites)} sites (planes >= {first_far} lie past 4 GiB), worst rel err {worst:.2e}")
-    del pre
+    for k in range(len(states) - 1):
+        pre, post = states[k], states[k + 1]
+        if storage == "f32t":
+            gA, gB = _total_window_gatherer(sim, pre, 0), _total_window_gatherer(sim, pre, 1)
+            post_cols = [_total_window_gatherer(sim, post, c) for c in (0, 1)]
+            col = lambda x, y, z: [c(np.array([z]), np.array([y]), np.array([x]))[:, 0, 0, 0] for c in post_cols]
+        else:
+            gA, gB = _window_gatherer(pre, 0), _window_gatherer(pre, 1)
+            col = lambda x, y, z: list(_column(post, x, y, z))
+        worst = 0.0
+        for (x, y, z) in sites:
+            a, b, _ = step_window(p, gA, gB, (x, y, z))
+            na, nb = col(x, y, z)
+            e = max(np.abs(na - a).max(), np.abs(nb - b).max()) / np.abs(a + b).max()
+            worst = max(worst, e)
+            assert e < 2e-6, ((x, y, z), k, e)
+        say(f"  step {6 + k}: sampled {len(sites)} sites (planes >= {first_far} lie past 4 GiB), "
+            f"worst rel err {worst:.2e}")
+    del states
     sim.close()
