@@ -116,7 +116,6 @@ class NaiveSim:
         newB = [[0.0] * N for _ in range(q)]
         fields = dict(phi=phi, rho_a=rhoA, rho_b=rhoB, u=[None] * N, f_nc=[None] * N,
                       flags=flag)
-        pre = 1.0 - 0.5 / p.tau
         for (x, y, z) in self.sites():
             s = self.idx(x, y, z)
             g = grad[s]
@@ -140,6 +139,12 @@ class NaiveSim:
                         break
             F = [p.body_force[a] + fnc[a] for a in range(3)]
             rho = rhoA[s] + rhoB[s]
+            tau = p.tau
+            if p.tau_b:
+                # harmonic mean of the colours' viscosities, weighted by density
+                nu_a, nu_b = (p.tau - 0.5) / 3.0, (p.tau_b - 0.5) / 3.0
+                tau = 3.0 / (rhoA[s] / (rho * nu_a) + rhoB[s] / (rho * nu_b)) + 0.5
+            pre = 1.0 - 0.5 / tau
             f = [pulled_A[i][s] + pulled_B[i][s] for i in range(q)]
             j = [sum(f[i] * self.c[i][a] for i in range(q)) for a in range(3)]
             u = [(j[a] + 0.5 * F[a]) / rho for a in range(3)]
@@ -154,7 +159,7 @@ class NaiveSim:
                 cg = ci[0] * g[0] + ci[1] * g[1] + ci[2] * g[2]
                 feq = self.w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
                 src = pre * self.w[i] * (3.0 * (cF - uF) + 9.0 * cu * cF)
-                val = f[i] - (f[i] - feq) / p.tau + src
+                val = f[i] - (f[i] - feq) / tau + src
                 cnorm = math.sqrt(ci[0] ** 2 + ci[1] ** 2 + ci[2] ** 2)
                 cos = 0.0
                 if gg > p.g_eps ** 2:

@@ -18,6 +18,9 @@ performs, for every fluid site and in this order:
 6.  near-contact force F_nc (Eq. near_cont_force, see ``near_contact_force``)
 7.  F = F_body + F_nc, u = (j + F/2) / rho                     [Guo forcing]
 8.  BGK on the total f = f~^A + f~^B with Guo source           [Eq. disteq]
+    at the local relaxation time of the mixture, 1/nu = (rho_A/rho)/nu_A +
+    (rho_B/rho)/nu_B, tau = 3 nu + 1/2 (the mixing rule under Eq. sigmaA);
+    one viscosity (tau_b = 0) gives tau everywhere
 9.  perturbation f* = f + A|g| [w_i (c_i.g)^2/|g|^2 - B_i]     [Omega^(2), A_A = A_B = A]
 10. recolouring f^A = (rho_A/rho) f* + beta rho_A rho_B / rho w_i cos(theta_i)
                 f^B = (rho_B/rho) f* - beta rho_A rho_B / rho w_i cos(theta_i)
@@ -51,7 +54,8 @@ class OracleParams:
     ny: int = 32
     nz: int = 32
     walls: tuple = (False, False, False)   # halfway bounce-back on both faces of that axis
-    tau: float = 1.0
+    tau: float = 1.0                       # relaxation time of colour A (of both if tau_b == 0)
+    tau_b: float = 0.0                     # relaxation time of colour B; 0: same as tau
     A: float = 0.01                        # perturbation amplitude A = A_A = A_B
     beta: float = 0.7                      # recolouring parameter
     rho0: float = 1.0
@@ -99,6 +103,8 @@ class OracleSim:
             raise ValueError("D2Q9 needs nz == 1")
         if p.tau <= 0.5:
             raise ValueError("tau must exceed 1/2")
+        if p.tau_b and p.tau_b <= 0.5:
+            raise ValueError("tau_b must exceed 1/2 (or be 0)")
         self.shape = (p.nz, p.ny, p.nx)
         self.n = (p.nx, p.ny, p.nz)
         self.walls = tuple(bool(b) for b in p.walls)
@@ -288,6 +294,19 @@ class OracleSim:
                 F[:, iz[use], iy[use], ix[use]] = Fm.T
         return F
 
+    def relaxation_time(self, rho_a, rho_b):
+        """Local relaxation time of the mixture (Sec. III.C.1, the mixing rule
+        stated with the surface tension, Eq. sigmaA): the inverse viscosity is
+        the density-weighted mean 1/nu = (rho_A/rho)/nu_A + (rho_B/rho)/nu_B
+        with nu_k = c_s^2 (tau_k - 1/2), and tau = nu/c_s^2 + 1/2.  With one
+        viscosity (tau_b == 0) this is tau at every site."""
+        p = self.p
+        if not p.tau_b:
+            return p.tau
+        rho = rho_a + rho_b
+        inv_nu = (rho_a / rho) / viscosity(p.tau) + (rho_b / rho) / viscosity(p.tau_b)
+        return 3.0 / inv_nu + 0.5
+
     # -------------------------------------------------------------------- step
     def step(self, n=1):
         for _ in range(n):
@@ -318,13 +337,14 @@ class OracleSim:
         # 7. force and velocity
         F = np.asarray(p.body_force, dtype=np.float64).reshape(3, 1, 1, 1) + f_nc
         u = (j + 0.5 * F) / rho
-        # 8. BGK + Guo source on the total
+        # 8. BGK + Guo source on the total, at the mixture's relaxation time
+        tau = self.relaxation_time(rho_a, rho_b)
         feq = self.equilibrium(rho, u)
         cu = np.einsum("ia,a...->i...", self.c, u)
         cF = np.einsum("ia,a...->i...", self.c, F)
         uF = (u * F).sum(0)
-        S = (1.0 - 0.5 / p.tau) * wq * (3.0 * (cF - uF) + 9.0 * cu * cF)
-        fpost = f - (f - feq) / p.tau + S
+        S = (1.0 - 0.5 / tau) * wq * (3.0 * (cF - uF) + 9.0 * cu * cF)
+        fpost = f - (f - feq) / tau + S
         # 9. perturbation
         gg = (g * g).sum(0)
         gn = np.sqrt(gg)

@@ -55,11 +55,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("tau_b", [0.0, 1.7])
 @pytest.mark.parametrize("name,shape,walls", CASES)
-def test_vectorised_equals_naive_per_site(name, shape, walls):
+def test_vectorised_equals_naive_per_site(name, shape, walls, tau_b):
     rng = np.random.default_rng(7)
     nx, ny, nz = shape
-    p = OracleParams(lattice=name, nx=nx, ny=ny, nz=nz, walls=walls, tau=0.8, A=0.05,
+    p = OracleParams(lattice=name, nx=nx, ny=ny, nz=nz, walls=walls, tau=0.8, tau_b=tau_b, A=0.05,
                      beta=0.7, body_force=(1e-3, -2e-3, 5e-4 if nz > 1 else 0.0),
                      nc=True, nc_A=0.05, phi_interface=0.95)
     sim = OracleSim(p)
@@ -170,17 +171,17 @@ def test_recolouring_beta_zero_proportional():
 
 
 # ---------------------------------------------------------------- viscosity
-@pytest.mark.parametrize("tau", [0.6, 1.0, 1.2])
-def test_shear_wave_viscosity(tau):
-    """u_x = U0 sin(2 pi y / L) decays as exp(-nu k^2 t) with nu = cs2 (tau - 1/2)."""
-    Ly = 64
-    p = OracleParams(lattice="D2Q9", nx=2, ny=Ly, nz=1, tau=tau, A=0.0, beta=0.0)
+def _shear_wave_nu(p, frac_a=1.0):
+    """Viscosity fitted to the decay of u_x = U0 sin(2 pi y / L) in a
+    composition-uniform fluid (colour A fraction frac_a of the density)."""
+    Ly = p.ny
     sim = OracleSim(p)
     y = np.arange(Ly).reshape(1, Ly, 1) * np.ones((1, 1, 2))
     k = 2 * np.pi / Ly
     u = np.zeros((3, 1, Ly, 2))
     u[0] = 1e-3 * np.sin(k * y)
-    sim.set_state(sim.equilibrium(np.ones((1, Ly, 2)), u), np.zeros((9, 1, Ly, 2)))
+    feq = sim.equilibrium(np.ones((1, Ly, 2)), u)
+    sim.set_state(frac_a * feq, (1.0 - frac_a) * feq)
     steps = 400
     amps = []
     for t in range(steps):
@@ -191,8 +192,56 @@ def test_shear_wave_viscosity(tau):
     ts = np.array([a[0] for a in amps], float)
     lg = np.log(np.array([a[1] for a in amps]))
     slope = np.polyfit(ts, lg, 1)[0]
-    nu_fit = -slope / k ** 2
+    return -slope / k ** 2
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.2])
+def test_shear_wave_viscosity(tau):
+    """u_x = U0 sin(2 pi y / L) decays as exp(-nu k^2 t) with nu = cs2 (tau - 1/2)."""
+    p = OracleParams(lattice="D2Q9", nx=2, ny=64, nz=1, tau=tau, A=0.0, beta=0.0)
+    nu_fit = _shear_wave_nu(p)
     assert abs(nu_fit / viscosity(tau) - 1) < 0.01, nu_fit
+
+
+@pytest.mark.parametrize("frac_a", [0.25, 0.7])
+def test_mixture_viscosity_is_density_weighted_harmonic_mean(frac_a):
+    """Two colours of viscosities 0.1 and 0.5 mixed uniformly (no gradient, so
+    no perturbation, and recolouring keeps the fractions): a shear wave
+    decays at the mixture viscosity 1/nu = x_A/nu_A + x_B/nu_B of the mixing
+    rule stated with the surface tension (Sec. III.C.1), within 1%; the
+    arithmetic mean x_A nu_A + x_B nu_B is off by more than 30%."""
+    tau_a, tau_b = 0.8, 2.0
+    nu_a, nu_b = viscosity(tau_a), viscosity(tau_b)
+    p = OracleParams(lattice="D2Q9", nx=2, ny=64, nz=1, tau=tau_a, tau_b=tau_b, A=0.01, beta=0.7)
+    nu_fit = _shear_wave_nu(p, frac_a)
+    harmonic = 1.0 / (frac_a / nu_a + (1 - frac_a) / nu_b)
+    arithmetic = frac_a * nu_a + (1 - frac_a) * nu_b
+    assert abs(nu_fit / harmonic - 1) < 0.01, (nu_fit, harmonic)
+    assert abs(nu_fit / arithmetic - 1) > 0.3
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+def test_pure_colours_relax_at_their_own_tau(name):
+    """phi == +1 (rho_B = 0) relaxes at tau_A and phi == -1 (rho_A = 0) at
+    tau_B: each reduces to textbook single-component BGK with Guo forcing at
+    its own relaxation time."""
+    rng = np.random.default_rng(12)
+    nz = 1 if name == "D2Q9" else 4
+    L = make_lattice(name)
+    for colour, tau in ((0, 0.7), (1, 1.6)):
+        p = OracleParams(lattice=name, nx=6, ny=5, nz=nz, walls=(False, True, False), tau=0.7,
+                         tau_b=1.6, A=0.05, beta=0.7, nc=True, body_force=(2e-4, 0, 0))
+        sim = OracleSim(p)
+        q = sim.lat.q
+        f = sim.w.reshape(q, 1, 1, 1) * rng.uniform(0.8, 1.2, (q,) + sim.shape)
+        z = np.zeros_like(f)
+        sim.set_state(*((f, z) if colour == 0 else (z, f)))
+        ref = f.copy()
+        for _ in range(5):
+            sim.step()
+            ref = _textbook_bgk_guo(ref, L.c.tolist(), L.w, L.opp, tau, p.body_force, p.walls)
+        got = sim.fA if colour == 0 else sim.fB
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15)
 
 
 # --------------------------------------------------------------- Poiseuille
