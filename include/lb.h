@@ -112,7 +112,8 @@ typedef struct lb_params {
   int nc_mode;            /* lb_nc_mode                                                  */
   int nx, ny, nz;         /* sites per axis; nz must be 1 for D2Q9                       */
   int wall[3];            /* per axis: 0 periodic, 1 halfway bounce-back wall on both faces */
-  double tau;             /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3              */
+  double tau;             /* BGK relaxation time of colour A (of both if tau_b == 0), > 1/2;
+                             nu = (tau - 1/2)/3                                          */
   double A;               /* perturbation amplitude A = A_A = A_B                        */
   double beta;            /* recolouring parameter                                       */
   double rho0;            /* reference total density (initial state and storage shift)   */
@@ -124,6 +125,11 @@ typedef struct lb_params {
   double phi_interface;   /* interface flag threshold phi_I in (0, 1)                    */
   int diag_every;         /* run the watchdog every this many steps inside lb_step (0 = never) */
   int streaming;          /* lb_streaming                                                */
+  double tau_b;           /* relaxation time of colour B, > 1/2, or 0 for one viscosity.
+                             Different viscosities mix per site (paper Sec. III.C.1, the
+                             rule stated with the surface tension, Eq. sigmaA):
+                             1/nu = (rho_A/rho)/nu_A + (rho_B/rho)/nu_B, and BGK and the
+                             forcing use tau = 3 nu + 1/2                                */
 } lb_params;
 
 typedef struct lb_handle lb_handle;

@@ -148,6 +148,9 @@ struct lb_handle {
     a.QN = (uint64_t)q * N;
     a.omega = 1.0 / p.tau;
     a.guo = 1.0 - 0.5 / p.tau;
+    a.visc_mix = p.tau_b != 0.0 && p.tau_b != p.tau;
+    a.inv_nu_a = 3.0 / (p.tau - 0.5);
+    a.inv_nu_b = a.visc_mix ? 3.0 / (p.tau_b - 0.5) : a.inv_nu_a;
     a.A = p.A;
     a.beta = p.beta;
     a.half_rho0 = 0.5 * p.rho0;
@@ -240,6 +243,8 @@ static int validate(const lb_params* p) {
                 N * span * storage_bytes(p->storage));
   if (N > 2147483647.0) return fail(LB_EINVAL, "at most 2^31 - 1 sites (droplet labels are int32)");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must exceed 1/2");
+  if (p->tau_b != 0.0 && (!(p->tau_b > 0.5) || !std::isfinite(p->tau_b)))
+    return fail(LB_EINVAL, "tau_b must exceed 1/2 (or be 0 for one viscosity)");
   if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive");
   if (!(p->phi_interface > 0.0 && p->phi_interface < 1.0)) return fail(LB_EINVAL, "phi_interface must lie in (0,1)");
   if (!std::isfinite(p->A) || !std::isfinite(p->beta)) return fail(LB_EINVAL, "A and beta must be finite");

@@ -55,7 +55,10 @@ struct Storage;
 // out-of-range accesses return 0 / are dropped instead of faulting
 // cache-policy operand of the stores: non-temporal (written once, read back
 // only after the whole pass), so the lines do not linger dirty in L2
-constexpr int CPOL_NT = 2;
+#ifndef LB_STORE_CPOL
+#define LB_STORE_CPOL 2
+#endif
+constexpr int CPOL_NT = LB_STORE_CPOL;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
@@ -146,6 +149,8 @@ struct StepArgs {
   uint64_t QN;       // Q * N (elements per colour block)
   double omega;      // 1/tau
   double guo;        // 1 - 1/(2 tau)
+  int visc_mix;      // colours of different viscosity: tau from the mixture at each site
+  double inv_nu_a, inv_nu_b;  // 1/nu_k = 3/(tau_k - 1/2)
   double A;          // perturbation amplitude
   double beta;       // recolouring
   double half_rho0;  // shift per colour is w_i * rho0 / 2
@@ -726,7 +731,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   if constexpr (MLP) mlp_stage(sm.net, net, tid, T::NT);
   __syncthreads();
 
-  const R omega = (R)a.omega, guo = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
+  const R omega_1 = (R)a.omega, guo_1 = (R)a.guo, Aamp = (R)a.A, beta = (R)a.beta;
   const R hshift = (R)a.half_rho0, phiI = (R)a.phi_I;
   const int c0 = (ty + T::RAD) * T::TXH + (tx + T::RAD);
   // populations through buffer resources over velocity pairs: one 32-bit lane
@@ -900,6 +905,14 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         }
         const R ra = hshift + sa, rb = hshift + sb;
         const R inv_rho = R(1) / rho;
+        R omega = omega_1, guo = guo_1;
+        if (a.visc_mix) {
+          // relaxation time of the mixture (Sec. III.C.1, with Eq. sigmaA):
+          // 1/nu = (rho_A/rho)/nu_A + (rho_B/rho)/nu_B, tau = 3 nu + 1/2
+          const R inv_nu = (ra * (R)a.inv_nu_a + rb * (R)a.inv_nu_b) * inv_rho;
+          omega = R(1) / (R(3) / inv_nu + R(0.5));
+          guo = R(1) - R(0.5) * omega;
+        }
         const R Fx = (R)a.fx + fnx, Fy = (R)a.fy + fny, Fz = (R)a.fz + fnz;
         const R ux = (jx + R(0.5) * Fx) * inv_rho;
         const R uy = (jy + R(0.5) * Fy) * inv_rho;

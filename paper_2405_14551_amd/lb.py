@@ -55,6 +55,7 @@ class LbParams(ctypes.Structure):
         ("phi_interface", ctypes.c_double),
         ("diag_every", ctypes.c_int),
         ("streaming", ctypes.c_int),
+        ("tau_b", ctypes.c_double),
     ]
 
 
@@ -150,7 +151,7 @@ def lattice_table(name):
 def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), walls=(0, 0, 0),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
                 nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0,
-                streaming="two_copies"):
+                streaming="two_copies", tau_b=0.0):
     p = LbParams()
     lib().lb_params_default(ctypes.byref(p))
     p.lattice = LATTICE[lattice]
@@ -166,6 +167,7 @@ def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), wa
     p.phi_interface = float(phi_interface)
     p.diag_every = int(diag_every)
     p.streaming = STREAMING[streaming]
+    p.tau_b = float(tau_b)
     return p
 
 

@@ -58,6 +58,9 @@ def _create(**kw):
 @pytest.mark.parametrize("kw", [
     dict(tau=0.5),
     dict(tau=0.3),
+    dict(tau_b=0.5),
+    dict(tau_b=-1.0),
+    dict(tau_b=float("nan")),
     dict(shape=(0, 4, 4)),
     dict(lattice="D2Q9", shape=(8, 8, 2)),
     dict(lattice="D2Q9", shape=(8, 8, 1), walls=(0, 0, 1)),

@@ -28,7 +28,7 @@ CHANNELS = [
          centres=[[21.17, 9.77, 6.81], [33.17, 10.11, 6.37]], radii=[4.0, 4.0]),
     dict(shape=(64, 16, 12), walls=(0, 0, 0), tau=0.7, A=0.01, body_force=(0.0, 1e-5, 0.0),
          centres=[[20.3, 7.9, 5.6]], radii=[4.5]),
-    dict(shape=(40, 24, 20), walls=(0, 0, 1), tau=1.1, A=0.015, body_force=(1e-5, 0.0, 2e-6),
+    dict(shape=(40, 24, 20), walls=(0, 0, 1), tau=1.1, tau_b=0.6, A=0.015, body_force=(1e-5, 0.0, 2e-6),
          centres=[[12.3, 11.7, 10.2], [26.8, 12.1, 9.9]], radii=[5.5, 5.5]),
 ]
 
@@ -44,7 +44,8 @@ def make(storage="f64", lattice="D3Q19"):
 def oracle(c, lattice, steps):
     nx, ny, nz = c["shape"]
     p = OracleParams(lattice=lattice, nx=nx, ny=ny, nz=nz, walls=tuple(bool(w) for w in c["walls"]),
-                     tau=c["tau"], A=c["A"], beta=0.7, body_force=tuple(c["body_force"]), nc=True)
+                     tau=c["tau"], tau_b=c.get("tau_b", 0.0), A=c["A"], beta=0.7,
+                     body_force=tuple(c["body_force"]), nc=True)
     return OracleSim(p).init_droplets(c["centres"], c["radii"]).step(steps)
 
 

@@ -59,8 +59,8 @@ STORAGES = ["f64", "f32", "f16", "bf16", "f32t", "f16t", "bf16t"]
 def test_in_place_equals_two_copies(lat, shape, walls, nc, storage):
     say(f"case in place vs two copies {lat} {storage} {shape} walls={walls} nc={nc}")
     cen, rad = _drops(shape, lat != "D2Q9")
-    kw = dict(lattice=lat, storage=storage, nc=nc, shape=shape, walls=walls, tau=0.9, A=0.02,
-              body_force=(2e-5, 1e-6, 0), u0=(0.01, -0.005, 0.0), nc_A=0.03)
+    kw = dict(lattice=lat, storage=storage, nc=nc, shape=shape, walls=walls, tau=0.9, tau_b=1.3,
+              A=0.02, body_force=(2e-5, 1e-6, 0), u0=(0.01, -0.005, 0.0), nc_A=0.03)
     ab = lb.Simulation(**kw).init_droplets(cen, rad)
     ip = lb.Simulation(streaming="in_place", **kw).init_droplets(cen, rad)
     _same(ab, ip)
