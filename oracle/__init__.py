@@ -18,6 +18,8 @@ naive    independent per-site Python-loop step for tiny lattices
 ccl      connected-component droplet labels (breadth-first search)
 mlp      FP64 reference of the near-contact MLP closure (forward, backward,
          Adam) used to check the GPU training kernels
+fp16c    the FP16C 16-bit storage format (1 sign, 4 exponent, 11 significand
+         bits) by its definition: decode, round-to-nearest-even encode
 
 Parity pins: every function documents which identity, closed form or brute
 force check pins it; the checks live under ``tests/`` (marker ``not gpu``).
