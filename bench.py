@@ -27,8 +27,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS & % HBM roofline, 2-comp D3Q27; FP16-store/learned vs plain FP32"
-ELEM = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32t": 4, "f16t": 2, "bf16t": 2}
-TOTAL = ("f32t", "f16t", "bf16t")
+ELEM = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32t": 4, "f16t": 2, "bf16t": 2, "f16ct": 2}
+TOTAL = ("f32t", "f16t", "bf16t", "f16ct")
 NSC_BYTES = 16  # recolouring scalars of the total layout, per site
 
 
@@ -375,7 +375,7 @@ def main():
         vs = min(args.steps, 200)
         var = {}
         for st, mode in (("f32t", "two_copies"), ("f16t", "two_copies"), ("bf16t", "two_copies"),
-                         ("f32", "in_place"), ("f16t", "in_place")):
+                         ("f16ct", "two_copies"), ("f32", "in_place"), ("f16t", "in_place")):
             name = st if mode == "two_copies" else f"{st}_in_place"
             var[name] = time_storage(kw, cen, rad, st, vs, args.warmup, mode)
             var[name]["vs_plain_f32"] = round(var[name]["MLUPS"] / mlups, 3)

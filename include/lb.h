@@ -65,7 +65,13 @@ typedef enum lb_lattice { LB_D2Q9 = 0, LB_D3Q19 = 1, LB_D3Q27 = 2 } lb_lattice;
  *    b = beta (rho_A rho_B / rho) n (n the unit colour gradient).  The
  *    recolouring equations (Eqs. ome3_1, ome3_2) give the colours exactly:
  *    f^A_i = a f*_i + (w_i / |c_i|) c_i . b, f^B_i = f*_i - f^A_i.  The two-colour
- *    step is unchanged; the state is Q storage values + 16 bytes per site. */
+ *    step is unchanged; the state is Q storage values + 16 bytes per site.
+ *  - LB_F16C_TOTAL stores T_i in FP16C, the custom 16-bit format the paper
+ *    cites for shifted populations (Sec. IV.A, second group): 1 sign, 4
+ *    exponent (bias 15) and 11 significand bits, i.e. binary16 with one more
+ *    significand bit and half its rounding error; normal magnitudes
+ *    2^-14 .. 2 - 2^-11, subnormals in steps of 2^-25, no infinities (values
+ *    beyond the largest saturate).  Rounded to nearest, ties to even. */
 typedef enum lb_storage {
   LB_F64 = 0,
   LB_F32 = 1,
@@ -73,7 +79,8 @@ typedef enum lb_storage {
   LB_BF16_SHIFTED = 3,
   LB_F32_TOTAL = 4,
   LB_F16_TOTAL = 5,
-  LB_BF16_TOTAL = 6
+  LB_BF16_TOTAL = 6,
+  LB_F16C_TOTAL = 7
 } lb_storage;
 
 /* Near-contact force: off; the explicit scan (Eq. near_cont_force); or the

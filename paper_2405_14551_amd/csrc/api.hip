@@ -65,12 +65,15 @@ size_t storage_bytes(int st) {
     case LB_F16_SHIFTED:
     case LB_BF16_SHIFTED:
     case LB_F16_TOTAL:
-    case LB_BF16_TOTAL: return 2;
+    case LB_BF16_TOTAL:
+    case LB_F16C_TOTAL: return 2;
   }
   return 0;
 }
 
-bool total_layout(int st) { return st == LB_F32_TOTAL || st == LB_F16_TOTAL || st == LB_BF16_TOTAL; }
+bool total_layout(int st) {
+  return st == LB_F32_TOTAL || st == LB_F16_TOTAL || st == LB_BF16_TOTAL || st == LB_F16C_TOTAL;
+}
 
 }  // namespace
 

@@ -11,7 +11,9 @@
 namespace lbm {
 
 // per-colour layouts, then the total layout (total population + recolouring scalars)
-enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32T = 4, ST_F16T = 5, ST_BF16T = 6 };
+enum StorageKind {
+  ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32T = 4, ST_F16T = 5, ST_BF16T = 6, ST_F16CT = 7
+};
 inline bool is_total(int st) { return st >= ST_F32T; }
 
 // pass-2 tile: 64 x-sites (one wave per row) by 4 rows unless overridden at build time

@@ -23,6 +23,7 @@ struct InPlaceLaunch {
       case ST_F32T: return B::template phase_total_t<float, true>(f, scin, phi, a, s);
       case ST_F16T: return B::template phase_total_t<_Float16, true>(f, scin, phi, a, s);
       case ST_BF16T: return B::template phase_total_t<__bf16, true>(f, scin, phi, a, s);
+      case ST_F16CT: return B::template phase_total_t<F16C, true>(f, scin, phi, a, s);
     }
     return hipErrorInvalidValue;
   }
@@ -49,6 +50,7 @@ struct InPlaceLaunch {
       case ST_F32T: return collide_s<float, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
       case ST_F16T: return collide_s<_Float16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
       case ST_BF16T: return collide_s<__bf16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_F16CT: return collide_s<F16C, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
     }
     return hipErrorInvalidValue;
   }
@@ -73,6 +75,7 @@ struct InPlaceLaunch {
         LB_MLP_CASE(ST_F32T, float, true)
         LB_MLP_CASE(ST_F16T, _Float16, true)
         LB_MLP_CASE(ST_BF16T, __bf16, true)
+        LB_MLP_CASE(ST_F16CT, F16C, true)
       }
 #undef LB_MLP_CASE
     }
@@ -100,6 +103,7 @@ struct InPlaceLaunch {
       case ST_BF16:
       case ST_F16T:
       case ST_BF16T:
+      case ST_F16CT:
         k_canonical<L, uint16_t><<<grid, block, 0, s>>>((const uint16_t*)f, (uint16_t*)out, i0, i1, a);
         break;
       default:

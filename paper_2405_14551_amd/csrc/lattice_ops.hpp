@@ -51,6 +51,7 @@ struct Launch {
       case ST_F32T: return phase_total_t<float>(fin, scin, phi, a, s);
       case ST_F16T: return phase_total_t<_Float16>(fin, scin, phi, a, s);
       case ST_BF16T: return phase_total_t<__bf16>(fin, scin, phi, a, s);
+      case ST_F16CT: return phase_total_t<F16C>(fin, scin, phi, a, s);
     }
     return hipErrorInvalidValue;
   }
@@ -91,6 +92,7 @@ struct Launch {
       case ST_F32T: return collide_s<float, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
       case ST_F16T: return collide_s<_Float16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
       case ST_BF16T: return collide_s<__bf16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_F16CT: return collide_s<F16C, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
     }
     return hipErrorInvalidValue;
   }
@@ -127,6 +129,7 @@ struct Launch {
         LB_MLP_CASE(ST_F32T, float, true)
         LB_MLP_CASE(ST_F16T, _Float16, true)
         LB_MLP_CASE(ST_BF16T, __bf16, true)
+        LB_MLP_CASE(ST_F16CT, F16C, true)
       }
 #undef LB_MLP_CASE
     }
@@ -162,6 +165,7 @@ struct Launch {
       case ST_F32T: return init_total_t<float>(f, sc, phi, fo, drops, a, s);
       case ST_F16T: return init_total_t<_Float16>(f, sc, phi, fo, drops, a, s);
       case ST_BF16T: return init_total_t<__bf16>(f, sc, phi, fo, drops, a, s);
+      case ST_F16CT: return init_total_t<F16C>(f, sc, phi, fo, drops, a, s);
     }
     return hipErrorInvalidValue;
   }
@@ -195,6 +199,7 @@ struct Launch {
       case ST_F32T: return ensemble_s<float, true>(nc, fields, chans, items, nitems, parity, s);
       case ST_F16T: return ensemble_s<_Float16, true>(nc, fields, chans, items, nitems, parity, s);
       case ST_BF16T: return ensemble_s<__bf16, true>(nc, fields, chans, items, nitems, parity, s);
+      case ST_F16CT: return ensemble_s<F16C, true>(nc, fields, chans, items, nitems, parity, s);
     }
     return hipErrorInvalidValue;
   }

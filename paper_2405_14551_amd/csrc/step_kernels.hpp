@@ -140,6 +140,47 @@ struct Storage<__bf16> {
   __device__ static __forceinline__ void store(__bf16* p, float d, float) { *p = (__bf16)d; }
 };
 
+// FP16C: 16 bits with 1 sign, 4 exponent (bias 15) and 11 significand bits,
+// one significand bit more than IEEE binary16 and half its rounding error, the
+// custom format the paper's mixed-precision section cites for shifted
+// populations (Sec. IV.A, second group).  Normal magnitudes 2^-14 .. 2 - 2^-11,
+// subnormals in steps of 2^-25, no infinities (encoding saturates).  Used by
+// the total layout only, whose shifted totals stay far below 2.
+struct F16C {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ float f16c_decode(uint32_t h) {
+  // the fields moved into FP32 position read as 2^-112 times the value: a
+  // normal FP32 number for normal codes, an FP32 subnormal (m 2^-137) for
+  // subnormal ones; the exact product with 2^112 rebiases both (FP32
+  // subnormals are kept, not flushed, in this build)
+  const uint32_t b = ((h & 0x7FFFu) << 12) | ((h & 0x8000u) << 16);
+  return __builtin_bit_cast(float, b) * 0x1p112f;
+}
+
+// nearest FP16C value, ties to the even code
+__device__ __forceinline__ uint32_t f16c_encode(float x) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, x);
+  const uint32_t a = u & 0x7FFFFFFFu;
+  // |x| >= 2^-14: round the FP32 significand to 11 bits on the integer bits
+  // (adding 0x7FF plus the kept lsb rounds half to even; a carry moves into
+  // the exponent) and rebias by 127 - 15 (folded into the same sum: the bias
+  // is a multiple of 2^12); beyond the largest value, saturate
+  const uint32_t nrm = (a + (0x7FFu - (112u << 23)) + ((a >> 12) & 1u)) >> 12;
+  // |x| < 2^-14: the FP32 sum with 0.25, whose ulp is 2^-25, rounds |x| to the
+  // subnormal grid (to nearest, ties to even); its low bits are the code
+  const uint32_t sub = __builtin_bit_cast(uint32_t, __builtin_fabsf(x) + 0.25f) - 0x3E800000u;
+  const uint32_t h = a >= 0x38800000u ? min(nrm, 0x7FFFu) : sub;
+  return h | ((u >> 16) & 0x8000u);
+}
+
+template <>
+struct Storage<F16C> {
+  using real = float;
+  static constexpr uint32_t ES = 2;
+};
+
 // ----------------------------------------------------------------------------
 // per-launch constants (passed by value, lives in SGPRs)
 struct StepArgs {
@@ -513,19 +554,25 @@ __device__ __forceinline__ int nc_scan_global(const R* __restrict__ phi, int x, 
 constexpr int NSC = 4;  // scalars per site: a, b_x, b_y, b_z
 
 template <class S>
-__device__ __forceinline__ float total_load(const S* p) { return (float)(*p); }
-template <class S>
 __device__ __forceinline__ float total_bload(__amdgpu_buffer_rsrc_t r, uint32_t vo) {
   if constexpr (sizeof(S) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, 0));
+  else if constexpr (std::is_same_v<S, F16C>) return f16c_decode(__builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, 0));
   else return (float)__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, 0));
 }
 template <class S>
 __device__ __forceinline__ void total_bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
-  if constexpr (sizeof(S) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, CPOL_NT);
-  else __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r, vo, so, CPOL_NT);
+  if constexpr (sizeof(S) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, CPOL_NT);
+  else if constexpr (std::is_same_v<S, F16C>)
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)f16c_encode(v), r, vo, so, CPOL_NT);
+  else
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r, vo, so, CPOL_NT);
 }
 template <class S>
-__device__ __forceinline__ void total_store(S* p, float v) { *p = (S)v; }
+__device__ __forceinline__ void total_store(S* p, float v) {
+  if constexpr (std::is_same_v<S, F16C>) p->bits = (uint16_t)f16c_encode(v);
+  else *p = (S)v;
+}
 template <>
 __device__ __forceinline__ void total_store<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
 

@@ -353,11 +353,19 @@ def test_mass_conservation_gpu():
 
 
 # --------------------------------------------------------------- total layout
+def total_T(sim, T):
+    """Stored totals as float64 (FP16C codes decoded by the format's definition)."""
+    if sim.storage == "f16ct":
+        from oracle import fp16c
+        return fp16c.decode(T.cpu().numpy().view(np.uint16))
+    return T.double().cpu().numpy()
+
+
 def total_to_colours(sim, raw, rho0=1.0):
     """Colours of a total-layout state by the layout's definition:
     f* = T + w rho0, f^A = a f* + (w / |c|) c . b, f^B = f* - f^A."""
     T, sc = sim.split_total_state(raw)
-    T = T.double().cpu().numpy()
+    T = total_T(sim, T)
     sc = sc.double().cpu().numpy()
     from oracle.lattice import make_lattice
     L = make_lattice(sim.lattice)
@@ -427,6 +435,75 @@ def test_total_layout_full_size_sampled_sites():
         worst = max(worst, e)
         assert e < 2e-6, ((x, y, z), e)
     say(f"  total layout: sampled {len(sites)} sites, worst rel err {worst:.2e}")
+    sim.close()
+
+
+def test_fp16c_init_codes_exact():
+    """FP16C total layout at t = 0: every stored code is the oracle's FP16C
+    encoding (oracle/fp16c.py) of the FP32-rounded shifted total
+    T_i = f^eq_i(rho, u0) - w_i rho0 (both sides decide in FP32)."""
+    from oracle import fp16c
+    from oracle.lattice import make_lattice
+    kw = dict(lattice="D3Q27", storage="f16ct", nc="explicit", shape=(40, 32, 32), walls=(0, 1, 1),
+              u0=(0.02, -0.01, 0.005))
+    cen = np.array([[11.13, 15.77, 16.21], [29.61, 16.19, 15.83]])
+    say("case fp16c init codes")
+    sim = lb.Simulation(**kw).init_droplets(cen, [7.5, 7.5])
+    T, _ = sim.split_total_state(sim.get_state())
+    codes = T.cpu().numpy().view(np.uint16)
+    orc = OracleSim(oparams(kw)).init_droplets(cen, [7.5, 7.5])
+    f = orc.fields()
+    rho = f["rho_a"] + f["rho_b"]
+    L = make_lattice("D3Q27")
+    u0 = np.array(kw["u0"])
+    cu = (L.c @ u0).reshape(-1, 1, 1, 1)
+    w = L.w.reshape(-1, 1, 1, 1)
+    T_orc = w * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * (u0 @ u0)))
+    want = fp16c.encode(T_orc.astype(np.float32))
+    n_bad = int((codes != want).sum())
+    say(f"  {codes.size} codes, {n_bad} differ")
+    assert n_bad == 0
+    sim.close()
+
+
+def test_fp16c_full_size_sampled_sites():
+    """The channel workload in the FP16C total layout: one GPU step from a
+    developed state against the oracle's windowed step; each stored total is
+    the oracle's total rounded to FP16C (within half a step of it, plus the
+    FP32 arithmetic's 2e-6 of the population scale), and the flags agree."""
+    from oracle.lattice import make_lattice
+    w = W.channel_3d(storage="f16ct")
+    kw, cen, rad = W.sim_kwargs(w)
+    say("case fp16c channel full size")
+    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    sim.step(30)
+    sA, sB = total_to_colours(sim, sim.get_state())
+    sim.step(1)
+    g = gpu_fields(sim, ("f_nc", "flags"))
+    Tn, _ = sim.split_total_state(sim.get_state())
+    Tn = total_T(sim, Tn)
+    wq = make_lattice("D3Q27").w
+    nx, ny, nz = kw["shape"]
+    rng = np.random.default_rng(8)
+    fnc_sites = np.argwhere(np.abs(g["f_nc"]).sum(0) > 0)
+    assert len(fnc_sites) > 0
+    sites = [tuple(int(v) for v in fnc_sites[j][::-1])
+             for j in rng.choice(len(fnc_sites), size=min(16, len(fnc_sites)), replace=False)]
+    sites += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (63, 3, 7), (64, 4, 8), (200, 1, 1)]
+    for _ in range(8):
+        sites.append((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    p = oparams(kw, np.float32)
+    worst = 0.0
+    for (x, y, z) in sites:
+        a, b, fl = step_window(p, sA, sB, (x, y, z))
+        T_orc = a + b - wq
+        half_step = np.maximum(np.abs(T_orc) * 2.0 ** -12, 2.0 ** -26)
+        d = np.abs(Tn[:, z, y, x] - T_orc)
+        excess = (d - half_step) / np.abs(a + b).max()
+        worst = max(worst, float(excess.max()))
+        assert np.all(excess < 2e-6), ((x, y, z), excess.max())
+        assert bool(g["flags"][z, y, x] & 1) == bool(fl["flags"]), (x, y, z)
+    say(f"  fp16c: sampled {len(sites)} sites, worst excess over half a step {worst:.2e}")
     sim.close()
 
 
