@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS & % HBM roofline, 2-comp D3Q27; FP16-store/learned vs plain FP32"
-ELEM = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32t": 4, "f16t": 2, "bf16t": 2, "f16ct": 2}
+ELEM = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32t": 4, "f16t": 2, "bf16t": 2, "f16ct": 2, "f32s": 4}
 TOTAL = ("f32t", "f16t", "bf16t", "f16ct")
 NSC_BYTES = 16  # recolouring scalars of the total layout, per site
 

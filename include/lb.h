@@ -58,7 +58,9 @@ typedef enum lb_lattice { LB_D2Q9 = 0, LB_D3Q19 = 1, LB_D3Q27 = 2 } lb_lattice;
  * equilibrium (paper: Sec. IV "Second group", Eqs. shift_f, shift-lbm,
  * shift-eq).
  *  - Per-colour layouts keep both colours f^k_i.  LB_F64 / LB_F32 store f^k_i;
- *    the 16-bit modes store f^k_i - w_i rho0 / 2 rounded to nearest even.
+ *    LB_F32_SHIFTED and the 16-bit modes store the shifted
+ *    f^k_i - w_i rho0 / 2 (Eq. shift_f per colour; 16-bit: rounded to
+ *    nearest even).
  *  - Total layouts keep the total post-collision population shifted by the
  *    rest equilibrium, T_i = f*_i - w_i rho0 (Eq. shift_f with rho0, u0 = 0), in
  *    the storage type, plus four FP32 scalars per site, a = rho_A / rho and
@@ -80,7 +82,8 @@ typedef enum lb_storage {
   LB_F32_TOTAL = 4,
   LB_F16_TOTAL = 5,
   LB_BF16_TOTAL = 6,
-  LB_F16C_TOTAL = 7
+  LB_F16C_TOTAL = 7,
+  LB_F32_SHIFTED = 8
 } lb_storage;
 
 /* Near-contact force: off; the explicit scan (Eq. near_cont_force); or the

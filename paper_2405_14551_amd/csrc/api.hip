@@ -61,7 +61,8 @@ size_t storage_bytes(int st) {
   switch (st) {
     case LB_F64: return 8;
     case LB_F32:
-    case LB_F32_TOTAL: return 4;
+    case LB_F32_TOTAL:
+    case LB_F32_SHIFTED: return 4;
     case LB_F16_SHIFTED:
     case LB_BF16_SHIFTED:
     case LB_F16_TOTAL:

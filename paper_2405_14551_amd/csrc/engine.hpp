@@ -12,9 +12,10 @@ namespace lbm {
 
 // per-colour layouts, then the total layout (total population + recolouring scalars)
 enum StorageKind {
-  ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32T = 4, ST_F16T = 5, ST_BF16T = 6, ST_F16CT = 7
+  ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32T = 4, ST_F16T = 5, ST_BF16T = 6, ST_F16CT = 7,
+  ST_F32S = 8  // per-colour, shifted populations in FP32
 };
-inline bool is_total(int st) { return st >= ST_F32T; }
+inline bool is_total(int st) { return st >= ST_F32T && st <= ST_F16CT; }
 
 // pass-2 tile: 64 x-sites (one wave per row) by 4 rows unless overridden at build time
 #ifndef LB_TILE_X
@@ -64,10 +65,10 @@ struct InPlaceOps {
 };
 
 // storages the learned closure is built for
-inline bool mlp_storage(int st) { return st == ST_F64 || st == ST_F32 || st >= ST_F32T; }
+inline bool mlp_storage(int st) { return st == ST_F64 || st == ST_F32 || is_total(st); }
 
 // storages the ensemble kernel is built for
-inline bool ensemble_storage(int st) { return st == ST_F64 || st == ST_F32 || st >= ST_F32T; }
+inline bool ensemble_storage(int st) { return st == ST_F64 || st == ST_F32 || is_total(st); }
 
 const LatticeOps* ops_d2q9();
 const LatticeOps* ops_d3q19();

@@ -20,6 +20,7 @@ struct InPlaceLaunch {
       case ST_F32: return B::template phase_t<float, true>(f, phi, a, s);
       case ST_F16: return B::template phase_t<_Float16, true>(f, phi, a, s);
       case ST_BF16: return B::template phase_t<__bf16, true>(f, phi, a, s);
+      case ST_F32S: return B::template phase_t<F32S, true>(f, phi, a, s);
       case ST_F32T: return B::template phase_total_t<float, true>(f, scin, phi, a, s);
       case ST_F16T: return B::template phase_total_t<_Float16, true>(f, scin, phi, a, s);
       case ST_BF16T: return B::template phase_total_t<__bf16, true>(f, scin, phi, a, s);
@@ -47,6 +48,7 @@ struct InPlaceLaunch {
       case ST_F32: return collide_s<float, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
       case ST_F16: return collide_s<_Float16, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
       case ST_BF16: return collide_s<__bf16, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
+      case ST_F32S: return collide_s<F32S, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
       case ST_F32T: return collide_s<float, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
       case ST_F16T: return collide_s<_Float16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
       case ST_BF16T: return collide_s<__bf16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
@@ -97,6 +99,7 @@ struct InPlaceLaunch {
         break;
       case ST_F32:
       case ST_F32T:
+      case ST_F32S:
         k_canonical<L, uint32_t><<<grid, block, 0, s>>>((const uint32_t*)f, (uint32_t*)out, i0, i1, a);
         break;
       case ST_F16:

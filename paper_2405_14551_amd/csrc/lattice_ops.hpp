@@ -48,6 +48,7 @@ struct Launch {
       case ST_F32: return phase_t<float>(fin, phi, a, s);
       case ST_F16: return phase_t<_Float16>(fin, phi, a, s);
       case ST_BF16: return phase_t<__bf16>(fin, phi, a, s);
+      case ST_F32S: return phase_t<F32S>(fin, phi, a, s);
       case ST_F32T: return phase_total_t<float>(fin, scin, phi, a, s);
       case ST_F16T: return phase_total_t<_Float16>(fin, scin, phi, a, s);
       case ST_BF16T: return phase_total_t<__bf16>(fin, scin, phi, a, s);
@@ -89,6 +90,7 @@ struct Launch {
       case ST_F32: return collide_s<float, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
       case ST_F16: return collide_s<_Float16, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
       case ST_BF16: return collide_s<__bf16, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_F32S: return collide_s<F32S, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
       case ST_F32T: return collide_s<float, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
       case ST_F16T: return collide_s<_Float16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
       case ST_BF16T: return collide_s<__bf16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
@@ -162,6 +164,7 @@ struct Launch {
       case ST_F32: return init_t<float>(f, phi, fo, drops, a, s);
       case ST_F16: return init_t<_Float16>(f, phi, fo, drops, a, s);
       case ST_BF16: return init_t<__bf16>(f, phi, fo, drops, a, s);
+      case ST_F32S: return init_t<F32S>(f, phi, fo, drops, a, s);
       case ST_F32T: return init_total_t<float>(f, sc, phi, fo, drops, a, s);
       case ST_F16T: return init_total_t<_Float16>(f, sc, phi, fo, drops, a, s);
       case ST_BF16T: return init_total_t<__bf16>(f, sc, phi, fo, drops, a, s);

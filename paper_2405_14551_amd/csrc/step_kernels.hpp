@@ -140,6 +140,32 @@ struct Storage<__bf16> {
   __device__ static __forceinline__ void store(__bf16* p, float d, float) { *p = (__bf16)d; }
 };
 
+// FP32 storage of the shifted population d^k_i = f^k_i - w_i rho0 / 2 itself
+// (Eq. shift_f per colour), as the 16-bit modes store it: the stored number
+// carries no rest-equilibrium offset, so its rounding is relative to the
+// deviation, not to f.
+struct F32S {
+  float v;
+};
+
+template <>
+struct Storage<F32S> {
+  using real = float;
+  static constexpr uint32_t ES = 4;
+  template <int I, class L>
+  __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, 0));
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, d), r, vo, so, CPOL_NT);
+  }
+  template <int I, class L>
+  __device__ static __forceinline__ float load(const F32S* p, float) { return p->v; }
+  template <int I, class L>
+  __device__ static __forceinline__ void store(F32S* p, float d, float) { __builtin_nontemporal_store(d, &p->v); }
+};
+
 // FP16C: 16 bits with 1 sign, 4 exponent (bias 15) and 11 significand bits,
 // one significand bit more than IEEE binary16 and half its rounding error, the
 // custom format the paper's mixed-precision section cites for shifted

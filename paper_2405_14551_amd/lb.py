@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "liblbmi.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENUMERIC, LB_ENODEV, LB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 LATTICE = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
-STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32t": 4, "f16t": 5, "bf16t": 6, "f16ct": 7}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32t": 4, "f16t": 5, "bf16t": 6, "f16ct": 7, "f32s": 8}
 TOTAL_LAYOUTS = ("f32t", "f16t", "bf16t", "f16ct")
 NC_MODE = {"off": 0, "explicit": 1, "mlp": 2}
 STREAMING = {"two_copies": 0, "in_place": 1}
@@ -195,7 +195,7 @@ class Simulation:
         self.real = torch.float64 if storage == "f64" else torch.float32
         self.state_dtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
                             "bf16": torch.bfloat16, "f32t": torch.float32, "f16t": torch.float16,
-                            "bf16t": torch.bfloat16, "f16ct": torch.int16}[storage]
+                            "bf16t": torch.bfloat16, "f16ct": torch.int16, "f32s": torch.float32}[storage]
         self.total = storage in TOTAL_LAYOUTS
 
     # -------------------------------------------------------------- lifetime

@@ -51,7 +51,7 @@ CASES = [
     ("D3Q27", (64, 8, 24), (1, 0, 0), "off"),
     ("D3Q27", (33, 17, 9), (1, 1, 1), "explicit"),
 ]
-STORAGES = ["f64", "f32", "f16", "bf16", "f32t", "f16t", "bf16t", "f16ct"]
+STORAGES = ["f64", "f32", "f32s", "f16", "bf16", "f32t", "f16t", "bf16t", "f16ct"]
 
 
 @pytest.mark.parametrize("lat,shape,walls,nc", CASES)

@@ -222,13 +222,14 @@ def test_laplace_case_fp64_1000_steps():
 
 
 # ----------------------------------------------------------------- FP32 parity
-@pytest.mark.parametrize("tau_b", [0.0, 0.65])
-def test_fp32_parity_100_steps(tau_b):
+@pytest.mark.parametrize("storage,tau_b", [("f32", 0.0), ("f32", 0.65), ("f32s", 0.0)])
+def test_fp32_parity_100_steps(storage, tau_b):
     """Periodic D3Q27 box, two droplets, uniform u0 = 0.02, body force, near
     contact on: densities and velocity within 1e-5 relative after 100 steps
-    (with tau_b = 0.65, droplets about 3x as viscous as the continuous phase)."""
+    (with tau_b = 0.65, droplets about 3x as viscous as the continuous phase;
+    f32s stores the shifted populations in FP32)."""
     shape = (40, 32, 32)
-    kw = dict(lattice="D3Q27", storage="f32", nc="explicit", shape=shape, walls=(0, 0, 0),
+    kw = dict(lattice="D3Q27", storage=storage, nc="explicit", shape=shape, walls=(0, 0, 0),
               u0=(0.02, 0.0, 0.0), body_force=(1e-6, 0.0, 0.0), tau_b=tau_b)
     cen = np.array([[11.13, 15.77, 16.21], [29.61, 16.19, 15.83]])
     sim, orc = run_pair(kw, cen, [7.5, 7.5], 100, decision=np.float32)

@@ -46,7 +46,7 @@ def test_storage_precision_vs_fp64_oracle():
     umax = np.sqrt((of["u"] ** 2).sum(0)).max()
     report = {"steps": STEPS, "shape": [nx, ny, nz], "droplets": int(len(rad)),
               "oracle": {"umax": float(umax), "laplace_dp": float(od[7]), "count": int(od[6])}}
-    for st in ("f32", "f16", "bf16", "f32t", "f16t", "bf16t", "f16ct"):
+    for st in ("f32", "f32s", "f16", "bf16", "f32t", "f16t", "bf16t", "f16ct"):
         kw2 = dict(kw, storage=st)
         sim = lb.Simulation(**kw2).init_droplets(cen, rad)
         d0 = sim.diagnostics()
