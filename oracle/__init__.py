@@ -20,6 +20,8 @@ mlp      FP64 reference of the near-contact MLP closure (forward, backward,
          Adam) used to check the GPU training kernels
 fp16c    the FP16C 16-bit storage format (1 sign, 4 exponent, 11 significand
          bits) by its definition: decode, round-to-nearest-even encode
+llb      ``OracleLLB``: the moment-based (regularised) colour-gradient step,
+         whose state is 15 moments per site instead of populations
 
 Parity pins: every function documents which identity, closed form or brute
 force check pins it; the checks live under ``tests/`` (marker ``not gpu``).
