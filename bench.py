@@ -107,14 +107,14 @@ def cpu_baseline(seconds_target=10.0):
                       f"(host nproc {os.cpu_count()})"}
 
 
-def time_storage(kw, cen, rad, storage, steps, warmup, streaming="two_copies"):
+def time_storage(kw, cen, rad, storage, steps, warmup, streaming="two_copies", scheme="populations"):
     """MLUPS and per-launch pass times of the same workload with another
     storage layout or streaming (HIP events on the library's stream), and the
     device memory the population state takes per site (both copies with
     two-copy streaming)."""
     import torch
     from paper_2405_14551_amd import lb
-    sim = lb.Simulation(**dict(kw, storage=storage, streaming=streaming)).init_droplets(cen, rad)
+    sim = lb.Simulation(**dict(kw, storage=storage, streaming=streaming, scheme=scheme)).init_droplets(cen, rad)
     copies = 1 if streaming == "in_place" else 2
     state_per_site = copies * sim.state_bytes() / (kw["shape"][0] * kw["shape"][1] * kw["shape"][2])
     sim.step(warmup)
@@ -380,6 +380,10 @@ def main():
             var[name] = time_storage(kw, cen, rad, st, vs, args.warmup, mode)
             var[name]["vs_plain_f32"] = round(var[name]["MLUPS"] / mlups, 3)
             print(f"# variant {name}: {var[name]}", file=sys.stderr, flush=True)
+        # the moment-based (regularised) scheme: 15 moments per site
+        var["moments_f32"] = time_storage(kw, cen, rad, "f32", vs, args.warmup, scheme="moments")
+        var["moments_f32"]["vs_plain_f32"] = round(var["moments_f32"]["MLUPS"] / mlups, 3)
+        print(f"# variant moments_f32: {var['moments_f32']}", file=sys.stderr, flush=True)
         if kw.get("nc") == "explicit":
             var["closure_f32"] = time_closure(kw, cen, rad, vs, args.warmup, col_ms)
             print(f"# variant closure: {var['closure_f32']}", file=sys.stderr, flush=True)

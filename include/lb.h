@@ -104,6 +104,25 @@ typedef enum lb_nc_mode { LB_NC_OFF = 0, LB_NC_EXPLICIT = 1, LB_NC_MLP = 2 } lb_
  *                        same results bit for bit.  Single lattices only. */
 typedef enum lb_streaming { LB_STREAM_TWO_COPIES = 0, LB_STREAM_IN_PLACE = 1 } lb_streaming;
 
+/* What the state holds between steps (paper Sec. IV.A, third group of
+ * memory strategies).
+ *  LB_SCHEME_POPULATIONS  the post-collision populations (storage above).
+ *  LB_SCHEME_MOMENTS      15 moments per site, from which the post-collision
+ *      colours are rebuilt exactly; the step is the regularised one: the
+ *      pulled total population enters BGK only through its projection on the
+ *      second-order Hermite subspace (rho, j - rho u and
+ *      Pi^neq = Pi - rho c_s^2 I - rho u u; Eqs. distnoneq, LBpostmom,
+ *      llb-pull), then Guo source, perturbation and recolouring as usual.
+ *      Moments, channel-major [15][N] in the storage type (LB_F64 or LB_F32):
+ *        0 rho - rho0, 1-3 J = rho u + (1 - omega)(j - rho u) + (1 - omega/2) F,
+ *        4-9 S (xx yy zz xy xz yz)
+ *            = rho u u + (1 - omega) Pi^neq + (1 - omega/2)(u F + F u) + (2A/9) g g/|g|,
+ *        10 s = A |g|, 11 a = rho_A / rho, 12-14 b = beta (rho_A rho_B / rho) g/|g|;
+ *      P_i = w_i [rho + 3 c_i.J + 4.5 (c_i c_i - I/3) : S] + (2/3)(delta_i0 - w_i) s,
+ *      P^A_i = a P_i + (w_i/|c_i|) c_i.b.  2D keeps the z channels at zero.
+ *      Single lattices, two-copy streaming, nc_mode off or explicit. */
+typedef enum lb_scheme { LB_SCHEME_POPULATIONS = 0, LB_SCHEME_MOMENTS = 1 } lb_scheme;
+
 /* field selection bits for lb_fields; dst[k] belongs to bit k */
 enum {
   LB_FIELD_RHO_A = 1u << 0,   /* real[N]                                   */
@@ -140,6 +159,7 @@ typedef struct lb_params {
                              rule stated with the surface tension, Eq. sigmaA):
                              1/nu = (rho_A/rho)/nu_A + (rho_B/rho)/nu_B, and BGK and the
                              forcing use tau = 3 nu + 1/2                                */
+  int scheme;             /* lb_scheme                                                   */
 } lb_params;
 
 typedef struct lb_handle lb_handle;

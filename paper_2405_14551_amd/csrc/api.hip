@@ -14,6 +14,7 @@
 #include "../../include/lb.h"
 #include "diag_kernels.hpp"
 #include "engine.hpp"
+#include "llb_kernels.hpp"
 #include "mlp_kernels.hpp"
 
 using namespace lbm;
@@ -44,6 +45,15 @@ const LatticeOps* ops_for(int lattice) {
     case LB_D2Q9: return ops_d2q9();
     case LB_D3Q19: return ops_d3q19();
     case LB_D3Q27: return ops_d3q27();
+  }
+  return nullptr;
+}
+
+const LlbOps* llb_for(int lattice) {
+  switch (lattice) {
+    case LB_D2Q9: return llb_d2q9();
+    case LB_D3Q19: return llb_d3q19();
+    case LB_D3Q27: return llb_d3q27();
   }
   return nullptr;
 }
@@ -96,6 +106,11 @@ struct lb_handle {
   const InPlaceOps* ip = nullptr;
   int ip_odd = 0;
   bool in_place() const { return ip != nullptr; }
+  // moment-based scheme: f[0] / f[1] hold the 15 moments per site, W the 11
+  // pre-collision moments between the two passes
+  const LlbOps* llb = nullptr;
+  void* W = nullptr;
+  bool moments() const { return llb != nullptr; }
   void* phi = nullptr;
   void* rho_a = nullptr;
   void* rho_b = nullptr;
@@ -262,6 +277,14 @@ static int validate(const lb_params* p) {
   if (p->diag_every < 0) return fail(LB_EINVAL, "diag_every must be >= 0");
   if (p->streaming != LB_STREAM_TWO_COPIES && p->streaming != LB_STREAM_IN_PLACE)
     return fail(LB_EINVAL, "unknown streaming %d", p->streaming);
+  if (p->scheme != LB_SCHEME_POPULATIONS && p->scheme != LB_SCHEME_MOMENTS)
+    return fail(LB_EINVAL, "unknown scheme %d", p->scheme);
+  if (p->scheme == LB_SCHEME_MOMENTS) {
+    if (p->storage != LB_F64 && p->storage != LB_F32)
+      return fail(LB_EINVAL, "the moment-based scheme stores its moments in LB_F64 or LB_F32");
+    if (p->nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "the moment-based scheme takes nc_mode off or explicit");
+    if (p->streaming != LB_STREAM_TWO_COPIES) return fail(LB_EINVAL, "the moment-based scheme streams with two copies");
+  }
   return LB_OK;
 }
 
@@ -278,7 +301,7 @@ int lb_destroy(lb_handle* h) {
   for (void* b : {(void*)h->d_chans, (void*)h->d_items_ph, (void*)h->d_items_co})
     if (b) (void)hipFree(b);
   for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
-  void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
+  void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->W, h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
                   h->diag_partial, h->diag_out, h->ccl_count, h->drops, h->mlp_theta, h->mlp_m1, h->mlp_m2,
                   h->mlp_grad, h->mlp_part, h->mlp_part_l, h->mlp_lo, h->mlp_bad, h->mlp_net};
   for (void* b : bufs)
@@ -315,9 +338,12 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
       return fail(LB_EINVAL, "channel %d: lattice, storage and nc_mode must agree across channels", c);
   }
   if (n_channels == 1) return create_single(p, hip_stream, out);
-  for (int c = 0; c < n_channels; ++c)
+  for (int c = 0; c < n_channels; ++c) {
     if (p[c].streaming != LB_STREAM_TWO_COPIES)
       return fail(LB_EINVAL, "channel %d: ensembles stream with two copies (LB_STREAM_TWO_COPIES)", c);
+    if (p[c].scheme != LB_SCHEME_POPULATIONS)
+      return fail(LB_EINVAL, "channel %d: ensembles use the population scheme", c);
+  }
   if (p[0].nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "ensembles take nc_mode LB_NC_OFF or LB_NC_EXPLICIT");
   if (!ensemble_storage(p[0].storage))
     return fail(LB_EINVAL, "ensembles take storage LB_F64, LB_F32 or a total layout (got %d)", p[0].storage);
@@ -370,6 +396,7 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
   h->total = total_layout(p->storage);
   h->stream = (hipStream_t)hip_stream;
   if (p->streaming == LB_STREAM_IN_PLACE) h->ip = inplace_for(p->lattice);
+  if (p->scheme == LB_SCHEME_MOMENTS) h->llb = llb_for(p->lattice);
   (void)hipGetDevice(&h->device);
   // pass-2 blocks march through z; aim for about 2048 blocks in flight
   {
@@ -385,7 +412,7 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
     h->z_per_block = (int)zb;
   }
   const size_t N = h->N;
-  const size_t pop = (h->total ? 1ull : 2ull) * h->q * N * h->esize;
+  const size_t pop = h->moments() ? (size_t)LLB_NM * N * h->esize : (h->total ? 1ull : 2ull) * h->q * N * h->esize;
 #define ALLOC(ptr, bytes)                                              \
   do {                                                                 \
     int r_ = dev_alloc((void**)&(ptr), (bytes), #ptr);                 \
@@ -396,6 +423,7 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
   // afterwards; no pass does both)
   ALLOC(h->f[0], pop);
   if (!h->in_place()) ALLOC(h->f[1], pop);
+  if (h->moments()) ALLOC(h->W, (size_t)LLB_NW * N * h->esize);
   if (h->total) {
     ALLOC(h->sc[0], sizeof(float) * NSC * N);
     if (!h->in_place()) ALLOC(h->sc[1], sizeof(float) * NSC * N);
@@ -460,7 +488,10 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
   a.half_rho0 = 0.5 * h->p.rho0;
   a.phi_I = h->p.phi_interface;
   // the state goes into the current copy, so an ensemble keeps one parity
-  HIP_TRY(h->ops->init(h->p.storage, h->f[h->cur], h->sc[h->cur], h->phi, h->field_ptrs(), h->drops, a, h->stream));
+  if (h->moments())
+    HIP_TRY(h->llb->init(h->p.storage, h->f[h->cur], h->phi, h->field_ptrs(), h->drops, a, h->stream));
+  else
+    HIP_TRY(h->ops->init(h->p.storage, h->f[h->cur], h->sc[h->cur], h->phi, h->field_ptrs(), h->drops, a, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));  // the host droplet list goes out of scope
   h->t = 0;
   h->ip_odd = 0;
@@ -692,7 +723,16 @@ int lb_step(lb_handle* h, int nsteps) {
     const bool fields = (s == nsteps - 1) || diag_now;
     int r = prof_mark(h, 0, true);
     if (r) return r;
-    if (h->in_place()) {
+    if (h->moments()) {
+      // pass 1 rebuilds the pulled populations from the upstream moments,
+      // pass 2 writes the new moments into the other copy
+      HIP_TRY(h->llb->pull(st, h->f[h->cur], h->W, h->phi, a, h->stream));
+      if ((r = prof_mark(h, 0, false))) return r;
+      if ((r = prof_mark(h, 1, true))) return r;
+      HIP_TRY(h->llb->collide(st, nc, fields, h->W, h->f[1 - h->cur], h->phi, fo, a, h->stream));
+      if ((r = prof_mark(h, 1, false))) return r;
+      h->cur = 1 - h->cur;
+    } else if (h->in_place()) {
       // one copy: even steps pull and push, odd steps work on the site's own slots
       void* f = h->f[0];
       float* sc = h->sc[0];
@@ -850,7 +890,8 @@ static size_t state_size(const lb_handle* h, size_t* pop_bytes) {
     if (pop_bytes) *pop_bytes = 0;
     return tot;
   }
-  const size_t pop = (h->total ? 1ull : 2ull) * h->q * h->N * h->esize;
+  const size_t pop = h->moments() ? (size_t)LLB_NM * h->N * h->esize
+                                   : (h->total ? 1ull : 2ull) * h->q * h->N * h->esize;
   if (pop_bytes) *pop_bytes = pop;
   return pop + (h->total ? sizeof(float) * NSC * h->N : 0);
 }

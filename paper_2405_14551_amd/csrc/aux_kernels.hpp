@@ -30,6 +30,20 @@ __device__ __forceinline__ double min_image(double d, int n, int wall) {
   return d - (double)n * rint(d / (double)n);
 }
 
+// phase field of the droplet list at site (x, y, z)
+__device__ __forceinline__ double droplet_phi(int x, int y, int z, const double* __restrict__ drops,
+                                              const InitArgs& a) {
+  double best = -1.0e300;
+  for (int d = 0; d < a.ndrop; ++d) {
+    const double dx = min_image((double)x - drops[4 * d + 0], a.nx, a.wall_x);
+    const double dy = min_image((double)y - drops[4 * d + 1], a.ny, a.wall_y);
+    const double dz = a.dims == 3 ? min_image((double)z - drops[4 * d + 2], a.nz, a.wall_z) : 0.0;
+    const double v = drops[4 * d + 3] - sqrt(dx * dx + dy * dy + dz * dz);
+    best = v > best ? v : best;
+  }
+  return a.phi_in * tanh(2.0 * best / a.width);
+}
+
 template <class L, class S>
 __global__ void __launch_bounds__(256) k_init(S* __restrict__ f, typename Storage<S>::real* __restrict__ phi_out,
                                               FieldPtrs fo, const double* __restrict__ drops,
@@ -40,15 +54,7 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ f, typename Storag
   const int x = s % a.nx;
   const int y = (s / a.nx) % a.ny;
   const int z = s / ((uint32_t)a.nx * a.ny);
-  double best = -1.0e300;
-  for (int d = 0; d < a.ndrop; ++d) {
-    const double dx = min_image((double)x - drops[4 * d + 0], a.nx, a.wall_x);
-    const double dy = min_image((double)y - drops[4 * d + 1], a.ny, a.wall_y);
-    const double dz = a.dims == 3 ? min_image((double)z - drops[4 * d + 2], a.nz, a.wall_z) : 0.0;
-    const double v = drops[4 * d + 3] - sqrt(dx * dx + dy * dy + dz * dz);
-    best = v > best ? v : best;
-  }
-  const double phi = a.phi_in * tanh(2.0 * best / a.width);
+  const double phi = droplet_phi(x, y, z, drops, a);
   const double rho_k[2] = {a.rho0 * (1.0 + phi) * 0.5, a.rho0 * (1.0 - phi) * 0.5};
   const double uu = a.u0x * a.u0x + a.u0y * a.u0y + a.u0z * a.u0z;
   const R hs = (R)a.half_rho0;
@@ -84,15 +90,7 @@ __global__ void __launch_bounds__(256) k_init_total(S* __restrict__ f, float* __
   const int x = s % a.nx;
   const int y = (s / a.nx) % a.ny;
   const int z = s / ((uint32_t)a.nx * a.ny);
-  double best = -1.0e300;
-  for (int d = 0; d < a.ndrop; ++d) {
-    const double dx = min_image((double)x - drops[4 * d + 0], a.nx, a.wall_x);
-    const double dy = min_image((double)y - drops[4 * d + 1], a.ny, a.wall_y);
-    const double dz = a.dims == 3 ? min_image((double)z - drops[4 * d + 2], a.nz, a.wall_z) : 0.0;
-    const double v = drops[4 * d + 3] - sqrt(dx * dx + dy * dy + dz * dz);
-    best = v > best ? v : best;
-  }
-  const double phi = a.phi_in * tanh(2.0 * best / a.width);
+  const double phi = droplet_phi(x, y, z, drops, a);
   const double ra = a.rho0 * (1.0 + phi) * 0.5, rb = a.rho0 * (1.0 - phi) * 0.5, rho = ra + rb;
   const double uu = a.u0x * a.u0x + a.u0y * a.u0y + a.u0z * a.u0z;
   static_for<0, L::Q>([&](auto ic) {

@@ -64,6 +64,17 @@ struct InPlaceOps {
   hipError_t (*canonical)(int storage, const void* f, void* out, int i0, int i1, const StepArgs& a, hipStream_t s);
 };
 
+// Moment-based (regularised) step: the state is 15 moments per site
+// (llb_kernels.hpp); storages ST_F64 and ST_F32.  W holds the 11 pre-collision
+// moments pass 1 writes and pass 2 reads.
+struct LlbOps {
+  hipError_t (*init)(int storage, void* M, void* phi, const FieldPtrs& fo, const double* drops, const InitArgs& a,
+                     hipStream_t s);
+  hipError_t (*pull)(int storage, const void* M, void* W, void* phi, const StepArgs& a, hipStream_t s);
+  hipError_t (*collide)(int storage, bool nc, bool fields, const void* W, void* M, const void* phi,
+                        const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
+};
+
 // storages the learned closure is built for
 inline bool mlp_storage(int st) { return st == ST_F64 || st == ST_F32 || is_total(st); }
 
@@ -76,5 +87,8 @@ const LatticeOps* ops_d3q27();
 const InPlaceOps* inplace_d2q9();
 const InPlaceOps* inplace_d3q19();
 const InPlaceOps* inplace_d3q27();
+const LlbOps* llb_d2q9();
+const LlbOps* llb_d3q19();
+const LlbOps* llb_d3q27();
 
 }  // namespace lbm

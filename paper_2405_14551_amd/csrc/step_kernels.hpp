@@ -517,6 +517,45 @@ __device__ __forceinline__ void ring_gradient(const R* __restrict__ ring, int c0
   });
 }
 
+// the explicit near-contact scan (Eq. near_cont_force) on a radius-4 ring: the
+// distance h of the first interface site along -g/|g|, within floor(h_max)
+// sites, whose gradient opposes g; 0 if none (a wall ends the scan)
+template <class L, class T, class R>
+__device__ __forceinline__ int nc_scan_ring(const R* __restrict__ ring, int c0, int zc, int x, int y, int z, R gx,
+                                            R gy, R gz, R gg, R phiI, const StepArgs& a) {
+  const R inv = R(1) / sqrt(gg);
+  const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
+  for (int s = 1; s <= a.nc_steps; ++s) {
+    // |s m| <= 3; the clamp only guards the LDS index against non-finite m
+    const int ox = max(-3, min(3, (int)round_half_away((R)s * mx)));
+    const int oy = max(-3, min(3, (int)round_half_away((R)s * my)));
+    const int oz = max(-3, min(3, (int)round_half_away((R)s * mz)));
+    if (a.wall_x && (x + ox < 0 || x + ox >= a.nx)) return 0;
+    if (a.wall_y && (y + oy < 0 || y + oy >= a.ny)) return 0;
+    if (a.wall_z && (z + oz < 0 || z + oz >= a.nz)) return 0;
+    const int cy0 = c0 + oy * T::TXH + ox;
+    const int py0 = ring_slot(zc, oz, T::NPL) * T::PL;
+    const R phy = ring[py0 + cy0];
+    if (fabs(phy) < phiI) {
+      const int pym = T::RZ ? ring_slot(zc, oz - 1, T::NPL) * T::PL : py0;
+      const int pyp = T::RZ ? ring_slot(zc, oz + 1, T::NPL) * T::PL : py0;
+      R hx, hy, hz;
+      ring_gradient<L, T, R>(ring, cy0, pym, py0, pyp, hx, hy, hz);
+      if (hx * gx + hy * gy + hz * gz < R(0)) return s;
+    }
+  }
+  return 0;
+}
+
+// A_h(h): the plateau strength up to h_min, decaying as (h_min / h)^3 beyond
+template <class R>
+__device__ __forceinline__ R nc_strength(int hit, const StepArgs& a) {
+  const R h = (R)hit, hmin = (R)a.nc_hmin;
+  R Ah = (R)a.nc_A;
+  if (h > hmin) { const R r = hmin / h; Ah = Ah * r * r * r; }
+  return Ah;
+}
+
 // phase field at a site within one layer beyond the lattice, read from memory
 // with the ring's halo rule (periodic wrap, mirrored wall ghosts)
 template <class R>
@@ -908,27 +947,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         if (flag && has_g && (!MLP || (valid_xy && !use_net))) {
           int hit = 0;
           if constexpr (T::RAD >= 4) {
-            const R inv = R(1) / sqrt(gg);
-            const R mx = -gx * inv, my = -gy * inv, mz = -gz * inv;
-            for (int s = 1; s <= a.nc_steps; ++s) {
-              // |s m| <= 3; the clamp only guards the LDS index against non-finite m
-              const int ox = max(-3, min(3, (int)round_half_away((R)s * mx)));
-              const int oy = max(-3, min(3, (int)round_half_away((R)s * my)));
-              const int oz = max(-3, min(3, (int)round_half_away((R)s * mz)));
-              if (a.wall_x && (x + ox < 0 || x + ox >= a.nx)) break;
-              if (a.wall_y && (y + oy < 0 || y + oy >= a.ny)) break;
-              if (a.wall_z && (z + oz < 0 || z + oz >= a.nz)) break;
-              const int cy0 = c0 + oy * T::TXH + ox;
-              const int py0 = ring_slot(zc, oz, T::NPL) * T::PL;
-              const R phy = ring[py0 + cy0];
-              if (fabs(phy) < phiI) {
-                const int pym = T::RZ ? ring_slot(zc, oz - 1, T::NPL) * T::PL : py0;
-                const int pyp = T::RZ ? ring_slot(zc, oz + 1, T::NPL) * T::PL : py0;
-                R hx, hy, hz;
-                ring_gradient<L, T, R>(ring, cy0, pym, py0, pyp, hx, hy, hz);
-                if (hx * gx + hy * gy + hz * gz < R(0)) { hit = s; break; }
-              }
-            }
+            hit = nc_scan_ring<L, T, R>(ring, c0, zc, x, y, z, gx, gy, gz, gg, phiI, a);
           } else {
             // a radius-1 ring (the learned closure's tile): the scan reads
             // the phase field from memory; it serves only sites outside the
@@ -936,9 +955,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
             hit = nc_scan_global<L, R>(phi, x, y, z, gx, gy, gz, gg, phiI, a);
           }
           if (hit) {
-            const R h = (R)hit, hmin = (R)a.nc_hmin;
-            R Ah = (R)a.nc_A;
-            if (h > hmin) { const R r = hmin / h; Ah = Ah * r * r * r; }
+            const R Ah = nc_strength<R>(hit, a);
             fnx = R(0.5) * Ah * gx; fny = R(0.5) * Ah * gy; fnz = R(0.5) * Ah * gz;
           }
         }

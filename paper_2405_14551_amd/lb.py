@@ -21,6 +21,8 @@ STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32t": 4, "f16t": 5, "bf16t
 TOTAL_LAYOUTS = ("f32t", "f16t", "bf16t", "f16ct")
 NC_MODE = {"off": 0, "explicit": 1, "mlp": 2}
 STREAMING = {"two_copies": 0, "in_place": 1}
+SCHEME = {"populations": 0, "moments": 1}
+N_MOMENTS = 15
 MLP_PARAMS = 6339
 MLP_ROW = 32
 FIELD_BITS = {"rho_a": 0, "rho_b": 1, "phi": 2, "u": 3, "f_nc": 4, "flags": 5, "labels": 6}
@@ -56,6 +58,7 @@ class LbParams(ctypes.Structure):
         ("diag_every", ctypes.c_int),
         ("streaming", ctypes.c_int),
         ("tau_b", ctypes.c_double),
+        ("scheme", ctypes.c_int),
     ]
 
 
@@ -151,7 +154,7 @@ def lattice_table(name):
 def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), walls=(0, 0, 0),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
                 nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0,
-                streaming="two_copies", tau_b=0.0):
+                streaming="two_copies", tau_b=0.0, scheme="populations"):
     p = LbParams()
     lib().lb_params_default(ctypes.byref(p))
     p.lattice = LATTICE[lattice]
@@ -168,6 +171,7 @@ def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), wa
     p.diag_every = int(diag_every)
     p.streaming = STREAMING[streaming]
     p.tau_b = float(tau_b)
+    p.scheme = SCHEME[scheme]
     return p
 
 
@@ -197,6 +201,7 @@ class Simulation:
                             "bf16": torch.bfloat16, "f32t": torch.float32, "f16t": torch.float16,
                             "bf16t": torch.bfloat16, "f16ct": torch.int16, "f32s": torch.float32}[storage]
         self.total = storage in TOTAL_LAYOUTS
+        self.moments = kw.get("scheme", "populations") == "moments"
 
     # -------------------------------------------------------------- lifetime
     def close(self):
@@ -287,7 +292,8 @@ class Simulation:
     def get_state(self, host=False):
         """Post-collision state on the device.  Per-colour layouts: a tensor
         (2, q, nz, ny, nx) of the storage type.  Total layouts: a uint8 tensor
-        of the raw bytes (use ``split_total_state``).  host=True: the raw bytes
+        of the raw bytes (use ``split_total_state``).  Moment scheme: a tensor
+        (15, nz, ny, nx) of the moments (channel 0 holds rho - rho0).  host=True: the raw bytes
         as a numpy uint8 array, copied by the library to host memory."""
         nx, ny, nz = self.shape
         if host:
@@ -296,6 +302,8 @@ class Simulation:
             return a
         if self.total:
             t = self.torch.empty((self.state_bytes(),), dtype=self.torch.uint8, device=self.device)
+        elif self.moments:
+            t = self.torch.empty((N_MOMENTS, nz, ny, nx), dtype=self.state_dtype, device=self.device)
         else:
             t = self.torch.empty((2, self.q, nz, ny, nx), dtype=self.state_dtype, device=self.device)
         check(lib().lb_get_state(self.h, ctypes.c_void_p(t.data_ptr()), self.state_bytes(), 1))

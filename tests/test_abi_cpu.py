@@ -59,6 +59,10 @@ def _create(**kw):
     dict(tau=0.5),
     dict(tau=0.3),
     dict(tau_b=0.5),
+    dict(scheme="moments", storage="f16"),                  # moments in FP64 / FP32 only
+    dict(scheme="moments", storage="f32t"),
+    dict(scheme="moments", nc="mlp"),
+    dict(scheme="moments", streaming="in_place"),
     dict(tau_b=-1.0),
     dict(tau_b=float("nan")),
     dict(shape=(0, 4, 4)),
@@ -90,6 +94,9 @@ def test_bad_enum_and_null():
     assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
     p = lb.make_params()
     p.wall[0] = 2
+    assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
+    p = lb.make_params()
+    p.scheme = 2
     assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
     p = lb.make_params()
     p.streaming = 2
@@ -127,6 +134,8 @@ def test_ensemble_argument_checks():
     arr[0] = lb.make_params(lattice="D3Q19", storage="f32", shape=(16, 8, 8))
     arr[1] = lb.make_params(lattice="D3Q19", storage="f32", shape=(16, 8, 8), streaming="in_place")
     assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # ensembles use two copies
+    arr[1] = lb.make_params(lattice="D3Q19", storage="f32", shape=(16, 8, 8), scheme="moments")
+    assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # and the population scheme
 
 
 def test_closure_calls_reject_null_arguments():
