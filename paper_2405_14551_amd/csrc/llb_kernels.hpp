@@ -44,8 +44,69 @@ constexpr double llb_v(int i) {
   return (2.0 / 3.0) * ((i == 0 ? 1.0 : 0.0) - L::w[i]);
 }
 
+// running sums of pass 1 (shifted densities, momentum, momentum flux)
+template <class R>
+struct LlbPullSums {
+  R dA = 0, dB = 0, jx = 0, jy = 0, jz = 0;
+  R p[6] = {0, 0, 0, 0, 0, 0};  // sum (P_i - w_i rho0) c c: xx yy zz xy xz yz
+};
+
+// add the population pulled along c_I, rebuilt from the moments at m (channel k
+// at m[k * stride]); sg = -1 for a population bounced back at a wall (it left
+// the site along -c_I, so the odd terms change sign).  FOLD: channel 0 holds
+// rho - rho0 - 1.5 tr S - (2/3) s instead, which turns the rebuild into
+// P_i - w_i rho0 = w_i [chan0 + 3 c.J + 4.5 (c c) : S] + (2/3) delta_i0 s
+// (the trace and the rest vector folded once per site, not per direction).
+template <class L, int I, bool FOLD = false, class R, class P>
+__device__ __forceinline__ void llb_pull_dir(const P* m, size_t stride, R sg, R rho0, LlbPullSums<R>& acc) {
+  constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+  R ccs = 0, cj = 0, cb = 0;
+  if constexpr (cx != 0) { ccs += m[4 * stride]; cj += R(cx) * m[1 * stride]; cb += R(cx) * m[12 * stride]; }
+  if constexpr (cy != 0) { ccs += m[5 * stride]; cj += R(cy) * m[2 * stride]; cb += R(cy) * m[13 * stride]; }
+  if constexpr (cz != 0) { ccs += m[6 * stride]; cj += R(cz) * m[3 * stride]; cb += R(cz) * m[14 * stride]; }
+  if constexpr (cx != 0 && cy != 0) ccs += R(2 * cx * cy) * m[7 * stride];
+  if constexpr (cx != 0 && cz != 0) ccs += R(2 * cx * cz) * m[8 * stride];
+  if constexpr (cy != 0 && cz != 0) ccs += R(2 * cy * cz) * m[9 * stride];
+  const R w = (R)L::w[I];
+  // P_i - w_i rho0 and P^A_i - w_i rho0 / 2
+  R dP;
+  if constexpr (FOLD) {
+    dP = w * (m[0] + R(3) * sg * cj + R(4.5) * ccs);
+    if constexpr (I == 0) dP += R(2.0 / 3.0) * m[10 * stride];
+  } else {
+    const R tr = m[4 * stride] + m[5 * stride] + (L::D == 3 ? (R)m[6 * stride] : R(0));
+    dP = w * (m[0] + R(3) * sg * cj + R(4.5) * (ccs - tr * R(1.0 / 3.0))) + (R)llb_v<L>(I) * m[10 * stride];
+  }
+  const R av = m[11 * stride];
+  R dPA = av * dP + w * rho0 * (av - R(0.5));
+  if constexpr (I != 0) dPA += sg * (R)(L::w[I] * inv_norm<L>(I)) * cb;
+  acc.dA += dPA;
+  acc.dB += dP - dPA;
+  if constexpr (cx != 0) { acc.jx += R(cx) * dP; acc.p[0] += dP; }
+  if constexpr (cy != 0) { acc.jy += R(cy) * dP; acc.p[1] += dP; }
+  if constexpr (cz != 0) { acc.jz += R(cz) * dP; acc.p[2] += dP; }
+  if constexpr (cx != 0 && cy != 0) acc.p[3] += R(cx * cy) * dP;
+  if constexpr (cx != 0 && cz != 0) acc.p[4] += R(cx * cz) * dP;
+  if constexpr (cy != 0 && cz != 0) acc.p[5] += R(cy * cz) * dP;
+}
+
+// phi and the pre-collision moments of site s
+template <class R, class S>
+__device__ __forceinline__ void llb_pull_store(const LlbPullSums<R>& acc, R rho0, uint32_t s, size_t N,
+                                               S* __restrict__ W, S* __restrict__ phi) {
+  phi[s] = (acc.dA - acc.dB) / (rho0 + (acc.dA + acc.dB));
+  W[s] = acc.dA;
+  W[N + s] = acc.dB;
+  W[2 * N + s] = acc.jx;
+  W[3 * N + s] = acc.jy;
+  W[4 * N + s] = acc.jz;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) W[(5 + k) * N + s] = acc.p[k];
+}
+
 // ----------------------------------------------------------------------------
-// pass 1: pulled populations rebuilt from upstream moments
+// pass 1: pulled populations rebuilt from upstream moments (read from memory;
+// the FP64 path)
 template <class L, class S>
 __global__ void __launch_bounds__(256) k_llb_pull(const S* __restrict__ M, S* __restrict__ W, S* __restrict__ phi,
                                                   StepArgs a) {
@@ -61,49 +122,111 @@ __global__ void __launch_bounds__(256) k_llb_pull(const S* __restrict__ M, S* __
   const Nbr n = make_nbr(x, y, z, a);
   const size_t N = a.N;
   const R rho0 = R(2) * (R)a.half_rho0;
-  R dA = 0, dB = 0, jx = 0, jy = 0, jz = 0;
-  R p[6] = {0, 0, 0, 0, 0, 0};  // sum (P_i - w_i rho0) c c: xx yy zz xy xz yz
+  LlbPullSums<R> acc;
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
-    constexpr int ix = 1 - cx, iy = 1 - cy, iz = 1 - cz;
+    constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
     const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
     const uint32_t src = solid ? n.site : n.xs[ix] + n.ys[iy] + n.zs[iz];
-    // the bounced population left the site along -c_i: odd terms flip sign
-    const R sg = solid ? R(-1) : R(1);
-    const S* m = M + src;
-    R ccs = 0, cj = 0, cb = 0;
-    if constexpr (cx != 0) { ccs += m[4 * N]; cj += R(cx) * m[1 * N]; cb += R(cx) * m[12 * N]; }
-    if constexpr (cy != 0) { ccs += m[5 * N]; cj += R(cy) * m[2 * N]; cb += R(cy) * m[13 * N]; }
-    if constexpr (cz != 0) { ccs += m[6 * N]; cj += R(cz) * m[3 * N]; cb += R(cz) * m[14 * N]; }
-    if constexpr (cx != 0 && cy != 0) ccs += R(2 * cx * cy) * m[7 * N];
-    if constexpr (cx != 0 && cz != 0) ccs += R(2 * cx * cz) * m[8 * N];
-    if constexpr (cy != 0 && cz != 0) ccs += R(2 * cy * cz) * m[9 * N];
-    const R tr = m[4 * N] + m[5 * N] + (L::D == 3 ? m[6 * N] : R(0));
-    const R w = (R)L::w[I];
-    // P_i - w_i rho0 and P^A_i - w_i rho0 / 2
-    const R dP = w * (m[0] + R(3) * sg * cj + R(4.5) * (ccs - tr * R(1.0 / 3.0))) + (R)llb_v<L>(I) * m[10 * N];
-    const R av = m[11 * N];
-    R dPA = av * dP + w * rho0 * (av - R(0.5));
-    if constexpr (I != 0) dPA += sg * (R)(L::w[I] * inv_norm<L>(I)) * cb;
-    dA += dPA;
-    dB += dP - dPA;
-    if constexpr (cx != 0) { jx += R(cx) * dP; p[0] += dP; }
-    if constexpr (cy != 0) { jy += R(cy) * dP; p[1] += dP; }
-    if constexpr (cz != 0) { jz += R(cz) * dP; p[2] += dP; }
-    if constexpr (cx != 0 && cy != 0) p[3] += R(cx * cy) * dP;
-    if constexpr (cx != 0 && cz != 0) p[4] += R(cx * cz) * dP;
-    if constexpr (cy != 0 && cz != 0) p[5] += R(cy * cz) * dP;
+    llb_pull_dir<L, I>(M + src, N, solid ? R(-1) : R(1), rho0, acc);
   });
-  const uint32_t s = n.site;
-  phi[s] = (dA - dB) / (rho0 + (dA + dB));
-  W[s] = dA;
-  W[N + s] = dB;
-  W[2 * N + s] = jx;
-  W[3 * N + s] = jy;
-  W[4 * N + s] = jz;
+  llb_pull_store(acc, rho0, n.site, N, W, phi);
+}
+
+// The same pass with the moments of a TX x TY tile plus a one-site halo staged
+// in an LDS ring, marching along z (the FP32 path): each moment is read from
+// memory once per tile, and the 27 upstream sites of a site come from LDS.
+// The ring is [slot][channel][plane position] with only the 2 RZ + 1 planes in
+// use (about 71 KB for a 3D 64 x 4 tile, so two workgroups fit a CU): the next
+// plane waits in registers and replaces the oldest between two barriers.
+template <class TS>
+constexpr int llb_slots() { return 2 * TS::RZ + 1; }
+template <class TS>
+struct LlbPullSmem {
+  float ring[llb_slots<TS>() * LLB_NM * TS::PL];
+};
+
+template <class TS>
+__device__ __forceinline__ void llb_fetch_plane(float (&v)[LLB_NM * ((TS::PL + TS::NT - 1) / TS::NT)], int zz,
+                                                const float* __restrict__ M, int x0, int y0, const StepArgs& a,
+                                                int tid) {
+  constexpr int NPC = (TS::PL + TS::NT - 1) / TS::NT;
+  const uint32_t gz = halo_coord(zz, a.nz, a.wall_z);
+  const uint32_t zoff = gz * (uint32_t)a.nx * (uint32_t)a.ny;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) W[(5 + k) * N + s] = p[k];
+  for (int k = 0; k < NPC; ++k) {
+    const int rr = min(tid + k * TS::NT, TS::PL - 1);  // surplus lanes reload the last position
+    const int hy = rr / TS::TXH, hx = rr - hy * TS::TXH;
+    const uint32_t gx = halo_coord(x0 - TS::RAD + hx, a.nx, a.wall_x);
+    const uint32_t gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
+    const float* m = M + (zoff + gy * (uint32_t)a.nx + gx);
+#pragma unroll
+    for (int ch = 0; ch < LLB_NM; ++ch) v[ch * NPC + k] = m[(size_t)ch * a.N];
+    // channel 0 as the FOLD form of llb_pull_dir reads it
+    v[k] = v[k] - 1.5f * (v[4 * NPC + k] + v[5 * NPC + k] + v[6 * NPC + k]) - (2.0f / 3.0f) * v[10 * NPC + k];
+  }
+}
+
+template <class TS>
+__device__ __forceinline__ void llb_commit_plane(float* __restrict__ ring, int slot,
+                                                 const float (&v)[LLB_NM * ((TS::PL + TS::NT - 1) / TS::NT)],
+                                                 int tid) {
+  constexpr int NPC = (TS::PL + TS::NT - 1) / TS::NT;
+  float* dst = ring + slot * (LLB_NM * TS::PL);
+#pragma unroll
+  for (int k = 0; k < NPC; ++k) {
+    const int rr = tid + k * TS::NT;
+    if (rr < TS::PL) {
+#pragma unroll
+      for (int ch = 0; ch < LLB_NM; ++ch) dst[ch * TS::PL + rr] = v[ch * NPC + k];
+    }
+  }
+}
+
+template <class L, class TS>
+__global__ void __launch_bounds__(TS::NT) k_llb_pull_ring(const float* __restrict__ M, float* __restrict__ W,
+                                                          float* __restrict__ phi, StepArgs a) {
+  __shared__ LlbPullSmem<TS> sm;
+  constexpr int NPC = (TS::PL + TS::NT - 1) / TS::NT;
+  constexpr int SLOT = LLB_NM * TS::PL;
+  const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, TS::TX, TS::TY);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TS::TX * ty;
+  const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool valid_xy = x < a.nx && y < a.ny;
+  constexpr int NS = llb_slots<TS>();
+  for (int dz = -TS::RZ; dz <= TS::RZ; ++dz) {
+    float v[LLB_NM * NPC];
+    llb_fetch_plane<TS>(v, z0 + dz, M, x0, y0, a, tid);
+    llb_commit_plane<TS>(sm.ring, plane_slot(z0 + dz, NS), v, tid);
+  }
+  __syncthreads();
+  const float rho0 = 2.0f * (float)a.half_rho0;
+  const int sc0 = (ty + 1) * TS::TXH + (tx + 1);
+  for (int z = z0; z < z1; ++z) {
+    const bool more = TS::RZ && z + 1 < z1;
+    float nxt[LLB_NM * NPC];
+    if (more) llb_fetch_plane<TS>(nxt, z + 1 + TS::RZ, M, x0, y0, a, tid);
+    if (valid_xy) {
+      const Nbr n = make_nbr(x, y, z, a);
+      const int zcs = plane_slot(z, NS);
+      LlbPullSums<float> acc;
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+        constexpr int ix = 1 - cx, iy = 1 - cy, iz = 1 - cz;
+        const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
+        const int moving = ring_slot(zcs, -cz, NS) * SLOT + sc0 - cy * TS::TXH - cx;
+        const int bounced = zcs * SLOT + sc0;
+        llb_pull_dir<L, I, true>(sm.ring + (solid ? bounced : moving), (size_t)TS::PL, solid ? -1.0f : 1.0f, rho0,
+                                 acc);
+      });
+      llb_pull_store(acc, rho0, n.site, a.N, W, phi);
+    }
+    __syncthreads();  // the oldest plane is no longer read
+    if (more) llb_commit_plane<TS>(sm.ring, plane_slot(z + 1 + TS::RZ, NS), nxt, tid);
+    __syncthreads();
+  }
 }
 
 // ----------------------------------------------------------------------------
