@@ -158,4 +158,27 @@ class OracleLLB(OracleSim):
                             nc_source=self._nc_source)
 
 
-__all__ = ["OracleLLB", "NM", "PAIRS", "v_vector"]
+def step_window_moments(params, M, site, radius=6):
+    """One moment-scheme step of the site at ``site`` = (x, y, z) from the full
+    moment state M (15, nz, ny, nx), run on the window of half-width
+    ``radius`` around it (the new moments at x depend on the moments within 6
+    sites: pull radius 1 for the phase field the gradient reads at the
+    near-contact scan points, 3 + 1 + 1, as for the population step).  M may be
+    a callable taking the window's index arrays (iz, iy, ix).  Returns (moments
+    at the site (15,), fields dict at the site)."""
+    from .sim import window_geometry
+    (ix, iy, iz), centre, walls = window_geometry(params, site, radius)
+    if callable(M):
+        wM = M(iz, iy, ix)
+    else:
+        wM = np.asarray(M)[np.ix_(np.arange(NM), iz, iy, ix)]
+    wp = params.replace(nx=len(ix), ny=len(iy), nz=len(iz), walls=walls)
+    sim = OracleLLB(wp).set_moments(np.asarray(wM, dtype=np.float64))
+    sim.step()
+    cx, cy, cz = centre
+    fl = sim.fields()
+    out = {k: (v[..., cz, cy, cx] if v.ndim == 3 else v[:, cz, cy, cx]) for k, v in fl.items()}
+    return sim.M[:, cz, cy, cx].copy(), out
+
+
+__all__ = ["OracleLLB", "NM", "PAIRS", "v_vector", "step_window_moments"]

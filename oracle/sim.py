@@ -420,20 +420,11 @@ __all__ = ["OracleParams", "OracleSim", "round_half_away", "flags_from_phi",
            "surface_tension", "viscosity"]
 
 
-def step_window(params: OracleParams, fA, fB, site, radius=6):
-    """One step of the site at ``site`` = (x, y, z) from the full post-collision
-    state (fA, fB) of shape (q, nz, ny, nx), computed by running the oracle on
-    the window of half-width ``radius`` around it.
-
-    The post-collision value at x depends on data within 5 sites only (pull
-    radius 1 for the populations of the sites whose phase field enters the
-    gradient at the near-contact scan points: 3 + 1 + 1), so with radius >= 6
-    the window's own boundary (periodic wrap on periodic axes, a wall on
-    walled axes, which coincides with the true wall where the window reaches
-    it) cannot influence the centre.  fA and fB may also be callables that
-    take the window's index arrays (iz, iy, ix) and return the window
-    (q, len(iz), len(iy), len(ix)), for states too large to hold on the host.
-    Returns (fA_site (q,), fB_site (q,), fields dict at the site)."""
+def window_geometry(params: OracleParams, site, radius):
+    """Index arrays (ix, iy, iz) of the window of half-width ``radius`` around
+    ``site``, the site's position in it and the window's walled axes: walled
+    axes are cut at the true walls, periodic axes wrap (whole when shorter
+    than the window)."""
     p = params
     n = (p.nx, p.ny, p.nz)
     lat = make_lattice(p.lattice)
@@ -460,7 +451,25 @@ def step_window(params: OracleParams, fA, fB, site, radius=6):
             idx.append(np.arange(xa - radius, xa + radius + 1) % na)
             centre.append(radius)
             walls.append(False)
-    ix, iy, iz = idx
+    return tuple(idx), tuple(centre), tuple(walls)
+
+
+def step_window(params: OracleParams, fA, fB, site, radius=6):
+    """One step of the site at ``site`` = (x, y, z) from the full post-collision
+    state (fA, fB) of shape (q, nz, ny, nx), computed by running the oracle on
+    the window of half-width ``radius`` around it.
+
+    The post-collision value at x depends on data within 5 sites only (pull
+    radius 1 for the populations of the sites whose phase field enters the
+    gradient at the near-contact scan points: 3 + 1 + 1), so with radius >= 6
+    the window's own boundary (periodic wrap on periodic axes, a wall on
+    walled axes, which coincides with the true wall where the window reaches
+    it) cannot influence the centre.  fA and fB may also be callables that
+    take the window's index arrays (iz, iy, ix) and return the window
+    (q, len(iz), len(iy), len(ix)), for states too large to hold on the host.
+    Returns (fA_site (q,), fB_site (q,), fields dict at the site)."""
+    p = params
+    (ix, iy, iz), centre, walls = window_geometry(p, site, radius)
     if callable(fA):
         wA, wB = fA(iz, iy, ix), fB(iz, iy, ix)
     else:
