@@ -57,27 +57,28 @@ struct LlbPullSums {
 // rho - rho0 - 1.5 tr S - (2/3) s instead, which turns the rebuild into
 // P_i - w_i rho0 = w_i [chan0 + 3 c.J + 4.5 (c c) : S] + (2/3) delta_i0 s
 // (the trace and the rest vector folded once per site, not per direction).
-template <class L, int I, bool FOLD = false, class R, class P>
-__device__ __forceinline__ void llb_pull_dir(const P* m, size_t stride, R sg, R rho0, LlbPullSums<R>& acc) {
+// moments read through m(k) (k the channel)
+template <class L, int I, bool FOLD, class R, class V>
+__device__ __forceinline__ void llb_pull_dir_v(const V& m, R sg, R rho0, LlbPullSums<R>& acc) {
   constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
   R ccs = 0, cj = 0, cb = 0;
-  if constexpr (cx != 0) { ccs += m[4 * stride]; cj += R(cx) * m[1 * stride]; cb += R(cx) * m[12 * stride]; }
-  if constexpr (cy != 0) { ccs += m[5 * stride]; cj += R(cy) * m[2 * stride]; cb += R(cy) * m[13 * stride]; }
-  if constexpr (cz != 0) { ccs += m[6 * stride]; cj += R(cz) * m[3 * stride]; cb += R(cz) * m[14 * stride]; }
-  if constexpr (cx != 0 && cy != 0) ccs += R(2 * cx * cy) * m[7 * stride];
-  if constexpr (cx != 0 && cz != 0) ccs += R(2 * cx * cz) * m[8 * stride];
-  if constexpr (cy != 0 && cz != 0) ccs += R(2 * cy * cz) * m[9 * stride];
+  if constexpr (cx != 0) { ccs += m(4); cj += R(cx) * m(1); cb += R(cx) * m(12); }
+  if constexpr (cy != 0) { ccs += m(5); cj += R(cy) * m(2); cb += R(cy) * m(13); }
+  if constexpr (cz != 0) { ccs += m(6); cj += R(cz) * m(3); cb += R(cz) * m(14); }
+  if constexpr (cx != 0 && cy != 0) ccs += R(2 * cx * cy) * m(7);
+  if constexpr (cx != 0 && cz != 0) ccs += R(2 * cx * cz) * m(8);
+  if constexpr (cy != 0 && cz != 0) ccs += R(2 * cy * cz) * m(9);
   const R w = (R)L::w[I];
   // P_i - w_i rho0 and P^A_i - w_i rho0 / 2
   R dP;
   if constexpr (FOLD) {
-    dP = w * (m[0] + R(3) * sg * cj + R(4.5) * ccs);
-    if constexpr (I == 0) dP += R(2.0 / 3.0) * m[10 * stride];
+    dP = w * (m(0) + R(3) * sg * cj + R(4.5) * ccs);
+    if constexpr (I == 0) dP += R(2.0 / 3.0) * m(10);
   } else {
-    const R tr = m[4 * stride] + m[5 * stride] + (L::D == 3 ? (R)m[6 * stride] : R(0));
-    dP = w * (m[0] + R(3) * sg * cj + R(4.5) * (ccs - tr * R(1.0 / 3.0))) + (R)llb_v<L>(I) * m[10 * stride];
+    const R tr = m(4) + m(5) + (L::D == 3 ? (R)m(6) : R(0));
+    dP = w * (m(0) + R(3) * sg * cj + R(4.5) * (ccs - tr * R(1.0 / 3.0))) + (R)llb_v<L>(I) * m(10);
   }
-  const R av = m[11 * stride];
+  const R av = m(11);
   R dPA = av * dP + w * rho0 * (av - R(0.5));
   if constexpr (I != 0) dPA += sg * (R)(L::w[I] * inv_norm<L>(I)) * cb;
   acc.dA += dPA;
@@ -88,6 +89,18 @@ __device__ __forceinline__ void llb_pull_dir(const P* m, size_t stride, R sg, R 
   if constexpr (cx != 0 && cy != 0) acc.p[3] += R(cx * cy) * dP;
   if constexpr (cx != 0 && cz != 0) acc.p[4] += R(cx * cz) * dP;
   if constexpr (cy != 0 && cz != 0) acc.p[5] += R(cy * cz) * dP;
+}
+
+// the same with channel k at m[k * stride]
+template <class P>
+struct LlbStrided {
+  const P* p;
+  size_t stride;
+  __device__ __forceinline__ P operator()(int k) const { return p[k * stride]; }
+};
+template <class L, int I, bool FOLD = false, class R, class P>
+__device__ __forceinline__ void llb_pull_dir(const P* m, size_t stride, R sg, R rho0, LlbPullSums<R>& acc) {
+  llb_pull_dir_v<L, I, FOLD>(LlbStrided<P>{m, stride}, sg, rho0, acc);
 }
 
 // phi and the pre-collision moments of site s
@@ -136,14 +149,46 @@ __global__ void __launch_bounds__(256) k_llb_pull(const S* __restrict__ M, S* __
 // The same pass with the moments of a TX x TY tile plus a one-site halo staged
 // in an LDS ring, marching along z (the FP32 path): each moment is read from
 // memory once per tile, and the 27 upstream sites of a site come from LDS.
-// The ring is [slot][channel][plane position] with only the 2 RZ + 1 planes in
-// use (about 71 KB for a 3D 64 x 4 tile, so two workgroups fit a CU): the next
-// plane waits in registers and replaces the oldest between two barriers.
+// Each staged position holds its 15 channels (channel 0 folded as
+// llb_pull_dir's FOLD form reads it) in four 16-byte records, grouped so that
+// a direction reads the first record and one more per nonzero component of
+// c_i:
+//   g0 {rho'', a, s, S_xy}  g1 {J_x, b_x, S_xx, S_xz}
+//   g2 {J_y, b_y, S_yy, S_yz}  g3 {J_z, b_z, S_zz, -}
+// (1 to 4 ds_read_b128 per direction).  The ring is [slot][record][position]
+// with only the 2 RZ + 1 planes in use (76 KB for a 3D 64 x 4 tile, so two
+// workgroups fit a CU): the next plane waits in registers and replaces the
+// oldest between two barriers.
 template <class TS>
 constexpr int llb_slots() { return 2 * TS::RZ + 1; }
 template <class TS>
 struct LlbPullSmem {
-  float ring[llb_slots<TS>() * LLB_NM * TS::PL];
+  float4 rec[llb_slots<TS>() * 4 * TS::PL];
+};
+
+// the four records of one staged position
+struct LlbPacked {
+  float4 g0, g1, g2, g3;
+  __device__ __forceinline__ float operator()(int k) const {
+    switch (k) {
+      case 0: return g0.x;
+      case 11: return g0.y;
+      case 10: return g0.z;
+      case 7: return g0.w;
+      case 1: return g1.x;
+      case 12: return g1.y;
+      case 4: return g1.z;
+      case 8: return g1.w;
+      case 2: return g2.x;
+      case 13: return g2.y;
+      case 5: return g2.z;
+      case 9: return g2.w;
+      case 3: return g3.x;
+      case 14: return g3.y;
+      case 6: return g3.z;
+    }
+    return 0.0f;
+  }
 };
 
 template <class TS>
@@ -168,17 +213,20 @@ __device__ __forceinline__ void llb_fetch_plane(float (&v)[LLB_NM * ((TS::PL + T
 }
 
 template <class TS>
-__device__ __forceinline__ void llb_commit_plane(float* __restrict__ ring, int slot,
+__device__ __forceinline__ void llb_commit_plane(float4* __restrict__ rec, int slot,
                                                  const float (&v)[LLB_NM * ((TS::PL + TS::NT - 1) / TS::NT)],
                                                  int tid) {
   constexpr int NPC = (TS::PL + TS::NT - 1) / TS::NT;
-  float* dst = ring + slot * (LLB_NM * TS::PL);
+  float4* dst = rec + slot * 4 * TS::PL;
 #pragma unroll
   for (int k = 0; k < NPC; ++k) {
     const int rr = tid + k * TS::NT;
     if (rr < TS::PL) {
-#pragma unroll
-      for (int ch = 0; ch < LLB_NM; ++ch) dst[ch * TS::PL + rr] = v[ch * NPC + k];
+      auto c = [&](int ch) { return v[ch * NPC + k]; };
+      dst[rr] = make_float4(c(0), c(11), c(10), c(7));
+      dst[TS::PL + rr] = make_float4(c(1), c(12), c(4), c(8));
+      dst[2 * TS::PL + rr] = make_float4(c(2), c(13), c(5), c(9));
+      dst[3 * TS::PL + rr] = make_float4(c(3), c(14), c(6), 0.0f);
     }
   }
 }
@@ -188,7 +236,6 @@ __global__ void __launch_bounds__(TS::NT) k_llb_pull_ring(const float* __restric
                                                           float* __restrict__ phi, StepArgs a) {
   __shared__ LlbPullSmem<TS> sm;
   constexpr int NPC = (TS::PL + TS::NT - 1) / TS::NT;
-  constexpr int SLOT = LLB_NM * TS::PL;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, TS::TX, TS::TY);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TS::TX * ty;
   const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
@@ -198,7 +245,7 @@ __global__ void __launch_bounds__(TS::NT) k_llb_pull_ring(const float* __restric
   for (int dz = -TS::RZ; dz <= TS::RZ; ++dz) {
     float v[LLB_NM * NPC];
     llb_fetch_plane<TS>(v, z0 + dz, M, x0, y0, a, tid);
-    llb_commit_plane<TS>(sm.ring, plane_slot(z0 + dz, NS), v, tid);
+    llb_commit_plane<TS>(sm.rec, plane_slot(z0 + dz, NS), v, tid);
   }
   __syncthreads();
   const float rho0 = 2.0f * (float)a.half_rho0;
@@ -216,15 +263,20 @@ __global__ void __launch_bounds__(TS::NT) k_llb_pull_ring(const float* __restric
         constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
         constexpr int ix = 1 - cx, iy = 1 - cy, iz = 1 - cz;
         const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
-        const int moving = ring_slot(zcs, -cz, NS) * SLOT + sc0 - cy * TS::TXH - cx;
-        const int bounced = zcs * SLOT + sc0;
-        llb_pull_dir<L, I, true>(sm.ring + (solid ? bounced : moving), (size_t)TS::PL, solid ? -1.0f : 1.0f, rho0,
-                                 acc);
+        const int slot = solid ? zcs : ring_slot(zcs, -cz, NS);
+        const int pos = solid ? sc0 : sc0 - cy * TS::TXH - cx;
+        const float4* r = sm.rec + slot * 4 * TS::PL + pos;
+        LlbPacked m{r[0], make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f),
+                    make_float4(0.f, 0.f, 0.f, 0.f)};
+        if constexpr (cx != 0) m.g1 = r[TS::PL];
+        if constexpr (cy != 0) m.g2 = r[2 * TS::PL];
+        if constexpr (cz != 0) m.g3 = r[3 * TS::PL];
+        llb_pull_dir_v<L, I, true>(m, solid ? -1.0f : 1.0f, rho0, acc);
       });
       llb_pull_store(acc, rho0, n.site, a.N, W, phi);
     }
     __syncthreads();  // the oldest plane is no longer read
-    if (more) llb_commit_plane<TS>(sm.ring, plane_slot(z + 1 + TS::RZ, NS), nxt, tid);
+    if (more) llb_commit_plane<TS>(sm.rec, plane_slot(z + 1 + TS::RZ, NS), nxt, tid);
     __syncthreads();
   }
 }
