@@ -398,10 +398,13 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
   if (p->streaming == LB_STREAM_IN_PLACE) h->ip = inplace_for(p->lattice);
   if (p->scheme == LB_SCHEME_MOMENTS) h->llb = llb_for(p->lattice);
   (void)hipGetDevice(&h->device);
-  // pass-2 blocks march through z; aim for about 2048 blocks in flight
+  // tiles march through z; aim for about 1024 workgroups (4 per CU): longer
+  // marches amortise the staging of the first planes, measured best at 16
+  // planes on the 256 x 128 x 128 channel (FP16 total layout +2%, moment
+  // scheme +6% over 8 planes; plain FP32 unchanged)
   {
     const long bxy = (long)((p->nx + TILE_X - 1) / TILE_X) * ((p->ny + TILE_Y - 1) / TILE_Y);
-    long zb = (bxy * p->nz) / 2048;
+    long zb = (bxy * p->nz) / 1024;
     if (zb < 1) zb = 1;
     if (zb > 16) zb = 16;
     if (zb > p->nz) zb = p->nz;
