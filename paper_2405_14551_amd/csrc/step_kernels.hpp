@@ -10,10 +10,12 @@
 //                        interface sites (Eq. near_cont_force), pull the
 //                        populations again, Guo-forced BGK on the total
 //                        (Eq. disteq), perturbation Omega^(2), recolouring
-//                        (Eqs. ome3_1, ome3_2), store into the other buffer.
+//                        (Eqs. ome3_1, ome3_2), store into the other buffer
+//                        (or, streaming in place, into the slots just read).
 // The colour gradient at t+1 needs phi of the neighbours after streaming, so
 // the phase field has to be complete before any site collides; the two passes
-// are that dependency.
+// are that dependency.  The moment-based scheme has its own two passes
+// (llb_kernels.hpp) and shares the ring, gradient and near-contact helpers.
 //
 // Layout: populations f[k][i][s] (k colour, i velocity, s = x + nx (y + ny z)),
 // x fastest, so each wave's 64 lanes touch 64 consecutive sites of one row for
@@ -46,8 +48,8 @@ __device__ __forceinline__ void static_for(F&& f) {
 // i.e. each colour minus its share of the rest equilibrium, so that sums and
 // BGK differences are formed from small numbers (the shifted-population
 // idea of the paper's mixed-precision section, applied to the arithmetic).
-// FP64/FP32 keep f^k_i in memory and shift on load/store; the 16-bit types
-// keep d^k_i itself, rounded to nearest even.
+// FP64/FP32 keep f^k_i in memory and shift on load/store; F32S and the 16-bit
+// types keep d^k_i itself (16-bit: rounded to nearest even).
 template <class S>
 struct Storage;
 
