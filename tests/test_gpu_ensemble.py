@@ -75,7 +75,7 @@ def test_ensemble_fp64_matches_oracle_per_channel(mode, graph, lattice):
     ens.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16t"])
+@pytest.mark.parametrize("storage", ["f32", "f16t", "f16ct"])
 def test_graph_replays_match_eager(storage):
     """Several graph replays, with eager work and synchronisations between
     them, give bit-identical states to eager single launches."""
