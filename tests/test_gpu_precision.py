@@ -69,6 +69,33 @@ def test_storage_precision_vs_fp64_oracle():
         }
         report[st] = e
         print(f"  {st}: {json.dumps(e)}", flush=True)
+    # the moment-based scheme in FP32 against its own FP64 definition
+    from oracle.llb import OracleLLB
+    lorc = OracleLLB(p).init_droplets(cen, rad)
+    done = 0
+    while done < STEPS:
+        k = min(50, STEPS - done)
+        lorc.step(k)
+        done += k
+        print(f"  moment oracle step {done}/{STEPS}", flush=True)
+    lf = lorc.fields()
+    lumax = np.sqrt((lf["u"] ** 2).sum(0)).max()
+    sim = lb.Simulation(**dict(kw, storage="f32", scheme="moments")).init_droplets(cen, rad)
+    d0 = sim.diagnostics()
+    sim.step(STEPS)
+    g = {k: v.double().cpu().numpy() for k, v in sim.fields(("rho_a", "rho_b", "phi", "u")).items()}
+    d = sim.diagnostics()
+    sim.close()
+    report["moments_f32"] = {
+        "rho_a": float(np.abs(g["rho_a"] - lf["rho_a"]).max() / np.abs(lf["rho_a"]).max()),
+        "u": float(np.abs(g["u"] - lf["u"]).max() / lumax),
+        "u_rms": float(np.sqrt(((g["u"] - lf["u"]) ** 2).mean()) / np.sqrt((lf["u"] ** 2).mean())),
+        "laplace_dp_rel": float(abs(d[7] - lorc.diagnostics()[7]) / abs(lorc.diagnostics()[7])),
+        "count": int(d[6]),
+        "mass_drift_a": float(abs(d[0] - d0[0]) / d0[0]),
+    }
+    print(f"  moments_f32 (vs the FP64 moment oracle): {json.dumps(report['moments_f32'])}", flush=True)
+    assert report["moments_f32"]["rho_a"] < 1e-4 and report["moments_f32"]["u"] < 1e-2
     out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
     if os.path.isdir(out):
         with open(os.path.join(out, f"precision_crop_{STEPS}.json"), "w") as fh:
