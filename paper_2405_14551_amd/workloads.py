@@ -15,6 +15,7 @@ Workloads (sizes as in the benchmark definitions):
                 near-contact range 3 / strength 0.02, FP32
   big_3d        same physics on 512x256x256 with 1024 droplets R=8
   dense_3d      D3Q27 384x384x192, 2000 droplets R=8 on a jittered FCC slab
+                (surface gap 3.5 +- 0.25 per coordinate)
 """
 from __future__ import annotations
 
@@ -63,10 +64,12 @@ def rsa_centres(shape, walls, radius, count, seed=SEED, min_gap=3.0, max_tries=2
     return cen
 
 
-def fcc_slab_centres(shape, radius, count, gap=2.0, jitter=0.5, seed=SEED):
+def fcc_slab_centres(shape, radius, count, gap=3.5, jitter=0.25, seed=SEED):
     """Droplets on an FCC lattice with nearest-neighbour surface gap ``gap``
     (+- ``jitter`` uniform displacement per coordinate), filling a slab
-    centred in z; periodic x/y, walls z."""
+    centred in z; periodic x/y, walls z.  With the defaults every surface
+    starts just outside the near-contact range (h_max = 3): the force keeps
+    the emulsion apart, and without it the films drain and the droplets merge."""
     rng = np.random.Generator(np.random.PCG64(seed))
     nx, ny, nz = shape
     dnn = 2 * radius + gap                   # nearest-neighbour distance

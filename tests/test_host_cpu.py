@@ -88,4 +88,8 @@ def test_large_recipes(kind):
     else:
         w = W.dense_3d()
         assert w["shape"] == (384, 384, 192) and len(w["radii"]) == 2000
+        # every film starts beyond the near-contact range h_max = 3
+        assert _min_gap(w["centres"], w["radii"], w["shape"], w["walls"]) > 3.0
+        assert np.all(w["centres"][:, 2] - 8.0 >= 2.0)
+        assert np.all(w["centres"][:, 2] + 8.0 <= w["shape"][2] - 1 - 2.0)
     assert np.all(np.isfinite(w["centres"]))
