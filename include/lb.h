@@ -287,8 +287,10 @@ int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int c
  *                (dx+1) + 3 (dy+1) + 9 (dz+1) (wall ghosts mirrored, periodic
  *                axes wrapped), then the unit normal g/|g|
  *   network      tanh(W1 x + b1) (64), tanh(W2 h1 + b2) (64), W3 h2 + b3 (3)
- *   output       F_nc / (nc_A |g|); the explicit force (A_h/2) g makes this the
- *                normal times A_h / (2 nc_A)
+ *   output       y, trained on F_nc / (nc_A |g|); the explicit force (A_h/2) g
+ *                makes this target the normal n = g/|g| times A_h / (2 nc_A)
+ *   force        the step applies the repulsive normal part of y, the form
+ *                of the explicit force: F_nc = nc_A |g| max(0, y . n) n
  * Parameters are LB_MLP_PARAMS floats: W1 (64x30, row-major), b1 (64),
  * W2 (64x64), b2 (64), W3 (3x64), b3 (3).  Inference (in the collision pass
  * under LB_NC_MLP, and lb_mlp_infer) uses BF16 inputs, weights and hidden

@@ -220,6 +220,16 @@ class Closure:
         return (np.all((X >= self.lo) & (X <= self.hi), axis=1)
                 & (np.asarray(gnorm, dtype=np.float32) >= self.gmin))
 
-    def force(self, X, gnorm, A_nc):
-        """F_nc = A_nc |g| y (|g| in FP64)."""
-        return A_nc * np.asarray(gnorm, dtype=np.float64)[:, None] * forward_bf16(self.theta, X)
+    def force(self, X, g):
+        """The force the closure gives at rows X: the explicit model (Eq.
+        near_cont_force) is a repulsion along the colour gradient, so only the
+        output's component along the unit normal is used, and only when it
+        pushes along g:  F_nc = A_nc |g| max(0, y . n) n,  n = g/|g|  (g the
+        FP64 gradient at the rows, shape (3, m); A_nc is applied by the
+        caller)."""
+        g = np.asarray(g, dtype=np.float64)
+        gn = np.sqrt((g * g).sum(0))
+        n = g / gn
+        y = forward_bf16(self.theta, X)
+        yn = np.maximum(0.0, (y * n.T).sum(1))
+        return gn[:, None] * yn[:, None] * n.T

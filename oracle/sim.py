@@ -290,7 +290,7 @@ class OracleSim:
             src[iz, iy, ix] = np.where(use, 1, 2)
             self._nc_source = src
             if use.any():
-                Fm = p.closure.force(X[use], gn[use], p.nc_A)
+                Fm = p.nc_A * p.closure.force(X[use], gx[:, use])
                 F[:, iz[use], iy[use], ix[use]] = Fm.T
         return F
 

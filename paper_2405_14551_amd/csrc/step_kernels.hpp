@@ -955,9 +955,12 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         mlp_wave_apply(sm.net, sm.queue[tid >> 6], inr, inputs, o);
         use_net = inr;
         if (inr) {
-          // the network gives the force per unit strength and |g|
+          // the network gives the force per unit strength and |g|; the force
+          // keeps the explicit model's form, a repulsion along the colour
+          // gradient: F = nc_A |g| max(0, y . g/|g|) g/|g|
           const R sA = (R)a.nc_A * gnr;
-          fnx = sA * (R)o[0]; fny = sA * (R)o[1]; fnz = sA * (R)o[2];
+          const R yn = fmax(R(0), ((R)o[0] * gx + (R)o[1] * gy + (R)o[2] * gz) / (gnr * gnr));
+          fnx = sA * yn * gx; fny = sA * yn * gy; fnz = sA * yn * gz;
         }
       }
       if constexpr (NC) {
