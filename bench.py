@@ -58,6 +58,17 @@ def plain_state_bytes(q, storage):
     return 2 * q * s * 2 + 2 * r
 
 
+def kernel_source_hash():
+    """Hash of the sources that fix the passes' code and launch shapes (the
+    kernels and their launch wrappers): a traffic figure measured for other
+    sources is not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("step_kernels.hpp", "lattice_ops.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2405_14551_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profiles(kernel_tag, workload_tag):
     """HBM bytes per launch measured with rocprofv3 counters, if a summary for
     this kernel source is committed (profiles/traffic_<kernel>_<workload>.txt
@@ -71,8 +82,7 @@ def traffic_from_profiles(kernel_tag, workload_tag):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2405_14551_amd", "csrc", "step_kernels.hpp")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = kernel_source_hash()
     if kv.get("source_hash") != h or "bytes_per_launch" not in kv:
         return None
     return float(kv["bytes_per_launch"])
