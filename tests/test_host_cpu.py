@@ -93,3 +93,17 @@ def test_large_recipes(kind):
         assert np.all(w["centres"][:, 2] - 8.0 >= 2.0)
         assert np.all(w["centres"][:, 2] + 8.0 <= w["shape"][2] - 1 - 2.0)
     assert np.all(np.isfinite(w["centres"]))
+
+
+@pytest.mark.parametrize("workload", ["channel_3d_f32", "channel_3d_f16t"])
+def test_committed_counter_summary_matches_the_kernel_sources(workload):
+    """The HBM traffic the benchmark reports comes from rocprofv3 counters
+    taken for exactly the committed kernel and launch sources: the summary's
+    source hash must match them (a kernel edit needs the counters taken
+    again), and the bytes per launch must exceed the algorithmic bytes of one
+    collision launch on the 256 x 128 x 128 channel."""
+    b = bench.traffic_from_profiles("collide", workload)
+    assert b is not None, "profiles/traffic_collide_%s.txt is stale or missing" % workload
+    sites = 256 * 128 * 128
+    per_site = bench.algorithmic_bytes(27, "f32" if workload.endswith("f32") else "f16t")[1]
+    assert 1.0 <= b / (per_site * sites) < 1.5
