@@ -27,7 +27,7 @@ performs, for every fluid site and in this order:
                                                                [Eqs. ome3_1, ome3_2]
 
 Readings where the paper is silent (each listed in the design notes):
-Guo forcing for the "forcing contribution"; B_0 = w_0 - 2/3, B_i = w_i;
+Guo forcing for the forcing term the paper leaves open; B_0 = w_0 - 2/3, B_i = w_i;
 surface tension sigma = (2/9)(A_A + A_B) tau (the printed omega-bar is read
 as 2/(6 nu + 1) = 1/tau); cos(theta) = 0 for the rest direction or g = 0;
 the near-contact scan of ``near_contact_force``; halfway bounce-back walls.
