@@ -6,7 +6,8 @@ force, near contact) runs with FP32, shifted FP16 and shifted BF16 storage
 accuracy bound for 16-bit storage, so these numbers are a measured statement
 ("parity unpinned"); the test asserts only what must hold at any precision
 (finite fields, FP32 close to FP64, per-colour mass to storage rounding) and
-records the errors.  LB_PRECISION_STEPS sets the step count (default 200)."""
+records the errors.  LB_PRECISION_STEPS sets the step count (default 200);
+LB_PRECISION_OUT names a directory for a JSON copy of the report."""
 import json
 import os
 import sys
@@ -96,8 +97,8 @@ def test_storage_precision_vs_fp64_oracle():
     }
     print(f"  moments_f32 (vs the FP64 moment oracle): {json.dumps(report['moments_f32'])}", flush=True)
     assert report["moments_f32"]["rho_a"] < 1e-4 and report["moments_f32"]["u"] < 1e-2
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("LB_PRECISION_OUT")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, f"precision_crop_{STEPS}.json"), "w") as fh:
             json.dump(report, fh, indent=1)
     assert report["f32"]["rho_a"] < 1e-4 and report["f32"]["u"] < 1e-2
