@@ -117,14 +117,16 @@ def cpu_baseline(seconds_target=10.0):
                       f"(host nproc {os.cpu_count()})"}
 
 
-def time_storage(kw, cen, rad, storage, steps, warmup, streaming="two_copies", scheme="populations"):
+def time_storage(kw, cen, rad, storage, steps, warmup, streaming="two_copies", scheme="populations",
+                 rounding="nearest"):
     """MLUPS and per-launch pass times of the same workload with another
     storage layout or streaming (HIP events on the library's stream), and the
     device memory the population state takes per site (both copies with
     two-copy streaming)."""
     import torch
     from paper_2405_14551_amd import lb
-    sim = lb.Simulation(**dict(kw, storage=storage, streaming=streaming, scheme=scheme)).init_droplets(cen, rad)
+    sim = lb.Simulation(**dict(kw, storage=storage, streaming=streaming, scheme=scheme,
+                               rounding=rounding)).init_droplets(cen, rad)
     copies = 1 if streaming == "in_place" else 2
     state_per_site = copies * sim.state_bytes() / (kw["shape"][0] * kw["shape"][1] * kw["shape"][2])
     sim.step(warmup)
@@ -390,6 +392,10 @@ def main():
             var[name] = time_storage(kw, cen, rad, st, vs, args.warmup, mode)
             var[name]["vs_plain_f32"] = round(var[name]["MLUPS"] / mlups, 3)
             print(f"# variant {name}: {var[name]}", file=sys.stderr, flush=True)
+        # FP16 total layout with stochastic rounding of the stored totals
+        var["f16t_sround"] = time_storage(kw, cen, rad, "f16t", vs, args.warmup, rounding="stochastic")
+        var["f16t_sround"]["vs_plain_f32"] = round(var["f16t_sround"]["MLUPS"] / mlups, 3)
+        print(f"# variant f16t_sround: {var['f16t_sround']}", file=sys.stderr, flush=True)
         # the moment-based (regularised) scheme: 15 moments per site
         var["moments_f32"] = time_storage(kw, cen, rad, "f32", vs, args.warmup, scheme="moments")
         var["moments_f32"]["vs_plain_f32"] = round(var["moments_f32"]["MLUPS"] / mlups, 3)

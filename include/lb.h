@@ -123,6 +123,20 @@ typedef enum lb_streaming { LB_STREAM_TWO_COPIES = 0, LB_STREAM_IN_PLACE = 1 } l
  *      Single lattices, two-copy streaming, nc_mode off or explicit. */
 typedef enum lb_scheme { LB_SCHEME_POPULATIONS = 0, LB_SCHEME_MOMENTS = 1 } lb_scheme;
 
+/* Rounding of the stored totals of LB_F16_TOTAL and LB_BF16_TOTAL (no other
+ * storage takes a setting other than the default).
+ *  LB_ROUND_NEAREST     nearest value, ties to even (the default).
+ *  LB_ROUND_STOCHASTIC  one of the two neighbouring 16-bit values, the upper
+ *                       one with probability equal to the value's fractional
+ *                       position between them (the MI355X's stochastic
+ *                       conversion), driven by a deterministic 32-bit word per
+ *                       store: lowbias32 (C. Wellons' integer hash) of
+ *                       (site * 32 + i) * 0x9E3779B9 + step * 0x85EBCA6B,
+ *                       exclusive-or the FP32 value's bits.  Runs repeat bit for
+ *                       bit, and in-place and two-copy streaming give the same
+ *                       values.  Single lattices, nc_mode off or explicit. */
+typedef enum lb_rounding { LB_ROUND_NEAREST = 0, LB_ROUND_STOCHASTIC = 1 } lb_rounding;
+
 /* field selection bits for lb_fields; dst[k] belongs to bit k */
 enum {
   LB_FIELD_RHO_A = 1u << 0,   /* real[N]                                   */
@@ -160,6 +174,7 @@ typedef struct lb_params {
                              1/nu = (rho_A/rho)/nu_A + (rho_B/rho)/nu_B, and BGK and the
                              forcing use tau = 3 nu + 1/2                                */
   int scheme;             /* lb_scheme                                                   */
+  int rounding;           /* lb_rounding                                                 */
 } lb_params;
 
 typedef struct lb_handle lb_handle;

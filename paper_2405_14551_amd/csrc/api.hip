@@ -179,6 +179,8 @@ struct lb_handle {
     a.nc_steps = (int)std::floor(p.nc_hmax);
     a.phi_I = p.phi_interface;
     a.z_per_block = z_per_block;
+    a.sround = p.rounding == LB_ROUND_STOCHASTIC;
+    a.step = 0;
     return a;
   }
   FieldPtrs field_ptrs() const { return FieldPtrs{rho_a, rho_b, u, fnc, flags}; }
@@ -285,6 +287,12 @@ static int validate(const lb_params* p) {
     if (p->nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "the moment-based scheme takes nc_mode off or explicit");
     if (p->streaming != LB_STREAM_TWO_COPIES) return fail(LB_EINVAL, "the moment-based scheme streams with two copies");
   }
+  if (p->rounding != LB_ROUND_NEAREST && p->rounding != LB_ROUND_STOCHASTIC)
+    return fail(LB_EINVAL, "unknown rounding %d", p->rounding);
+  if (p->rounding == LB_ROUND_STOCHASTIC && p->storage != LB_F16_TOTAL && p->storage != LB_BF16_TOTAL)
+    return fail(LB_EINVAL, "stochastic rounding applies to LB_F16_TOTAL and LB_BF16_TOTAL only");
+  if (p->rounding == LB_ROUND_STOCHASTIC && p->nc_mode == LB_NC_MLP)
+    return fail(LB_EINVAL, "stochastic rounding takes nc_mode off or explicit");
   return LB_OK;
 }
 
@@ -343,6 +351,8 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
       return fail(LB_EINVAL, "channel %d: ensembles stream with two copies (LB_STREAM_TWO_COPIES)", c);
     if (p[c].scheme != LB_SCHEME_POPULATIONS)
       return fail(LB_EINVAL, "channel %d: ensembles use the population scheme", c);
+    if (p[c].rounding != LB_ROUND_NEAREST)
+      return fail(LB_EINVAL, "channel %d: ensembles round to nearest (stochastic rounding is single-lattice)", c);
   }
   if (p[0].nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "ensembles take nc_mode LB_NC_OFF or LB_NC_EXPLICIT");
   if (!ensemble_storage(p[0].storage))
@@ -716,12 +726,13 @@ int lb_step(lb_handle* h, int nsteps) {
   if (h->p.nc_mode == LB_NC_MLP && !h->mlp_weights)
     return fail(LB_EINVAL, "LB_NC_MLP needs network parameters (lb_mlp_set_weights or lb_mlp_train)");
   (void)hipSetDevice(h->device);
-  const StepArgs a = h->step_args();
+  StepArgs a = h->step_args();
   const FieldPtrs fo = h->field_ptrs();
   const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
   const bool mlp = h->p.nc_mode == LB_NC_MLP;
   const int st = h->p.storage;
   for (int s = 0; s < nsteps; ++s) {
+    a.step = (uint32_t)h->t;  // keys the stochastic rounding of this step's stores
     const bool diag_now = h->p.diag_every > 0 && ((h->t + 1) % h->p.diag_every) == 0;
     const bool fields = (s == nsteps - 1) || diag_now;
     int r = prof_mark(h, 0, true);

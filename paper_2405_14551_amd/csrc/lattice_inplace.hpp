@@ -32,12 +32,7 @@ struct InPlaceLaunch {
   template <class S, bool TOT, int STREAM>
   static hipError_t collide_s(bool nc, bool fields, void* f, float* scout, const void* phi, const FieldPtrs& fo,
                               const StepArgs& a, hipStream_t s) {
-    if (nc) {
-      return fields ? B::template collide_t<S, 4, true, true, TOT, STREAM>(f, f, scout, phi, fo, a, s)
-                    : B::template collide_t<S, 4, true, false, TOT, STREAM>(f, f, scout, phi, fo, a, s);
-    }
-    return fields ? B::template collide_t<S, 1, false, true, TOT, STREAM>(f, f, scout, phi, fo, a, s)
-                  : B::template collide_t<S, 1, false, false, TOT, STREAM>(f, f, scout, phi, fo, a, s);
+    return B::template collide_s<S, TOT, STREAM>(nc, fields, f, f, scout, phi, fo, a, s);
   }
 
   template <int STREAM>

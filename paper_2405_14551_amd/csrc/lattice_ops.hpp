@@ -57,7 +57,7 @@ struct Launch {
     return hipErrorInvalidValue;
   }
 
-  template <class S, int RAD, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
+  template <class S, int RAD, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool SR = false>
   static hipError_t collide_t(const void* fin, void* fout, float* scout, const void* phi,
                               const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     using R = typename Storage<S>::real;
@@ -79,19 +79,28 @@ struct Launch {
     }
     b.z_per_block = zb;
     dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide<L, S, T, NC, FIELDS, TOT, STREAM><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b);
+    k_collide<L, S, T, NC, FIELDS, TOT, STREAM, SR><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b);
     return hipGetLastError();
   }
 
-  template <class S, bool TOT>
-  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, float* scout,
+  template <class S, bool TOT, int STREAM = STREAM_AB, bool SR = false>
+  static hipError_t collide_n(bool nc, bool fields, const void* fin, void* fout, float* scout,
                               const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
     if (nc) {
-      return fields ? collide_t<S, 4, true, true, TOT>(fin, fout, scout, phi, fo, a, s)
-                    : collide_t<S, 4, true, false, TOT>(fin, fout, scout, phi, fo, a, s);
+      return fields ? collide_t<S, 4, true, true, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s)
+                    : collide_t<S, 4, true, false, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s);
     }
-    return fields ? collide_t<S, 1, false, true, TOT>(fin, fout, scout, phi, fo, a, s)
-                  : collide_t<S, 1, false, false, TOT>(fin, fout, scout, phi, fo, a, s);
+    return fields ? collide_t<S, 1, false, true, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s)
+                  : collide_t<S, 1, false, false, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s);
+  }
+  // the stochastic-rounding kernels exist for the FP16 and BF16 totals only
+  template <class S, bool TOT, int STREAM = STREAM_AB>
+  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, float* scout,
+                              const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+    if constexpr (TOT && sizeof(S) == 2 && !std::is_same_v<S, F16C>) {
+      if (a.sround) return collide_n<S, TOT, STREAM, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
+    }
+    return collide_n<S, TOT, STREAM, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
   }
 
   static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, float* scout, const void* phi,

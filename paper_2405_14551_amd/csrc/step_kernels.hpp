@@ -229,6 +229,8 @@ struct StepArgs {
   double phi_I;      // interface threshold
   int z_per_block;   // planes a pass-2 block marches through
   int tiles_x, tiles_y;  // tile counts of the launch (x fastest)
+  int sround;        // 16-bit totals: stochastic rounding of the stores (selects the kernel)
+  uint32_t step;     // step index, part of the stochastic rounding key
 };
 
 // Workgroups are handed to the 8 XCDs round-robin in dispatch order.  Renumber
@@ -626,6 +628,29 @@ __device__ __forceinline__ float total_bload(__amdgpu_buffer_rsrc_t r, uint32_t 
   else if constexpr (std::is_same_v<S, F16C>) return f16c_decode(__builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, CP));
   else return (float)__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, CP));
 }
+// Stochastic rounding of a stored total to FP16 or BF16: the hardware
+// conversion picks the upper neighbour with probability equal to the value's
+// fractional position between the two, from a 32-bit random word.  The word
+// is lowbias32 (C. Wellons' 32-bit integer hash) of the site, direction and
+// step, exclusive-or the value's bits: a deterministic stream that does not
+// depend on where the value is stored (pushed slots or the site's own).
+__device__ __forceinline__ uint32_t sround_word(uint32_t site, int i, uint32_t step, float v) {
+  uint32_t x = (site * 32u + (uint32_t)i) * 0x9E3779B9u + step * 0x85EBCA6Bu;
+  x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+  return x ^ __builtin_bit_cast(uint32_t, v);
+}
+
+template <class S>
+__device__ __forceinline__ unsigned short sround_bits(float v, uint32_t word) {
+  if constexpr (std::is_same_v<S, _Float16>) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned short, __builtin_amdgcn_cvt_sr_f16_f32((h2){0, 0}, v, word, false)[0]);
+  } else {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned short, __builtin_amdgcn_cvt_sr_bf16_f32((b2){0, 0}, v, word, false)[0]);
+  }
+}
+
 template <class S>
 __device__ __forceinline__ void total_bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
   if constexpr (sizeof(S) == 4)
@@ -824,7 +849,8 @@ struct CollideSmem<L, S, T, TOT, true> : CollideSmem<L, S, T, TOT, false> {
 // takes part (lanes outside the lattice compute on a clamped site and store
 // nothing).  STREAM selects two-copy or in-place streaming (fin == fout for
 // the in-place kinds).
-template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false, int STREAM = STREAM_AB>
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false, int STREAM = STREAM_AB,
+          bool SR = false>
 __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __restrict__ fout,
                                              const typename Storage<S>::real* __restrict__ phi,
                                              float* __restrict__ scout,
@@ -1064,7 +1090,12 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
             so = (uint32_t)(I - pair_lo<L, I>()) * a.N * ES;
           }
           if constexpr (TOT) {
-            total_bstore<S>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, (float)ds);
+            const auto rs = pair_rsrc<L, I>((const S*)foutA, a.N);
+            if constexpr (SR)
+              __builtin_amdgcn_raw_buffer_store_b16(sround_bits<S>((float)ds, sround_word(n.site, I, a.step, (float)ds)),
+                                                    rs, vo, so, CPOL_NT);
+            else
+              total_bstore<S>(rs, vo, so, (float)ds);
           } else {
             const R wi = (R)L::w[I];
             const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
@@ -1124,14 +1155,16 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   }
 }
 
-template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
+// SR: stochastic rounding of the stored 16-bit totals (FP16 / BF16 total layouts)
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool SR = false>
 __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::real* __restrict__ phi,
                                                     float* __restrict__ scout,
                                                     FieldPtrs fo, StepArgs a) {
+  static_assert(!SR || (TOT && sizeof(S) == 2 && !std::is_same_v<S, F16C>), "stochastic rounding: FP16/BF16 totals");
   __shared__ CollideSmem<L, S, T, TOT> sm;
   const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
-  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM>(fin, fout, phi, scout, fo, a, tc, sm);
+  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM, SR>(fin, fout, phi, scout, fo, a, tc, sm);
 }
 
 // collision pass with the learned near-contact closure

@@ -22,6 +22,7 @@ TOTAL_LAYOUTS = ("f32t", "f16t", "bf16t", "f16ct")
 NC_MODE = {"off": 0, "explicit": 1, "mlp": 2}
 STREAMING = {"two_copies": 0, "in_place": 1}
 SCHEME = {"populations": 0, "moments": 1}
+ROUNDING = {"nearest": 0, "stochastic": 1}
 N_MOMENTS = 15
 MLP_PARAMS = 6339
 MLP_ROW = 32
@@ -59,6 +60,7 @@ class LbParams(ctypes.Structure):
         ("streaming", ctypes.c_int),
         ("tau_b", ctypes.c_double),
         ("scheme", ctypes.c_int),
+        ("rounding", ctypes.c_int),
     ]
 
 
@@ -154,7 +156,7 @@ def lattice_table(name):
 def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), walls=(0, 0, 0),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
                 nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0,
-                streaming="two_copies", tau_b=0.0, scheme="populations"):
+                streaming="two_copies", tau_b=0.0, scheme="populations", rounding="nearest"):
     p = LbParams()
     lib().lb_params_default(ctypes.byref(p))
     p.lattice = LATTICE[lattice]
@@ -172,6 +174,7 @@ def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), wa
     p.streaming = STREAMING[streaming]
     p.tau_b = float(tau_b)
     p.scheme = SCHEME[scheme]
+    p.rounding = ROUNDING[rounding]
     return p
 
 

@@ -78,6 +78,10 @@ def _create(**kw):
     dict(nc="mlp", lattice="D2Q9", shape=(16, 16, 1)),      # the learned closure is 3D
     dict(nc="mlp", storage="f16"),                          # per-colour 16-bit storage
     dict(nc="mlp", shape=(64, 3, 8)),
+    dict(rounding="stochastic"),                            # FP32 storage rounds nothing
+    dict(rounding="stochastic", storage="f16"),             # per-colour 16-bit
+    dict(rounding="stochastic", storage="f16ct"),           # FP16C has its own encoder
+    dict(rounding="stochastic", storage="f16t", nc="mlp"),  # not with the learned closure
 ])
 def test_invalid_params_rejected(kw):
     assert _create(**kw) == lb.LB_EINVAL
@@ -100,6 +104,9 @@ def test_bad_enum_and_null():
     assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
     p = lb.make_params()
     p.streaming = 2
+    assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
+    p = lb.make_params(storage="f16t")
+    p.rounding = 2
     assert L.lb_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == lb.LB_EINVAL
     p = lb.make_params()
     assert L.lb_create(ctypes.byref(p), 2, None, ctypes.byref(h)) == lb.LB_EINVAL
@@ -136,6 +143,9 @@ def test_ensemble_argument_checks():
     assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # ensembles use two copies
     arr[1] = lb.make_params(lattice="D3Q19", storage="f32", shape=(16, 8, 8), scheme="moments")
     assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # and the population scheme
+    arr[0] = lb.make_params(lattice="D3Q19", storage="f16t", shape=(16, 8, 8))
+    arr[1] = lb.make_params(lattice="D3Q19", storage="f16t", shape=(16, 8, 8), rounding="stochastic")
+    assert L.lb_create(arr, 2, None, ctypes.byref(h)) == lb.LB_EINVAL      # and round to nearest
 
 
 def test_closure_calls_reject_null_arguments():

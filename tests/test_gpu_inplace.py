@@ -70,6 +70,31 @@ def test_in_place_equals_two_copies(lat, shape, walls, nc, storage):
         _same(ab, ip)
     # the host copy of an odd-count state goes through the staging plane
     assert np.array_equal(ip.get_state(host=True), ab.get_state(host=True))
+
+
+@pytest.mark.parametrize("lat,shape,walls,nc", CASES[1:])
+@pytest.mark.parametrize("storage", ["f16t", "bf16t"])
+def test_in_place_equals_two_copies_stochastic_rounding(lat, shape, walls, nc, storage):
+    """Stochastic rounding keys its random words on site, direction and step,
+    not on where a value is stored: pushed slots (in place) and the site's own
+    (two copies) receive the same bits, and a second run repeats them."""
+    say(f"case in place vs two copies, stochastic rounding {lat} {storage} {shape}")
+    cen, rad = _drops(shape, True)
+    kw = dict(lattice=lat, storage=storage, nc=nc, shape=shape, walls=walls, tau=0.9, A=0.02,
+              body_force=(2e-5, 1e-6, 0), u0=(0.01, -0.005, 0.0), nc_A=0.03, rounding="stochastic")
+    ab = lb.Simulation(**kw).init_droplets(cen, rad)
+    ip = lb.Simulation(streaming="in_place", **kw).init_droplets(cen, rad)
+    again = lb.Simulation(**kw).init_droplets(cen, rad)
+    for n in (5, 1):
+        ab.step(n)
+        ip.step(n)
+        again.step(n)
+        _same(ab, ip)
+        _same(ab, again)
+    # the rounding differs from round-to-nearest
+    rne = lb.Simulation(**dict(kw, rounding="nearest")).init_droplets(cen, rad)
+    rne.step(6)
+    assert not torch.equal(rne.get_state(), ab.get_state())
     ab.close()
     ip.close()
 

@@ -508,6 +508,54 @@ def test_fp16c_full_size_sampled_sites():
     sim.close()
 
 
+@pytest.mark.parametrize("storage,frac_bits", [("f16t", 10), ("bf16t", 7)])
+def test_stochastic_rounding_full_size_sampled_sites(storage, frac_bits):
+    """The channel workload in a 16-bit total layout with stochastic
+    rounding: one GPU step from a developed state against the oracle's
+    windowed step.  Each stored total is one of the two 16-bit neighbours of
+    the oracle's total (within one step of it, plus the FP32 arithmetic's
+    2e-6 of the population scale), a good share of them is the farther
+    neighbour (rounding to nearest never is), and the rounding residuals
+    average out (their mean in units of the step is near 0)."""
+    w = W.channel_3d(storage=storage)
+    kw, cen, rad = W.sim_kwargs(w)
+    kw["rounding"] = "stochastic"
+    say(f"case stochastic rounding channel full size {storage}")
+    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    sim.step(30)
+    sA, sB = total_to_colours(sim, sim.get_state())
+    sim.step(1)
+    Tn, _ = sim.split_total_state(sim.get_state())
+    Tn = total_T(sim, Tn)
+    from oracle.lattice import make_lattice
+    wq = make_lattice("D3Q27").w
+    nx, ny, nz = kw["shape"]
+    rng = np.random.default_rng(9)
+    sites = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (63, 3, 7), (64, 4, 8), (200, 1, 1)]
+    for _ in range(40):
+        sites.append((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    p = oparams(kw, np.float32)
+    resid, worst = [], 0.0
+    for (x, y, z) in sites:
+        a, b, _ = step_window(p, sA, sB, (x, y, z))
+        T_orc = a + b - wq
+        # one step of the format at T_orc (normal numbers; the subnormal step below)
+        e = np.floor(np.log2(np.maximum(np.abs(T_orc), 2.0 ** -126)))
+        step = np.maximum(2.0 ** (e - frac_bits), 2.0 ** (-14 - 10) if frac_bits == 10 else 2.0 ** -133)
+        d = Tn[:, z, y, x] - T_orc
+        excess = (np.abs(d) - step) / np.abs(a + b).max()
+        worst = max(worst, float(excess.max()))
+        assert np.all(excess < 2e-6), ((x, y, z), excess.max())
+        resid.append(d / step)
+    r = np.concatenate(resid)
+    far = float(np.mean(np.abs(r) > 0.5 + 1e-3))
+    say(f"  {storage}: {len(r)} stored totals, worst excess over one step {worst:.2e}, "
+        f"farther neighbour {far:.3f}, mean residual {r.mean():+.4f} steps")
+    assert far > 0.1
+    assert abs(r.mean()) < 0.05
+    sim.close()
+
+
 def test_total_layout_checkpoint_roundtrip():
     w = W.channel_3d(storage="f16t", shape=(64, 40, 32), count=6, radius=6.0)
     kw, cen, rad = W.sim_kwargs(w)

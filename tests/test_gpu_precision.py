@@ -47,8 +47,10 @@ def test_storage_precision_vs_fp64_oracle():
     umax = np.sqrt((of["u"] ** 2).sum(0)).max()
     report = {"steps": STEPS, "shape": [nx, ny, nz], "droplets": int(len(rad)),
               "oracle": {"umax": float(umax), "laplace_dp": float(od[7]), "count": int(od[6])}}
-    for st in ("f32", "f32s", "f16", "bf16", "f32t", "f16t", "bf16t", "f16ct"):
-        kw2 = dict(kw, storage=st)
+    runs = [(st, st, "nearest") for st in ("f32", "f32s", "f16", "bf16", "f32t", "f16t", "bf16t", "f16ct")]
+    runs += [("f16t_sround", "f16t", "stochastic"), ("bf16t_sround", "bf16t", "stochastic")]
+    for name, st, rounding in runs:
+        kw2 = dict(kw, storage=st, rounding=rounding)
         sim = lb.Simulation(**kw2).init_droplets(cen, rad)
         d0 = sim.diagnostics()
         sim.step(STEPS)
@@ -56,7 +58,7 @@ def test_storage_precision_vs_fp64_oracle():
         d = sim.diagnostics()
         sim.close()
         for k in g:
-            assert np.isfinite(g[k]).all(), (st, k)
+            assert np.isfinite(g[k]).all(), (name, k)
         e = {
             "rho_a": float(np.abs(g["rho_a"] - of["rho_a"]).max() / np.abs(of["rho_a"]).max()),
             "rho_b": float(np.abs(g["rho_b"] - of["rho_b"]).max() / np.abs(of["rho_b"]).max()),
@@ -68,8 +70,8 @@ def test_storage_precision_vs_fp64_oracle():
             "mass_drift_a": float(abs(d[0] - d0[0]) / d0[0]),
             "mass_drift_b": float(abs(d[1] - d0[1]) / d0[1]),
         }
-        report[st] = e
-        print(f"  {st}: {json.dumps(e)}", flush=True)
+        report[name] = e
+        print(f"  {name}: {json.dumps(e)}", flush=True)
     # the moment-based scheme in FP32 against its own FP64 definition
     from oracle.llb import OracleLLB
     lorc = OracleLLB(p).init_droplets(cen, rad)
