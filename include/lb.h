@@ -130,9 +130,10 @@ typedef enum lb_scheme { LB_SCHEME_POPULATIONS = 0, LB_SCHEME_MOMENTS = 1 } lb_s
  *                       one with probability equal to the value's fractional
  *                       position between them (the MI355X's stochastic
  *                       conversion), driven by a deterministic 32-bit word per
- *                       store: lowbias32 (C. Wellons' integer hash) of
- *                       (site * 32 + i) * 0x9E3779B9 + step * 0x85EBCA6B,
- *                       exclusive-or the FP32 value's bits.  Runs repeat bit for
+ *                       store: (h + i * 0x9E3779B9) exclusive-or the FP32
+ *                       value's bits, with h = lowbias32 (C. Wellons' integer
+ *                       hash) of site * 0x9E3779B9 + step * 0x85EBCA6B, one
+ *                       hash per site and step.  Runs repeat bit for
  *                       bit, and in-place and two-copy streaming give the same
  *                       values.  Single lattices, nc_mode off or explicit. */
 typedef enum lb_rounding { LB_ROUND_NEAREST = 0, LB_ROUND_STOCHASTIC = 1 } lb_rounding;

@@ -630,14 +630,19 @@ __device__ __forceinline__ float total_bload(__amdgpu_buffer_rsrc_t r, uint32_t 
 }
 // Stochastic rounding of a stored total to FP16 or BF16: the hardware
 // conversion picks the upper neighbour with probability equal to the value's
-// fractional position between the two, from a 32-bit random word.  The word
-// is lowbias32 (C. Wellons' 32-bit integer hash) of the site, direction and
-// step, exclusive-or the value's bits: a deterministic stream that does not
-// depend on where the value is stored (pushed slots or the site's own).
-__device__ __forceinline__ uint32_t sround_word(uint32_t site, int i, uint32_t step, float v) {
-  uint32_t x = (site * 32u + (uint32_t)i) * 0x9E3779B9u + step * 0x85EBCA6Bu;
+// fractional position between the two, from a 32-bit random word.  Per site
+// and step one hash, lowbias32 (C. Wellons' 32-bit integer hash) of
+// site * 0x9E3779B9 + step * 0x85EBCA6B, gives a base; direction i takes
+// base + i * 0x9E3779B9 (a Weyl sequence over the directions), exclusive-or
+// the value's bits.  The stream is deterministic and does not depend on
+// where the value is stored (pushed slots or the site's own).
+__device__ __forceinline__ uint32_t sround_base(uint32_t site, uint32_t step) {
+  uint32_t x = site * 0x9E3779B9u + step * 0x85EBCA6Bu;
   x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
-  return x ^ __builtin_bit_cast(uint32_t, v);
+  return x;
+}
+__device__ __forceinline__ uint32_t sround_word(uint32_t base, int i, float v) {
+  return (base + (uint32_t)i * 0x9E3779B9u) ^ __builtin_bit_cast(uint32_t, v);
 }
 
 template <class S>
@@ -1050,6 +1055,8 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           guo = R(1) - R(0.5) * omega;
         }
         const R Fx = (R)a.fx + fnx, Fy = (R)a.fy + fny, Fz = (R)a.fz + fnz;
+        // stochastic rounding: one hash per site and step
+        [[maybe_unused]] const uint32_t sr_base = SR ? sround_base(n.site, a.step) : 0u;
         const R ux = (jx + R(0.5) * Fx) * inv_rho;
         const R uy = (jy + R(0.5) * Fy) * inv_rho;
         const R uz = (jz + R(0.5) * Fz) * inv_rho;
@@ -1092,7 +1099,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           if constexpr (TOT) {
             const auto rs = pair_rsrc<L, I>((const S*)foutA, a.N);
             if constexpr (SR)
-              __builtin_amdgcn_raw_buffer_store_b16(sround_bits<S>((float)ds, sround_word(n.site, I, a.step, (float)ds)),
+              __builtin_amdgcn_raw_buffer_store_b16(sround_bits<S>((float)ds, sround_word(sr_base, I, (float)ds)),
                                                     rs, vo, so, CPOL_NT);
             else
               total_bstore<S>(rs, vo, so, (float)ds);
