@@ -1,6 +1,7 @@
 """The 256 x 128 x 128 channel (64 droplets R = 10, near contact, walls y/z,
 body force 1e-6) over its full length of 10000 steps, through the C ABI, in
-four modes: plain FP32, FP16 and FP16C total storage, and the moment scheme.
+five modes: plain FP32, FP16 total rounded to nearest and stochastically,
+FP16C total, and the moment scheme.
 Properties that hold at this size: the near-contact force keeps all 64
 droplets apart, colour-A mass stays within the accumulated FP32 rounding of
 10000 steps, and the flow stays far below the lattice sound speed."""
@@ -18,13 +19,16 @@ if not torch.cuda.is_available():
 from paper_2405_14551_amd import lb, workloads as W  # noqa: E402
 
 
-@pytest.mark.parametrize("storage,scheme", [("f32", "populations"), ("f16t", "populations"),
-                                            ("f16ct", "populations"), ("f32", "moments")])
-def test_channel_ten_thousand_steps(storage, scheme):
-    print(f"case channel 10000 steps {storage} {scheme}", flush=True)
+@pytest.mark.parametrize("storage,scheme,rounding", [("f32", "populations", "nearest"),
+                                                     ("f16t", "populations", "nearest"),
+                                                     ("f16t", "populations", "stochastic"),
+                                                     ("f16ct", "populations", "nearest"),
+                                                     ("f32", "moments", "nearest")])
+def test_channel_ten_thousand_steps(storage, scheme, rounding):
+    print(f"case channel 10000 steps {storage} {scheme} {rounding}", flush=True)
     w = W.channel_3d()
     kw, cen, rad = W.sim_kwargs(w)
-    sim = lb.Simulation(**dict(kw, storage=storage, scheme=scheme)).init_droplets(cen, rad)
+    sim = lb.Simulation(**dict(kw, storage=storage, scheme=scheme, rounding=rounding)).init_droplets(cen, rad)
     d0 = sim.diagnostics()
     assert int(d0[6]) == 64
     sim.step(10000)
