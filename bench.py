@@ -220,12 +220,16 @@ def ensemble_bench(args):
         e1.record(ens.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    prof_steps = 20
     ens.profile_begin()
-    ens.step(20)
+    ens.step(prof_steps)
     prof = ens.profile_end()
     ens.sync()
-    col_ms = prof["ms_collide"] / max(prof["n_collide"], 1)
-    ph_ms = prof["ms_phase"] / max(prof["n_phase"], 1)
+    # collision and phase time per step: one launch each in the batched mode,
+    # one per channel in the per-channel mode
+    col_ms = prof["ms_collide"] / prof_steps
+    ph_ms = prof["ms_phase"] / prof_steps
+    launches = max(prof["n_collide"], 1) // prof_steps
     ens.close()
     q = 19
     b_step, b_col, b_phase = algorithmic_bytes(q, "f32")
@@ -259,7 +263,8 @@ def ensemble_bench(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "ensemble collision launch" if best["mode"] == "batched" else "per-channel collision launches",
-                     "bytes_per_site": b_col, "avg_launch_ms": round(col_ms, 5)},
+                     "bytes_per_site": b_col, "avg_launch_ms": round(col_ms, 5),
+                     "launches_per_step": launches},
         "step_roofline": {"bytes_per_site": b_step, "frac": round(mlups * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
                           "phase_launch_ms": round(ph_ms, 5)},
         "standalone": {"MLUPS": round(sa_mlups, 1), "steps": sa_steps,

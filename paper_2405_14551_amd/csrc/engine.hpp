@@ -39,9 +39,10 @@ struct LatticeOps {
   hipError_t (*init)(int storage, void* f, float* sc, void* phi, const FieldPtrs& fo, const double* drops,
                      const InitArgs& a, hipStream_t s);
   // batched ensemble launch: one workgroup per entry of `items` (storages
-  // ST_F64, ST_F32 and the total layouts)
-  hipError_t (*ensemble)(int storage, bool nc, bool fields, const ChannelDev* chans, const uint32_t* items,
-                         uint32_t nitems, int parity, hipStream_t s);
+  // ST_F64, ST_F32 and the total layouts); phase_only: every item is a
+  // phase tile, launched with the phase pass's own (smaller) kernel
+  hipError_t (*ensemble)(int storage, bool nc, bool fields, bool phase_only, const ChannelDev* chans,
+                         const uint32_t* items, uint32_t nitems, int parity, hipStream_t s);
   // collision pass with the learned near-contact closure (3D; storages
   // ST_F64, ST_F32 and the total layouts); NULL for 2D
   hipError_t (*collide_mlp)(int storage, bool fields, const void* fin, void* fout, float* scout, const void* phi,

@@ -64,6 +64,28 @@ union EnsembleSmem {
   PhaseTotalSmem<Tile<T::TX, T::TY, 1, L::D>> p;
 };
 
+// phase items only: the phase pass's registers and LDS, not those of the
+// collision tile it shares k_ensemble with
+template <class L, class S, class TS, bool TOT>
+__global__ void __launch_bounds__(TS::NT) k_ensemble_phase(const ChannelDev* __restrict__ chans,
+                                                           const uint32_t* __restrict__ items, int parity) {
+  using R = typename Storage<S>::real;
+  const uint32_t e = __builtin_amdgcn_readfirstlane(items[xcd_tile_index(blockIdx.x, gridDim.x)]);
+  const uint32_t c = (e >> ITEM_CH_SHIFT) & ITEM_CH_MASK;
+  const ChannelDev* C = chans + c;
+  const StepArgs a = uniform_args(C->a);
+  const TileCoord tc = tile_coord(e & ITEM_TILE_MASK, a, TS::TX, TS::TY);
+  const S* fin = uniform_ptr((const S*)C->f[parity]);
+  void* phi = uniform_ptr(C->phi);
+  if constexpr (TOT) {
+    __shared__ PhaseTotalSmem<TS> sm;
+    const float* scin = uniform_ptr((const float*)C->sc[parity]);
+    phase_total_tile<L, S, TS>(fin, scin, (float*)phi, a, tc, sm);
+  } else {
+    phase_tile<L, S>(fin, (R*)phi, a, tc, TS::TX);
+  }
+}
+
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
 __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict__ chans,
                                                      const uint32_t* __restrict__ items, int parity) {

@@ -204,9 +204,14 @@ struct Launch {
   }
 
   template <class S, bool TOT>
-  static hipError_t ensemble_s(bool nc, bool fields, const ChannelDev* chans, const uint32_t* items, uint32_t nitems,
-                               int parity, hipStream_t s) {
+  static hipError_t ensemble_s(bool nc, bool fields, bool phase_only, const ChannelDev* chans, const uint32_t* items,
+                               uint32_t nitems, int parity, hipStream_t s) {
     dim3 block(TILE_X, TILE_Y, 1), grid(nitems);
+    if (phase_only) {
+      using TS = Tile<TILE_X, TILE_Y, 1, L::D>;
+      k_ensemble_phase<L, S, TS, TOT><<<grid, block, 0, s>>>(chans, items, parity);
+      return hipGetLastError();
+    }
     if (nc) {
       if (fields) ens_kernel<S, true, true, TOT>()<<<grid, block, 0, s>>>(chans, items, parity);
       else ens_kernel<S, true, false, TOT>()<<<grid, block, 0, s>>>(chans, items, parity);
@@ -217,16 +222,16 @@ struct Launch {
     return hipGetLastError();
   }
 
-  static hipError_t ensemble(int st, bool nc, bool fields, const ChannelDev* chans, const uint32_t* items,
-                             uint32_t nitems, int parity, hipStream_t s) {
+  static hipError_t ensemble(int st, bool nc, bool fields, bool phase_only, const ChannelDev* chans,
+                             const uint32_t* items, uint32_t nitems, int parity, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
     switch (st) {
-      case ST_F64: return ensemble_s<double, false>(nc, fields, chans, items, nitems, parity, s);
-      case ST_F32: return ensemble_s<float, false>(nc, fields, chans, items, nitems, parity, s);
-      case ST_F32T: return ensemble_s<float, true>(nc, fields, chans, items, nitems, parity, s);
-      case ST_F16T: return ensemble_s<_Float16, true>(nc, fields, chans, items, nitems, parity, s);
-      case ST_BF16T: return ensemble_s<__bf16, true>(nc, fields, chans, items, nitems, parity, s);
-      case ST_F16CT: return ensemble_s<F16C, true>(nc, fields, chans, items, nitems, parity, s);
+      case ST_F64: return ensemble_s<double, false>(nc, fields, phase_only, chans, items, nitems, parity, s);
+      case ST_F32: return ensemble_s<float, false>(nc, fields, phase_only, chans, items, nitems, parity, s);
+      case ST_F32T: return ensemble_s<float, true>(nc, fields, phase_only, chans, items, nitems, parity, s);
+      case ST_F16T: return ensemble_s<_Float16, true>(nc, fields, phase_only, chans, items, nitems, parity, s);
+      case ST_BF16T: return ensemble_s<__bf16, true>(nc, fields, phase_only, chans, items, nitems, parity, s);
+      case ST_F16CT: return ensemble_s<F16C, true>(nc, fields, phase_only, chans, items, nitems, parity, s);
     }
     return hipErrorInvalidValue;
   }
