@@ -41,7 +41,16 @@ def test_billion_site_fp16_total_in_place_sampled_sites():
     say(f"case largest FP16 total lattice in place {shape} ({n / 1e9:.3f}e9 sites, {len(rad)} droplets)")
     # the library allocates its ~120 GB itself: hand back what torch holds cached
     torch.cuda.empty_cache()
-    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    free, total = torch.cuda.mem_get_info()
+    if free < 210e9:
+        pytest.skip(f"needs about 200 GB of free device memory, {free / 1e9:.0f} GB free")
+    try:
+        sim = lb.Simulation(**kw)
+    except lb.LBError as e:
+        if e.code == lb.LB_ENOMEM:
+            pytest.skip(f"device memory: {e}")
+        raise
+    sim.init_droplets(cen, rad)
     sim.step(5)
     sim.sync()
     # throughput at this size (20 steps, HIP events on the library's stream)
