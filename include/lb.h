@@ -185,7 +185,10 @@ typedef struct lb_handle lb_handle;
  *                (every channel's phase tiles, then every channel's collision
  *                tiles; one tile per workgroup).
  *                LB_ENSEMBLE_PER_CHANNEL: the single-lattice phase and
- *                collision launches, channel after channel.
+ *                collision launches, channel after channel; without the
+ *                watchdog, lb_step(n) takes each channel through all n steps
+ *                before the next channel (same results, bit for bit; the
+ *                channel's state stays in the last-level cache).
  *  z_per_block   z-planes per collision tile (>= 1)
  *  use_graph     1: replay non-field steps from a captured hipGraph of two steps
  *  ms_per_step   filled by lb_autotune with the measured time of the choice */
