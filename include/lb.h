@@ -138,6 +138,23 @@ typedef enum lb_scheme { LB_SCHEME_POPULATIONS = 0, LB_SCHEME_MOMENTS = 1 } lb_s
  *                       values.  Single lattices, nc_mode off or explicit. */
 typedef enum lb_rounding { LB_ROUND_NEAREST = 0, LB_ROUND_STOCHASTIC = 1 } lb_rounding;
 
+/* How a step forms the phase field its colour gradient needs, that of the
+ * neighbours after streaming (Sec. III.C.1).  Both give the same step up to
+ * the rounding order of the colour sums.
+ *  LB_PHASE_SCATTER  read-once step (the default): the collision pass of step
+ *                    t adds every post-collision value, as storage will return
+ *                    it, to the colour densities of the site that pulls it at
+ *                    step t+1 (x + c_i, or x itself when x + c_i is solid), so
+ *                    the populations are read once per step; values that
+ *                    leave a collision tile are summed into its halo block
+ *                    and a small combine pass finishes the phase field.  The
+ *                    first step after lb_init_droplets / lb_set_state runs the
+ *                    phase pass once.  Single lattices with the population
+ *                    scheme; ensembles and the moment scheme use the phase pass.
+ *  LB_PHASE_PASS     a separate pass pulls the populations a second time each
+ *                    step and forms the phase field before the collision pass. */
+typedef enum lb_phase_mode { LB_PHASE_SCATTER = 0, LB_PHASE_PASS = 1 } lb_phase_mode;
+
 /* field selection bits for lb_fields; dst[k] belongs to bit k */
 enum {
   LB_FIELD_RHO_A = 1u << 0,   /* real[N]                                   */
@@ -176,6 +193,7 @@ typedef struct lb_params {
                              forcing use tau = 3 nu + 1/2                                */
   int scheme;             /* lb_scheme                                                   */
   int rounding;           /* lb_rounding                                                 */
+  int phase_pass;         /* lb_phase_mode                                               */
 } lb_params;
 
 typedef struct lb_handle lb_handle;
@@ -273,11 +291,12 @@ int lb_step_count(const lb_handle* h, long long* t);
 
 /* Per-kernel timing for benchmarks.  Between lb_profile_begin and
  * lb_profile_end, lb_step records a hipEvent pair on the handle's stream
- * around every launch of the phase-field pass and of the collision pass.
- * lb_profile_end synchronises and returns the summed milliseconds and the
- * launch counts of each pass (any pointer may be NULL). */
+ * around every launch of the phase pass, of the collision pass and of the
+ * read-once step's combine pass.  lb_profile_end synchronises and returns the
+ * summed milliseconds and the launch counts of each (any pointer may be NULL). */
 int lb_profile_begin(lb_handle* h);
-int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_phase, int* n_collide);
+int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, double* ms_combine, int* n_phase,
+                   int* n_collide, int* n_combine);
 
 /* Block until all work of the handle is done. */
 int lb_sync(lb_handle* h);

@@ -52,7 +52,13 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # the heaviest translation units (D3Q27, then D3Q19 collision passes) first,
+    # so that the parallel build does not end on one long compile
+    def cost(path):
+        name = os.path.basename(path)
+        lat = 0 if "d3q27" in name else (1 if "d3q19" in name else 2)
+        return (lat, 0 if "collide" in name else 1, name)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")), key=cost)
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))

@@ -111,7 +111,24 @@ struct lb_handle {
   const LlbOps* llb = nullptr;
   void* W = nullptr;
   bool moments() const { return llb != nullptr; }
+  // phase field: two buffers.  phi_at(pcur) is what the next collision pass
+  // reads; phi_at(pfield) belongs to the fields of the last step (or of the
+  // initial state).  The read-once step's combine pass writes the other buffer.
   void* phi = nullptr;
+  void* phi2 = nullptr;
+  int pcur = 0, pfield = 0;
+  void* phi_at(int k) const { return k ? phi2 : phi; }
+  void* phi_field() const { return phi_at(pfield); }
+  // read-once step (lb_params.phase_pass == LB_PHASE_SCATTER): the collision
+  // pass scatters the next step's colour densities into ro_part (2 x N) and
+  // ro_halo (per tile-march halo blocks, marches of ro_zb planes); phi_ready
+  // says that phi_at(pcur) already holds the phase field of the next pull
+  bool ro = false;
+  bool phi_ready = false;
+  int ro_zb = 1;
+  void* ro_part = nullptr;
+  void* ro_halo = nullptr;
+  size_t ro_halo_bytes = 0;
   void* rho_a = nullptr;
   void* rho_b = nullptr;
   void* u = nullptr;
@@ -156,7 +173,7 @@ struct lb_handle {
   // each launch while profiling is on
   bool prof_on = false;
   std::vector<hipEvent_t> prof_events;
-  std::vector<int> prof_kind;  // one entry per event pair: 0 phase, 1 collide
+  std::vector<int> prof_kind;  // one entry per event pair: 0 phase, 1 collide, 2 combine
   size_t prof_used = 0;
 
   StepArgs step_args() const {
@@ -287,6 +304,8 @@ static int validate(const lb_params* p) {
     if (p->nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "the moment-based scheme takes nc_mode off or explicit");
     if (p->streaming != LB_STREAM_TWO_COPIES) return fail(LB_EINVAL, "the moment-based scheme streams with two copies");
   }
+  if (p->phase_pass != LB_PHASE_SCATTER && p->phase_pass != LB_PHASE_PASS)
+    return fail(LB_EINVAL, "unknown phase_pass %d", p->phase_pass);
   if (p->rounding != LB_ROUND_NEAREST && p->rounding != LB_ROUND_STOCHASTIC)
     return fail(LB_EINVAL, "unknown rounding %d", p->rounding);
   if (p->rounding == LB_ROUND_STOCHASTIC && p->storage != LB_F16_TOTAL && p->storage != LB_BF16_TOTAL)
@@ -309,7 +328,7 @@ int lb_destroy(lb_handle* h) {
   for (void* b : {(void*)h->d_chans, (void*)h->d_items_ph, (void*)h->d_items_co})
     if (b) (void)hipFree(b);
   for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
-  void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->W, h->phi, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
+  void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->W, h->phi, h->phi2, h->ro_part, h->ro_halo, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
                   h->diag_partial, h->diag_out, h->ccl_count, h->drops, h->mlp_theta, h->mlp_m1, h->mlp_m2,
                   h->mlp_grad, h->mlp_part, h->mlp_part_l, h->mlp_lo, h->mlp_bad, h->mlp_net};
   for (void* b : bufs)
@@ -330,8 +349,9 @@ static int dev_alloc(void** p, size_t bytes, const char* what) {
   return LB_OK;
 }
 
-static int create_single(const lb_params* p, void* hip_stream, lb_handle** out);
+static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, bool channel = false);
 static int ensemble_plan(lb_handle* h);
+static int ro_plan(lb_handle* h);
 
 int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** out) {
   if (!out) return fail(LB_EINVAL, "out is NULL");
@@ -374,7 +394,7 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
   (void)hipGetDevice(&h->device);
   for (int c = 0; c < n_channels; ++c) {
     lb_handle* sub = nullptr;
-    int rc = create_single(&p[c], hip_stream, &sub);
+    int rc = create_single(&p[c], hip_stream, &sub, true);
     if (rc) { lb_destroy(h); return rc; }
     h->chans.push_back(sub);
     h->N += sub->N;
@@ -389,7 +409,9 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
   return LB_OK;
 }
 
-static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) {
+// channel: a channel of an ensemble (stepped by the ensemble's launches, which
+// keep the phase pass)
+static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, bool channel) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
     (void)hipGetLastError();
@@ -442,6 +464,11 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
     if (!h->in_place()) ALLOC(h->sc[1], sizeof(float) * NSC * N);
   }
   ALLOC(h->phi, N * h->rsize);
+  h->ro = !channel && !h->moments() && p->phase_pass == LB_PHASE_SCATTER;
+  if (h->ro) {
+    ALLOC(h->phi2, N * h->rsize);
+    ALLOC(h->ro_part, 2 * N * h->rsize);
+  }
   ALLOC(h->rho_a, N * h->rsize);
   ALLOC(h->rho_b, N * h->rsize);
   ALLOC(h->u, 3 * N * h->rsize);
@@ -452,8 +479,54 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out) 
   ALLOC(h->diag_out, sizeof(double) * DG_COUNT);
   ALLOC(h->ccl_count, sizeof(unsigned int));
 #undef ALLOC
+  if (h->ro) {
+    int rc = ro_plan(h);
+    if (rc) { lb_destroy(h); return rc; }
+  }
   *out = h;
   g_err.clear();
+  return LB_OK;
+}
+
+// march depth of the read-once collision launch and the halo blocks it needs
+// (scatter_geom.hpp); grows the halo buffer when the depth needs more
+static int ro_plan(lb_handle* h) {
+  const lb_params& p = h->p;
+  long zb = h->z_per_block;
+  const long bxy = (long)((p.nx + TILE_X - 1) / TILE_X) * ((p.ny + TILE_Y - 1) / TILE_Y);
+  if (p.nc_mode == LB_NC_MLP) {
+    // the closure pass holds the network in LDS and runs three workgroups
+    // per CU; it measured faster with half the march depth
+    zb = zb > 1 ? zb / 2 : 1;
+  } else if (storage_bytes(p.storage) == 4 && !total_layout(p.storage)) {
+    // small grids (at most 1024 workgroups): marches twice as long, so that
+    // the grid runs in one round.  The march depth fixes which sums the
+    // combine pass adds (tile-march edges), so both streaming modes use the
+    // same rule and give the same results bit for bit.
+    if (bxy * ((p.nz + zb - 1) / zb) <= 1024 && 2 * zb <= p.nz) zb *= 2;
+  }
+  if (zb > p.nz) zb = p.nz;
+  h->ro_zb = (int)zb;
+  HaloGeom g{};
+  g.TX = TILE_X; g.TY = TILE_Y; g.zb = h->ro_zb;
+  g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+  g.dims = h->d;
+  g.tiles_x = (p.nx + TILE_X - 1) / TILE_X;
+  g.tiles_y = (p.ny + TILE_Y - 1) / TILE_Y;
+  g.marches = (p.nz + h->ro_zb - 1) / h->ro_zb;
+  const size_t need = (size_t)g.entries() * 2 * h->rsize;
+  if (need > h->ro_halo_bytes) {
+    (void)hipSetDevice(h->device);
+    if (h->ro_halo) {
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      HIP_TRY(hipFree(h->ro_halo));
+      h->ro_halo = nullptr;
+      h->ro_halo_bytes = 0;
+    }
+    int rc = dev_alloc(&h->ro_halo, need, "scatter halo blocks");
+    if (rc) return rc;
+    h->ro_halo_bytes = need;
+  }
   return LB_OK;
 }
 
@@ -501,6 +574,8 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
   a.half_rho0 = 0.5 * h->p.rho0;
   a.phi_I = h->p.phi_interface;
   // the state goes into the current copy, so an ensemble keeps one parity
+  h->pcur = h->pfield = 0;
+  h->phi_ready = false;
   if (h->moments())
     HIP_TRY(h->llb->init(h->p.storage, h->f[h->cur], h->phi, h->field_ptrs(), h->drops, a, h->stream));
   else
@@ -542,11 +617,11 @@ static int run_diag(lb_handle* h) {
   if (h->p.storage == LB_F64) {
     k_diag_partial<double><<<DIAG_BLOCKS, DIAG_THREADS, 0, h->stream>>>(
         (const double*)h->rho_a, (const double*)h->rho_b, (const double*)h->u, (const double*)h->fnc,
-        (const double*)h->phi, h->diag_partial, a);
+        (const double*)h->phi_field(), h->diag_partial, a);
   } else {
     k_diag_partial<float><<<DIAG_BLOCKS, DIAG_THREADS, 0, h->stream>>>(
         (const float*)h->rho_a, (const float*)h->rho_b, (const float*)h->u, (const float*)h->fnc,
-        (const float*)h->phi, h->diag_partial, a);
+        (const float*)h->phi_field(), h->diag_partial, a);
   }
   HIP_TRY(hipGetLastError());
   k_diag_final<<<1, DIAG_THREADS, 0, h->stream>>>(h->diag_partial, DIAG_BLOCKS, h->diag_out);
@@ -639,7 +714,7 @@ static int ensemble_launch(lb_handle* h, bool fields, int parity, hipStream_t s)
     if ((rc = prof_mark(h, 0, false))) return rc;
     if ((rc = prof_mark(h, 1, true))) return rc;
     HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[1 - parity], c->phi,
-                            c->field_ptrs(), a, s));
+                            c->field_ptrs(), a, nullptr, s));
     if ((rc = prof_mark(h, 1, false))) return rc;
   }
   return LB_OK;
@@ -700,7 +775,7 @@ static int ensemble_step(lb_handle* h, int nsteps) {
         if ((rc = prof_mark(h, 0, false))) return rc;
         if ((rc = prof_mark(h, 1, true))) return rc;
         HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[1 - parity],
-                                c->phi, c->field_ptrs(), a, h->stream));
+                                c->phi, c->field_ptrs(), a, nullptr, h->stream));
         if ((rc = prof_mark(h, 1, false))) return rc;
       }
     }
@@ -772,6 +847,61 @@ int lb_step(lb_handle* h, int nsteps) {
       HIP_TRY(h->llb->collide(st, nc, fields, h->W, h->f[1 - h->cur], h->phi, fo, a, h->stream));
       if ((r = prof_mark(h, 1, false))) return r;
       h->cur = 1 - h->cur;
+    } else if (h->ro) {
+      // read-once step: the collision pass reads phi_at(pcur) and scatters
+      // the next step's colour densities; the combine pass turns them into
+      // the next phase field in the other buffer.  The first step after
+      // lb_init_droplets / lb_set_state scatters the stored state first (the
+      // bootstrap pass, bit for bit what the collision pass that stored it
+      // would have scattered), so restarts repeat uninterrupted runs exactly.
+      StepArgs b = a;
+      b.z_per_block = h->ro_zb;
+      const ScatterOut so{h->ro_part, h->ro_halo};
+      void* phin = h->phi_at(h->pcur);
+      void* phout = h->phi_at(1 - h->pcur);
+      if (h->in_place()) {
+        void* f = h->f[0];
+        float* sc = h->sc[0];
+        const int odd = h->ip_odd;
+        if (!h->phi_ready) {
+          // an initialised or restored state is canonical (odd == 0); the
+          // phase pass covers any other case
+          if (odd) {
+            HIP_TRY(h->ip->phase_odd(st, f, sc, phin, a, h->stream));
+          } else {
+            HIP_TRY(h->ops->boot(st, f, sc, so, b, h->stream));
+            HIP_TRY(h->ops->combine(st, so, phin, b, h->stream));
+          }
+          if ((r = prof_mark(h, 0, false))) return r;
+        }
+        // (without the phase pass, the next mark reuses the open one)
+        if ((r = prof_mark(h, 1, true))) return r;
+        if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, phin, fo, b, h->mlp_net, &so, h->stream));
+        else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, phin, fo, b, &so, h->stream));
+        h->ip_odd = 1 - odd;
+      } else {
+        void* fin = h->f[h->cur];
+        void* fout = h->f[1 - h->cur];
+        if (!h->phi_ready) {
+          HIP_TRY(h->ops->boot(st, fin, h->sc[h->cur], so, b, h->stream));
+          HIP_TRY(h->ops->combine(st, so, phin, b, h->stream));
+          if ((r = prof_mark(h, 0, false))) return r;
+        }
+        if ((r = prof_mark(h, 1, true))) return r;
+        if (mlp)
+          HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], phin, fo, b, h->mlp_net, &so,
+                                      h->stream));
+        else
+          HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], phin, fo, b, &so, h->stream));
+        h->cur = 1 - h->cur;
+      }
+      if ((r = prof_mark(h, 1, false))) return r;
+      if ((r = prof_mark(h, 2, true))) return r;
+      HIP_TRY(h->ops->combine(st, so, phout, b, h->stream));
+      if ((r = prof_mark(h, 2, false))) return r;
+      if (fields) h->pfield = h->pcur;
+      h->pcur = 1 - h->pcur;
+      h->phi_ready = true;
     } else if (h->in_place()) {
       // one copy: even steps pull and push, odd steps work on the site's own slots
       void* f = h->f[0];
@@ -781,8 +911,8 @@ int lb_step(lb_handle* h, int nsteps) {
       else HIP_TRY(h->ops->phase(st, f, sc, h->phi, a, h->stream));
       if ((r = prof_mark(h, 0, false))) return r;
       if ((r = prof_mark(h, 1, true))) return r;
-      if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, h->phi, fo, a, h->mlp_net, h->stream));
-      else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, h->phi, fo, a, h->stream));
+      if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, h->phi, fo, a, h->mlp_net, nullptr, h->stream));
+      else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, h->phi, fo, a, nullptr, h->stream));
       if ((r = prof_mark(h, 1, false))) return r;
       h->ip_odd = 1 - odd;
     } else {
@@ -792,9 +922,10 @@ int lb_step(lb_handle* h, int nsteps) {
       if ((r = prof_mark(h, 0, false))) return r;
       if ((r = prof_mark(h, 1, true))) return r;
       if (mlp)
-        HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->mlp_net, h->stream));
+        HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->mlp_net, nullptr,
+                                    h->stream));
       else
-        HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->stream));
+        HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, nullptr, h->stream));
       if ((r = prof_mark(h, 1, false))) return r;
       h->cur = 1 - h->cur;
     }
@@ -820,9 +951,9 @@ static int run_labels(lb_handle* h, unsigned int* count_host) {
   c.N = h->N;
   const dim3 grid((h->N + 255) / 256), block(256);
   if (h->p.storage == LB_F64)
-    k_ccl_init<double><<<grid, block, 0, h->stream>>>((const double*)h->phi, h->labels, h->N);
+    k_ccl_init<double><<<grid, block, 0, h->stream>>>((const double*)h->phi_field(), h->labels, h->N);
   else
-    k_ccl_init<float><<<grid, block, 0, h->stream>>>((const float*)h->phi, h->labels, h->N);
+    k_ccl_init<float><<<grid, block, 0, h->stream>>>((const float*)h->phi_field(), h->labels, h->N);
   HIP_TRY(hipGetLastError());
   k_ccl_merge<<<grid, block, 0, h->stream>>>(h->labels, c);
   HIP_TRY(hipGetLastError());
@@ -851,7 +982,7 @@ int lb_fields(lb_handle* h, int channel, unsigned mask, void* const* dst, int ds
       if (!dst[b]) return fail(LB_EINVAL, "dst[%d] is NULL for a selected field", b);
   (void)hipSetDevice(h->device);
   const size_t N = h->N, r = h->rsize;
-  const void* src[LB_NUM_FIELDS] = {h->rho_a, h->rho_b, h->phi, h->u, h->fnc, h->flags, h->labels};
+  const void* src[LB_NUM_FIELDS] = {h->rho_a, h->rho_b, h->phi_field(), h->u, h->fnc, h->flags, h->labels};
   const size_t bytes[LB_NUM_FIELDS] = {N * r, N * r, N * r, 3 * N * r, 3 * N * r, N, 4 * N};
   if (mask & LB_FIELD_LABELS) {
     int rc = run_labels(h, nullptr);
@@ -994,6 +1125,7 @@ int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device)
   h->ip_odd = 0;  // the state given is canonical
   h->initialised = true;
   h->fields_valid = false;
+  h->phi_ready = false;
   return LB_OK;
 }
 
@@ -1010,12 +1142,13 @@ int lb_profile_begin(lb_handle* h) {
   return LB_OK;
 }
 
-int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_phase, int* n_collide) {
+int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, double* ms_combine, int* n_phase,
+                   int* n_collide, int* n_combine) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
   (void)hipSetDevice(h->device);
   HIP_TRY(hipStreamSynchronize(h->stream));
-  double t[2] = {0.0, 0.0};
-  int n[2] = {0, 0};
+  double t[3] = {0.0, 0.0, 0.0};
+  int n[3] = {0, 0, 0};
   for (size_t k = 0; k < h->prof_used; ++k) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, h->prof_events[2 * k], h->prof_events[2 * k + 1]));
@@ -1026,8 +1159,10 @@ int lb_profile_end(lb_handle* h, double* ms_phase, double* ms_collide, int* n_ph
   h->prof_used = 0;
   if (ms_phase) *ms_phase = t[0];
   if (ms_collide) *ms_collide = t[1];
+  if (ms_combine) *ms_combine = t[2];
   if (n_phase) *n_phase = n[0];
   if (n_collide) *n_collide = n[1];
+  if (n_combine) *n_combine = n[2];
   return LB_OK;
 }
 
@@ -1060,7 +1195,7 @@ int lb_set_tuning(lb_handle* h, const lb_tuning* t) {
   if (t->z_per_block < 1 || t->z_per_block > 4096) return fail(LB_EINVAL, "z_per_block must lie in [1, 4096]");
   if (!h->ensemble()) {
     h->z_per_block = t->z_per_block;
-    return LB_OK;
+    return h->ro ? ro_plan(h) : LB_OK;
   }
   if (t->mode != LB_ENSEMBLE_BATCHED && t->mode != LB_ENSEMBLE_PER_CHANNEL) return fail(LB_EINVAL, "unknown mode");
   if (t->use_graph != 0 && t->use_graph != 1) return fail(LB_EINVAL, "use_graph must be 0 or 1");
@@ -1362,7 +1497,7 @@ static int collect_t(lb_handle* h, float* rows, float* targets, long long cap, l
   }
   std::vector<uint32_t> c(2 * (size_t)nblk);
   std::vector<uint64_t> o(2 * (size_t)nblk);
-  const R* phi = (const R*)h->phi;
+  const R* phi = (const R*)h->phi_field();
   const R* fnc = (const R*)h->fnc;
   hipError_t e = hipSuccess;
   k_collect_count<L, R><<<nblk, 256, 0, h->stream>>>(phi, fnc, a, counts);

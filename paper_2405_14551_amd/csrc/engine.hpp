@@ -34,8 +34,10 @@ struct LatticeOps {
   // scin / scout: recolouring scalars of the total layout (unused otherwise);
   // the collision pass writes them but never reads them
   hipError_t (*phase)(int storage, const void* fin, const float* scin, void* phi, const StepArgs& a, hipStream_t s);
+  // ro: read-once step (NULL: two-pass step), see step_kernels.hpp
   hipError_t (*collide)(int storage, bool nc, bool fields, const void* fin, void* fout, float* scout,
-                        const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
+                        const void* phi, const FieldPtrs& fo, const StepArgs& a, const ScatterOut* ro,
+                        hipStream_t s);
   hipError_t (*init)(int storage, void* f, float* sc, void* phi, const FieldPtrs& fo, const double* drops,
                      const InitArgs& a, hipStream_t s);
   // batched ensemble launch: one workgroup per entry of `items` (storages
@@ -46,7 +48,16 @@ struct LatticeOps {
   // collision pass with the learned near-contact closure (3D; storages
   // ST_F64, ST_F32 and the total layouts); NULL for 2D
   hipError_t (*collide_mlp)(int storage, bool fields, const void* fin, void* fout, float* scout, const void* phi,
-                            const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s);
+                            const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, const ScatterOut* ro,
+                            hipStream_t s);
+  // read-once step: the next phase field from the scatter's outputs; a: the
+  // collision launch's arguments
+  hipError_t (*combine)(int storage, const ScatterOut& ro, void* phi, const StepArgs& a, hipStream_t s);
+  // read-once step after an initialisation or a restore: the scatter of the
+  // stored state (canonical layout; sc: the total layout's scalars) that the
+  // collision pass storing it would have made
+  hipError_t (*boot)(int storage, const void* f, const float* sc, const ScatterOut& ro, const StepArgs& a,
+                     hipStream_t s);
 };
 
 // One-copy (in-place) streaming: even and odd steps alternate, the even kind
@@ -56,10 +67,11 @@ struct InPlaceOps {
   hipError_t (*phase_odd)(int storage, const void* f, const float* scin, void* phi, const StepArgs& a,
                           hipStream_t s);
   hipError_t (*collide)(int storage, int odd, bool nc, bool fields, void* f, float* scout, const void* phi,
-                        const FieldPtrs& fo, const StepArgs& a, hipStream_t s);
+                        const FieldPtrs& fo, const StepArgs& a, const ScatterOut* ro, hipStream_t s);
   // NULL for 2D; storages as LatticeOps::collide_mlp
   hipError_t (*collide_mlp)(int storage, int odd, bool fields, void* f, float* scout, const void* phi,
-                            const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s);
+                            const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, const ScatterOut* ro,
+                            hipStream_t s);
   // planes i0 .. i1-1 of the colour block at f, in the canonical layout, from
   // the layout an even step leaves; out holds (i1 - i0) N elements
   hipError_t (*canonical)(int storage, const void* f, void* out, int i0, int i1, const StepArgs& a, hipStream_t s);

@@ -1,0 +1,4 @@
+// Collision-pass instantiations: D3Q27, ab streaming, read-once false.
+#include "collide_launch.hpp"
+
+LB_INSTANTIATE_COLLIDE(D3Q27, STREAM_AB, false)

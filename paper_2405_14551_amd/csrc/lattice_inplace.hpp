@@ -29,60 +29,28 @@ struct InPlaceLaunch {
     return hipErrorInvalidValue;
   }
 
-  template <class S, bool TOT, int STREAM>
-  static hipError_t collide_s(bool nc, bool fields, void* f, float* scout, const void* phi, const FieldPtrs& fo,
-                              const StepArgs& a, hipStream_t s) {
-    return B::template collide_s<S, TOT, STREAM>(nc, fields, f, f, scout, phi, fo, a, s);
-  }
-
-  template <int STREAM>
-  static hipError_t collide_k(int st, bool nc, bool fields, void* f, float* scout, const void* phi,
-                              const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
-    switch (st) {
-      case ST_F64: return collide_s<double, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_F32: return collide_s<float, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_F16: return collide_s<_Float16, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_BF16: return collide_s<__bf16, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_F32S: return collide_s<F32S, false, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_F32T: return collide_s<float, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_F16T: return collide_s<_Float16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_BF16T: return collide_s<__bf16, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-      case ST_F16CT: return collide_s<F16C, true, STREAM>(nc, fields, f, scout, phi, fo, a, s);
-    }
-    return hipErrorInvalidValue;
-  }
-
+  // collision pass of either kind (collide_launch.hpp, instantiated in the
+  // lattice_*_collide_*.hip files); one copy: fin == fout
   static hipError_t collide(int st, int odd, bool nc, bool fields, void* f, float* scout, const void* phi,
-                            const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
-    return odd ? collide_k<STREAM_ODD>(st, nc, fields, f, scout, phi, fo, a, s)
-               : collide_k<STREAM_EVEN>(st, nc, fields, f, scout, phi, fo, a, s);
-  }
-
-  template <int STREAM>
-  static hipError_t collide_mlp_k(int st, bool fields, void* f, float* scout, const void* phi, const FieldPtrs& fo,
-                                  const StepArgs& a, const MlpPacked* net, hipStream_t s) {
-    if constexpr (L::D == 3) {
-#define LB_MLP_CASE(ST, TYPE, TOT)                                                                     \
-  case ST:                                                                                             \
-    return fields ? B::template collide_mlp_t<TYPE, true, TOT, STREAM>(f, f, scout, phi, fo, a, net, s) \
-                  : B::template collide_mlp_t<TYPE, false, TOT, STREAM>(f, f, scout, phi, fo, a, net, s);
-      switch (st) {
-        LB_MLP_CASE(ST_F64, double, false)
-        LB_MLP_CASE(ST_F32, float, false)
-        LB_MLP_CASE(ST_F32T, float, true)
-        LB_MLP_CASE(ST_F16T, _Float16, true)
-        LB_MLP_CASE(ST_BF16T, __bf16, true)
-        LB_MLP_CASE(ST_F16CT, F16C, true)
-      }
-#undef LB_MLP_CASE
-    }
-    return hipErrorInvalidValue;
+                            const FieldPtrs& fo, const StepArgs& a, const ScatterOut* ro, hipStream_t s) {
+    if (ro)
+      return odd ? collide_impl<L, STREAM_ODD, true>(st, nc, fields, f, f, scout, phi, fo, a, ro, s)
+                 : collide_impl<L, STREAM_EVEN, true>(st, nc, fields, f, f, scout, phi, fo, a, ro, s);
+    return odd ? collide_impl<L, STREAM_ODD, false>(st, nc, fields, f, f, scout, phi, fo, a, ro, s)
+               : collide_impl<L, STREAM_EVEN, false>(st, nc, fields, f, f, scout, phi, fo, a, ro, s);
   }
 
   static hipError_t collide_mlp(int st, int odd, bool fields, void* f, float* scout, const void* phi,
-                                const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
-    return odd ? collide_mlp_k<STREAM_ODD>(st, fields, f, scout, phi, fo, a, net, s)
-               : collide_mlp_k<STREAM_EVEN>(st, fields, f, scout, phi, fo, a, net, s);
+                                const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, const ScatterOut* ro,
+                                hipStream_t s) {
+    if constexpr (L::D == 3) {
+      if (ro)
+        return odd ? collide_mlp_impl<L, STREAM_ODD, true>(st, fields, f, f, scout, phi, fo, a, net, ro, s)
+                   : collide_mlp_impl<L, STREAM_EVEN, true>(st, fields, f, f, scout, phi, fo, a, net, ro, s);
+      return odd ? collide_mlp_impl<L, STREAM_ODD, false>(st, fields, f, f, scout, phi, fo, a, net, ro, s)
+                 : collide_mlp_impl<L, STREAM_EVEN, false>(st, fields, f, f, scout, phi, fo, a, net, ro, s);
+    }
+    return hipErrorInvalidValue;
   }
 
   static hipError_t canonical(int st, const void* f, void* out, int i0, int i1, const StepArgs& a, hipStream_t s) {

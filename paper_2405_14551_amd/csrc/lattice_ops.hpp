@@ -7,6 +7,20 @@
 
 namespace lbm {
 
+// collision passes of one streaming mode and read-once setting, defined in
+// collide_launch.hpp and instantiated per lattice in their own translation
+// units (lattice_*_collide*.hip) so that the builds run in parallel.  ro: the
+// read-once scatter's outputs (NULL without); with ro, a.z_per_block is the
+// march depth the caller sized the halo blocks for and is used as given.
+template <class L, int STREAM, bool RO>
+hipError_t collide_impl(int st, bool nc, bool fields, const void* fin, void* fout, float* scout, const void* phi,
+                        const FieldPtrs& fo, const StepArgs& a, const ScatterOut* ro, hipStream_t s);
+// the same with the learned near-contact closure (3D lattices)
+template <class L, int STREAM, bool RO>
+hipError_t collide_mlp_impl(int st, bool fields, const void* fin, void* fout, float* scout, const void* phi,
+                            const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, const ScatterOut* ro,
+                            hipStream_t s);
+
 template <class L>
 struct Launch {
   // OWN / STREAM: read mode of the phase pass and streaming mode of the
@@ -57,107 +71,66 @@ struct Launch {
     return hipErrorInvalidValue;
   }
 
-  template <class S, int RAD, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool SR = false>
-  static hipError_t collide_t(const void* fin, void* fout, float* scout, const void* phi,
-                              const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
-    using R = typename Storage<S>::real;
-    using T = Tile<TILE_X, TILE_Y, RAD, L::D>;
+  // collision pass (two-copy streaming): the kernels of each read-once
+  // setting are instantiated in their own translation unit (collide_launch.hpp)
+  static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, float* scout, const void* phi,
+                            const FieldPtrs& fo, const StepArgs& a, const ScatterOut* ro, hipStream_t s) {
+    return ro ? collide_impl<L, STREAM_AB, true>(st, nc, fields, fin, fout, scout, phi, fo, a, ro, s)
+              : collide_impl<L, STREAM_AB, false>(st, nc, fields, fin, fout, scout, phi, fo, a, ro, s);
+  }
+
+  // read-once step after an initialisation or a restore: scatter the stored
+  // state (canonical layout) as the collision pass would have; a: with the
+  // read-once march depth
+  template <class S, bool TOT>
+  static hipError_t boot_t(const void* f, const float* sc, const ScatterOut& ro, const StepArgs& a, hipStream_t s) {
+    using T = Tile<TILE_X, TILE_Y, 1, L::D>;
     dim3 block(T::TX, T::TY, 1);
     StepArgs b = a;
     b.tiles_x = (a.nx + T::TX - 1) / T::TX;
     b.tiles_y = (a.ny + T::TY - 1) / T::TY;
-    int zb = a.z_per_block;
-    // two-copy 4-byte per-colour layouts: when the grid is small (at most
-    // 1024 workgroups), marches twice as long halve it so that it runs in a
-    // single round instead of a full round and a partial one.  Measured on
-    // the 256 x 128 x 128 channel: 399 -> 384 us for the FP32 pass; on grids
-    // of several thousand workgroups longer marches were 1-2% slower, and
-    // the in-place, FP64 and total-layout passes did not gain
-    if constexpr (!TOT && sizeof(S) == 4 && STREAM == STREAM_AB) {
-      const long g = (long)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb);
-      if (g <= 1024 && 2 * zb <= a.nz) zb *= 2;
-    }
-    b.z_per_block = zb;
-    dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide<L, S, T, NC, FIELDS, TOT, STREAM, SR><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b);
+    dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + a.z_per_block - 1) / a.z_per_block));
+    k_boot_scatter<L, S, T, TOT><<<grid, block, 0, s>>>((const S*)f, sc, b, ro);
     return hipGetLastError();
   }
-
-  template <class S, bool TOT, int STREAM = STREAM_AB, bool SR = false>
-  static hipError_t collide_n(bool nc, bool fields, const void* fin, void* fout, float* scout,
-                              const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
-    if (nc) {
-      return fields ? collide_t<S, 4, true, true, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s)
-                    : collide_t<S, 4, true, false, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s);
-    }
-    return fields ? collide_t<S, 1, false, true, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s)
-                  : collide_t<S, 1, false, false, TOT, STREAM, SR>(fin, fout, scout, phi, fo, a, s);
-  }
-  // the stochastic-rounding kernels exist for the FP16 and BF16 totals only
-  template <class S, bool TOT, int STREAM = STREAM_AB>
-  static hipError_t collide_s(bool nc, bool fields, const void* fin, void* fout, float* scout,
-                              const void* phi, const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
-    if constexpr (TOT && sizeof(S) == 2 && !std::is_same_v<S, F16C>) {
-      if (a.sround) return collide_n<S, TOT, STREAM, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
-    }
-    return collide_n<S, TOT, STREAM, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
-  }
-
-  static hipError_t collide(int st, bool nc, bool fields, const void* fin, void* fout, float* scout, const void* phi,
-                            const FieldPtrs& fo, const StepArgs& a, hipStream_t s) {
+  static hipError_t boot(int st, const void* f, const float* sc, const ScatterOut& ro, const StepArgs& a,
+                         hipStream_t s) {
     switch (st) {
-      case ST_F64: return collide_s<double, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_F32: return collide_s<float, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_F16: return collide_s<_Float16, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_BF16: return collide_s<__bf16, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_F32S: return collide_s<F32S, false>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_F32T: return collide_s<float, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_F16T: return collide_s<_Float16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_BF16T: return collide_s<__bf16, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
-      case ST_F16CT: return collide_s<F16C, true>(nc, fields, fin, fout, scout, phi, fo, a, s);
+      case ST_F64: return boot_t<double, false>(f, sc, ro, a, s);
+      case ST_F32: return boot_t<float, false>(f, sc, ro, a, s);
+      case ST_F16: return boot_t<_Float16, false>(f, sc, ro, a, s);
+      case ST_BF16: return boot_t<__bf16, false>(f, sc, ro, a, s);
+      case ST_F32S: return boot_t<F32S, false>(f, sc, ro, a, s);
+      case ST_F32T: return boot_t<float, true>(f, sc, ro, a, s);
+      case ST_F16T: return boot_t<_Float16, true>(f, sc, ro, a, s);
+      case ST_BF16T: return boot_t<__bf16, true>(f, sc, ro, a, s);
+      case ST_F16CT: return boot_t<F16C, true>(f, sc, ro, a, s);
     }
     return hipErrorInvalidValue;
   }
 
-  // collision pass with the learned near-contact closure (3D lattices)
-  template <class S, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
-  static hipError_t collide_mlp_t(const void* fin, void* fout, float* scout, const void* phi,
-                                  const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
-    using R = typename Storage<S>::real;
-    // radius-1 phase ring: the network needs the 3x3x3 neighbourhood; the
-    // explicit scan for sites outside its range reads the phase field from memory
-    using T = Tile<TILE_X, TILE_Y, 1, L::D>;
-    dim3 block(T::TX, T::TY, 1);
-    // half the planes per workgroup of the other passes: this pass holds the
-    // network and its row queues in LDS and runs three workgroups per CU,
-    // and measured faster with twice as many, shorter marches
-    const int zb = a.z_per_block > 1 ? a.z_per_block / 2 : 1;
+  // read-once step, second launch: the phase field of the next step from the
+  // scatter's outputs; a: the arguments the collision launch used
+  static hipError_t combine(int st, const ScatterOut& ro, void* phi, const StepArgs& a, hipStream_t s) {
     StepArgs b = a;
-    b.z_per_block = zb;
-    b.tiles_x = (a.nx + T::TX - 1) / T::TX;
-    b.tiles_y = (a.ny + T::TY - 1) / T::TY;
-    dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + zb - 1) / zb));
-    k_collide_mlp<L, S, T, FIELDS, TOT, STREAM><<<grid, block, 0, s>>>((const S*)fin, (S*)fout, (const R*)phi, scout, fo, b,
-                                                               net);
+    b.tiles_x = (a.nx + TILE_X - 1) / TILE_X;
+    b.tiles_y = (a.ny + TILE_Y - 1) / TILE_Y;
+    dim3 block(256), grid((a.N + 255) / 256);
+    if (st == ST_F64)
+      k_combine<L, double, TILE_X, TILE_Y><<<grid, block, 0, s>>>((const double*)ro.part,
+                                                                  (const RPair<double>*)ro.halo, (double*)phi, b);
+    else
+      k_combine<L, float, TILE_X, TILE_Y><<<grid, block, 0, s>>>((const float*)ro.part,
+                                                                 (const RPair<float>*)ro.halo, (float*)phi, b);
     return hipGetLastError();
   }
 
   static hipError_t collide_mlp(int st, bool fields, const void* fin, void* fout, float* scout, const void* phi,
-                                const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, hipStream_t s) {
+                                const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, const ScatterOut* ro,
+                                hipStream_t s) {
     if constexpr (L::D == 3) {
-#define LB_MLP_CASE(ST, TYPE, TOT)                                                          \
-  case ST:                                                                                  \
-    return fields ? collide_mlp_t<TYPE, true, TOT>(fin, fout, scout, phi, fo, a, net, s) \
-                  : collide_mlp_t<TYPE, false, TOT>(fin, fout, scout, phi, fo, a, net, s);
-      switch (st) {
-        LB_MLP_CASE(ST_F64, double, false)
-        LB_MLP_CASE(ST_F32, float, false)
-        LB_MLP_CASE(ST_F32T, float, true)
-        LB_MLP_CASE(ST_F16T, _Float16, true)
-        LB_MLP_CASE(ST_BF16T, __bf16, true)
-        LB_MLP_CASE(ST_F16CT, F16C, true)
-      }
-#undef LB_MLP_CASE
+      return ro ? collide_mlp_impl<L, STREAM_AB, true>(st, fields, fin, fout, scout, phi, fo, a, net, ro, s)
+                : collide_mlp_impl<L, STREAM_AB, false>(st, fields, fin, fout, scout, phi, fo, a, net, ro, s);
     }
     return hipErrorInvalidValue;
   }
@@ -237,7 +210,8 @@ struct Launch {
   }
 
   static LatticeOps ops() {
-    return LatticeOps{L::Q, L::D, &phase, &collide, &init, &ensemble, L::D == 3 ? &collide_mlp : nullptr};
+    return LatticeOps{L::Q, L::D, &phase, &collide, &init, &ensemble, L::D == 3 ? &collide_mlp : nullptr, &combine,
+                      &boot};
   }
 };
 

@@ -29,6 +29,7 @@
 
 #include "lattice.hpp"
 #include "mlp_device.hpp"
+#include "scatter_geom.hpp"
 
 namespace lbm {
 
@@ -65,24 +66,42 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
+// FP64 / FP32 keep f = d + w_i h in memory.  The shift and its inverse are
+// written without contracted multiply-adds, so that a value read back from
+// storage (bload) and the same value formed in registers right after its
+// store (rt) are bit-identical wherever the compiler inlines them.
+template <int I, class L, class R>
+__device__ __forceinline__ R shift_up(R d, R h) {
+#pragma clang fp contract(off)
+  return d + (R)L::w[I] * h;
+}
+template <int I, class L, class R>
+__device__ __forceinline__ R shift_down(R v, R h) {
+#pragma clang fp contract(off)
+  return v - (R)L::w[I] * h;
+}
+
 template <>
 struct Storage<double> {
   using real = double;
   static constexpr uint32_t ES = 8;
   template <int I, class L, int CP = 0>
   __device__ static __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, double h) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, CP)) - L::w[I] * h;
+    return shift_down<I, L>(__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, CP)), h);
   }
   template <int I, class L>
   __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double d, double h) {
     using u2 = unsigned __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, d + L::w[I] * h), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, shift_up<I, L>(d, h)), r, vo, so, CPOL_NT);
   }
   template <int I, class L>
-  __device__ static __forceinline__ double load(const double* p, double h) { return *p - L::w[I] * h; }
+  __device__ static __forceinline__ double load(const double* p, double h) { return shift_down<I, L>(*p, h); }
+  // the shifted value a load returns after bstore<I>(d)
+  template <int I, class L>
+  __device__ static __forceinline__ double rt(double d, double h) { return shift_down<I, L>(shift_up<I, L>(d, h), h); }
   template <int I, class L>
   __device__ static __forceinline__ void store(double* p, double d, double h) {
-    __builtin_nontemporal_store(d + L::w[I] * h, p);
+    __builtin_nontemporal_store(shift_up<I, L>(d, h), p);
   }
 };
 
@@ -92,17 +111,19 @@ struct Storage<float> {
   static constexpr uint32_t ES = 4;
   template <int I, class L, int CP = 0>
   __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float h) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, CP)) - (float)L::w[I] * h;
+    return shift_down<I, L>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, CP)), h);
   }
   template <int I, class L>
   __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float h) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, d + (float)L::w[I] * h), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, shift_up<I, L>(d, h)), r, vo, so, CPOL_NT);
   }
   template <int I, class L>
-  __device__ static __forceinline__ float load(const float* p, float h) { return *p - (float)L::w[I] * h; }
+  __device__ static __forceinline__ float load(const float* p, float h) { return shift_down<I, L>(*p, h); }
+  template <int I, class L>
+  __device__ static __forceinline__ float rt(float d, float h) { return shift_down<I, L>(shift_up<I, L>(d, h), h); }
   template <int I, class L>
   __device__ static __forceinline__ void store(float* p, float d, float h) {
-    __builtin_nontemporal_store(d + (float)L::w[I] * h, p);
+    __builtin_nontemporal_store(shift_up<I, L>(d, h), p);
   }
 };
 
@@ -121,6 +142,8 @@ struct Storage<_Float16> {
   template <int I, class L>
   __device__ static __forceinline__ float load(const _Float16* p, float) { return (float)(*p); }
   template <int I, class L>
+  __device__ static __forceinline__ float rt(float d, float) { return (float)(_Float16)d; }
+  template <int I, class L>
   __device__ static __forceinline__ void store(_Float16* p, float d, float) { *p = (_Float16)d; }
 };
 
@@ -138,6 +161,8 @@ struct Storage<__bf16> {
   }
   template <int I, class L>
   __device__ static __forceinline__ float load(const __bf16* p, float) { return (float)(*p); }
+  template <int I, class L>
+  __device__ static __forceinline__ float rt(float d, float) { return (float)(__bf16)d; }
   template <int I, class L>
   __device__ static __forceinline__ void store(__bf16* p, float d, float) { *p = (__bf16)d; }
 };
@@ -164,6 +189,8 @@ struct Storage<F32S> {
   }
   template <int I, class L>
   __device__ static __forceinline__ float load(const F32S* p, float) { return p->v; }
+  template <int I, class L>
+  __device__ static __forceinline__ float rt(float d, float) { return d; }
   template <int I, class L>
   __device__ static __forceinline__ void store(F32S* p, float d, float) { __builtin_nontemporal_store(d, &p->v); }
 };
@@ -665,6 +692,13 @@ __device__ __forceinline__ void total_bstore(__amdgpu_buffer_rsrc_t r, uint32_t 
   else
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r, vo, so, CPOL_NT);
 }
+// the total a load returns after total_bstore<S>(v)
+template <class S>
+__device__ __forceinline__ float total_rt(float v) {
+  if constexpr (sizeof(S) == 4) return v;
+  else if constexpr (std::is_same_v<S, F16C>) return f16c_decode(f16c_encode(v));
+  else return (float)(S)v;
+}
 template <class S>
 __device__ __forceinline__ void total_store(S* p, float v) {
   if constexpr (std::is_same_v<S, F16C>) p->bits = (uint16_t)f16c_encode(v);
@@ -834,15 +868,148 @@ __device__ __forceinline__ void phase_tile(const S* __restrict__ fin, typename S
 
 // ----------------------------------------------------------------------------
 // pass 2: gradient, flags, near contact, collision, recolouring, store
-// LDS of one collision tile: the phase-field ring
-template <class L, class S, class T, bool TOT, bool MLP = false>
-struct CollideSmem {
+//
+// Read-once step (RO).  The collision pass also forms the colour densities of
+// the next step: each post-collision value (as the next pull will read it
+// back from storage) is added to the site that pulls it, x + c_i, or to x
+// itself when x + c_i is solid (scatter_geom.hpp).  Within a tile, values
+// move one lane along x with DPP wave shifts (v_add_f32_dpp wave_shr:1 /
+// wave_shl:1), one row along y through a small LDS exchange, and one plane
+// along z through three rotating accumulators (planes z-1, z, z+1) while the
+// march advances.  Values that leave the tile (the edge lanes' x-spills, the
+// edge rows' y-exchanges, the first and last planes' z-neighbours) collect in
+// the ring threads' LDS accumulators and go to the march's halo block; the
+// tile's own sites go to the partial field P.  A combine pass then adds each
+// site's halo entries (k_combine).  Every sum is taken in a fixed order, so
+// results repeat bit for bit.
+template <class R>
+struct alignas(2 * sizeof(R)) RPair {
+  R a, b;
+};
+
+template <class T, class R>
+struct ScatterSmem {
+  static constexpr int RING = 2 * (T::TX + 2) + 2 * T::TY;
+  RPair<R> xrow[3][2][T::TY][T::TX];  // [cz+1][cy=-1: 0, +1: 1][row][lane]: row sums that change row
+  RPair<R> xsp[3][3][T::TY][2];       // [cz+1][cy+1][row][0: lane 0 along -x, 1: last lane along +x]
+  RPair<R> racc[3][RING];             // ring accumulators, plane p in slot (p + 3) % 3
+};
+template <class T, class R, bool RO>
+struct ScatterLds {};
+template <class T, class R>
+struct ScatterLds<T, R, true> {
+  ScatterSmem<T, R> scat;
+};
+
+// device pointers of the scatter: P (2 x N values, colour A then B) and the
+// halo blocks (scatter_geom.hpp), both in the collision arithmetic's type
+struct ScatterOut {
+  void* part;
+  void* halo;
+};
+
+// velocity pairs of the read-once collision in groups of the class pair
+// {(c_y, c_z), (-c_y, -c_z)}: (0,0), (0,1), (1,0), (1,1), (1,-1); a group's
+// row-changing sums are complete when its last pair has been emitted
+template <class L>
+struct RoOrder {
+  static constexpr int NP = (L::Q - 1) / 2;
+  int first[NP];
+  int gend[5];
+  constexpr RoOrder() : first(), gend() {
+    const int rep[5][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}, {1, -1}};
+    int k = 0;
+    for (int g = 0; g < 5; ++g) {
+      for (int i = 1; i < L::Q; ++i) {
+        if (L::cy[i] != rep[g][0] || L::cz[i] != rep[g][1]) continue;
+        if (g == 0 && L::cx[i] != 1) continue;
+        first[k++] = i;
+      }
+      gend[g] = k;
+    }
+  }
+};
+template <class L>
+inline constexpr RoOrder<L> ro_order{};
+
+// v of lane l - 1 (0 in lane 0) and of lane l + 1 (0 in lane 63)
+__device__ __forceinline__ float dpp_from_below(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float dpp_from_above(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double dpp_from_below(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x138, 0xf, 0xf, true);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x138, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double dpp_from_above(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x130, 0xf, 0xf, true);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x130, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// the halo geometry of a launch (tile extent TX x TY, marches of z_per_block planes)
+template <class T>
+__device__ __forceinline__ HaloGeom launch_geom(const StepArgs& a, int dims) {
+  HaloGeom g;
+  g.TX = T::TX; g.TY = T::TY; g.zb = a.z_per_block;
+  g.nx = a.nx; g.ny = a.ny; g.nz = a.nz;
+  g.wall_x = a.wall_x; g.wall_y = a.wall_y; g.wall_z = a.wall_z;
+  g.dims = dims;
+  g.tiles_x = a.tiles_x; g.tiles_y = a.tiles_y;
+  g.marches = (a.nz + a.z_per_block - 1) / a.z_per_block;
+  return g;
+}
+
+// colour A (shifted by w_i rho0/2) of a stored total T_i with the site's
+// stored recolouring scalars a, b: a (T + w rho0) + (w/|c|) c.b - w rho0/2.
+// Written without contracted multiply-adds, so that the collision pass (from
+// the value it just stored) and the bootstrap scatter (from the value read
+// back) form the same bits.
+template <class L, int I>
+__device__ __forceinline__ float colour_of_total(float T, float a, float bx, float by, float bz, float rho0, float h) {
+#pragma clang fp contract(off)
+  constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+  float v = a * T + (float)L::w[I] * (a * rho0 - h);
+  if constexpr (I != 0) {
+    float cb = 0.f;
+    if constexpr (cx != 0) cb += (float)cx * bx;
+    if constexpr (cy != 0) cb += (float)cy * by;
+    if constexpr (cz != 0) cb += (float)cz * bz;
+    v += (float)(L::w[I] * inv_norm<L>(I)) * cb;
+  }
+  return v;
+}
+
+// velocity pairs in the read-once order (ro_order), calling pair(I) for each
+// and group_end(czr) after the last pair of each group whose classes change
+// row (czr: c_z of the group's c_y = +1 class)
+template <class L, class P, class G>
+__device__ __forceinline__ void ro_pairs(P&& pair, G&& group_end) {
+  static_for<0, RoOrder<L>::NP>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int I = ro_order<L>.first[k];
+    pair(std::integral_constant<int, I>{});
+    constexpr int g = k + 1 == ro_order<L>.gend[2] ? 2
+                      : (k + 1 == ro_order<L>.gend[3] && ro_order<L>.gend[3] > ro_order<L>.gend[2] ? 3
+                      : (k + 1 == ro_order<L>.gend[4] && ro_order<L>.gend[4] > ro_order<L>.gend[3] ? 4 : -1));
+    if constexpr (g >= 2) group_end(std::integral_constant<int, g == 2 ? 0 : (g == 3 ? 1 : -1)>{});
+  });
+}
+
+// LDS of one collision tile: the phase-field ring (and the scatter's exchange)
+template <class L, class S, class T, bool TOT, bool MLP = false, bool RO = false>
+struct CollideSmem : ScatterLds<T, typename Storage<S>::real, RO> {
   using R = typename Storage<S>::real;
   R ring[T::NPL * T::PL];
 };
 // with the learned closure: the packed network and one row queue per wave
-template <class L, class S, class T, bool TOT>
-struct CollideSmem<L, S, T, TOT, true> : CollideSmem<L, S, T, TOT, false> {
+template <class L, class S, class T, bool TOT, bool RO>
+struct CollideSmem<L, S, T, TOT, true, RO> : CollideSmem<L, S, T, TOT, false, RO> {
   MlpPacked net;
   MlpQueue queue[T::NT / 64];
 };
@@ -852,27 +1019,57 @@ struct CollideSmem<L, S, T, TOT, true> : CollideSmem<L, S, T, TOT, false> {
 // interface sites whose stencil lies in its training range, the explicit scan
 // at the others; the closure runs on whole waves, so in that mode every lane
 // takes part (lanes outside the lattice compute on a clamped site and store
-// nothing).  STREAM selects two-copy or in-place streaming (fin == fout for
-// the in-place kinds).
+// nothing).  RO: the read-once scatter, which also needs every lane (the DPP
+// shifts read neighbouring lanes).  STREAM selects two-copy or in-place
+// streaming (fin == fout for the in-place kinds).  tile_id: the tile's index
+// in the launch (RO: its halo block).  BOOT (with RO): no collision; the
+// stored state at fin (canonical layout, total layout's scalars at scout) is
+// scattered exactly as the collision pass that stored it would have
+// scattered it, which starts the read-once step after an initialisation or a
+// restore with the same phase field, bit for bit.
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false, int STREAM = STREAM_AB,
-          bool SR = false>
+          bool SR = false, bool RO = false, bool BOOT = false>
 __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __restrict__ fout,
                                              const typename Storage<S>::real* __restrict__ phi,
                                              float* __restrict__ scout,
                                              const FieldPtrs& fo, const StepArgs& a, const TileCoord& tc,
-                                             CollideSmem<L, S, T, TOT, MLP>& sm,
-                                             const MlpPacked* __restrict__ net = nullptr) {
+                                             CollideSmem<L, S, T, TOT, MLP, RO>& sm,
+                                             const MlpPacked* __restrict__ net = nullptr, uint32_t tile_id = 0,
+                                             ScatterOut sout = ScatterOut{nullptr, nullptr}) {
   static_assert(!MLP || (NC && L::D == 3), "the learned closure replaces the 3D near-contact scan");
+  static_assert(!RO || (T::TX == 64), "the read-once scatter shifts along one 64-lane wave per row");
+  static_assert(!BOOT || RO, "the bootstrap scatter is part of the read-once step");
   using R = typename Storage<S>::real;
+  constexpr bool ALL = MLP || RO;   // every lane runs the collision
   R* ring = sm.ring;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + T::TX * ty;
   const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0, z1 = tc.z1;
   const int x = x0 + tx, y = y0 + ty;
   const bool valid_xy = x < a.nx && y < a.ny;
+  // tile widths (wave-uniform) and, for the ring threads, their ring position
+  const int wx = min(T::TX, a.nx - x0), wy = min(T::TY, a.ny - y0);
+  [[maybe_unused]] int rhx = 0, rhy = 0;
+  [[maybe_unused]] bool ring_ok = false;
+  [[maybe_unused]] HaloGeom geo;
+  [[maybe_unused]] RPair<R>* halo_blk = nullptr;
+  [[maybe_unused]] R* part = nullptr;
+  [[maybe_unused]] R accA[3] = {0, 0, 0}, accB[3] = {0, 0, 0};
+  if constexpr (RO) {
+    geo = launch_geom<T>(a, L::D);
+    halo_blk = (RPair<R>*)sout.halo + (uint64_t)tile_id * geo.stride();
+    part = (R*)sout.part;
+    constexpr int RING = ScatterSmem<T, R>::RING;
+    ring_ok = tid < RING && geo.ring_pos(tid, wx, wy, rhx, rhy);
+    if (tid < RING)
+      for (int c = 0; c < 3; ++c) sm.scat.racc[c][tid] = RPair<R>{0, 0};
+    // spills of classes without an x-moving velocity (D3Q19 corners) stay zero
+    if (tid < 3 * 3 * T::TY * 2) (&sm.scat.xsp[0][0][0][0])[tid] = RPair<R>{0, 0};
+  }
 
   // stage planes z0 - RZ .. z0 + RZ; plane zz lives in slot plane_slot(zz)
-  for (int dz = -T::RZ; dz <= T::RZ; ++dz)
-    load_plane<T>(ring, plane_slot(z0 + dz, T::NPL), z0 + dz, phi, x0, y0, a, tid);
+  if constexpr (!BOOT)
+    for (int dz = -T::RZ; dz <= T::RZ; ++dz)
+      load_plane<T>(ring, plane_slot(z0 + dz, T::NPL), z0 + dz, phi, x0, y0, a, tid);
   if constexpr (MLP) mlp_stage(sm.net, net, tid, T::NT);
   __syncthreads();
 
@@ -899,10 +1096,83 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   constexpr int LCP = STREAM == STREAM_EVEN ? LB_INPLACE_LOAD_CPOL_EVEN
                                             : (STREAM == STREAM_ODD ? LB_INPLACE_LOAD_CPOL_ODD : 0);
 
+  // RO: the ring threads' densities of plane zd go to the halo block
+  [[maybe_unused]] auto ring_emit = [&](int zd, bool cap_lo_, bool cap_hi_) {
+    if constexpr (RO) {
+      if (tid < ScatterSmem<T, R>::RING) {
+        RPair<R>& acc = sm.scat.racc[(zd + 3) % 3][tid];
+        if (ring_ok) {
+          uint32_t e;
+          if (cap_lo_) e = geo.cap_lo(rhx, rhy);
+          else if (cap_hi_) e = geo.cap_hi(rhx, rhy);
+          else e = geo.side(zd - z0, tid);
+          halo_blk[e] = acc;
+        }
+        acc = RPair<R>{0, 0};
+      }
+    }
+  };
+
+  // RO: sums of the values that change row (cy = +1 and cy = -1 classes of
+  // the current group), after their move along x
+  [[maybe_unused]] R clsPA = 0, clsPB = 0, clsNA = 0, clsNB = 0;
+  // RO: send the stored values (cA, cB) of direction I of the site of n to
+  // the site that pulls them next step
+  [[maybe_unused]] auto route = [&](auto ic, R cA, R cB, const Nbr& n, bool open, bool live) {
+    if constexpr (RO) {
+      constexpr int I = decltype(ic)::value;
+      constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
+      cA = live ? cA : R(0);
+      cB = live ? cB : R(0);
+      if constexpr (I != 0) {
+        if (!open) {
+          // halfway bounce-back: a value sent into a wall returns to the site
+          bool solid = false;
+          if constexpr (cx != 0) solid = solid || n.solid_x[1 + cx];
+          if constexpr (cy != 0) solid = solid || n.solid_y[1 + cy];
+          if constexpr (cz != 0) solid = solid || n.solid_z[1 + cz];
+          accA[1] += solid ? cA : R(0);
+          accB[1] += solid ? cB : R(0);
+          cA = solid ? R(0) : cA;
+          cB = solid ? R(0) : cB;
+        }
+      }
+      R vA = cA, vB = cB;
+      if constexpr (cx == 1) {
+        vA = dpp_from_below(cA);
+        vB = dpp_from_below(cB);
+        if (tx == wx - 1) sm.scat.xsp[cz + 1][cy + 1][ty][1] = RPair<R>{cA, cB};
+      } else if constexpr (cx == -1) {
+        vA = dpp_from_above(cA);
+        vB = dpp_from_above(cB);
+        if (tx == 0) sm.scat.xsp[cz + 1][cy + 1][ty][0] = RPair<R>{cA, cB};
+      }
+      if constexpr (cy == 0) {
+        accA[cz + 1] += vA;
+        accB[cz + 1] += vB;
+      } else if constexpr (cy == 1) {
+        clsPA += vA;
+        clsPB += vB;
+      } else {
+        clsNA += vA;
+        clsNB += vB;
+      }
+    }
+  };
+  // RO: a group's row-changing sums are complete: to LDS
+  [[maybe_unused]] auto flush = [&](auto czc) {
+    if constexpr (RO) {
+      constexpr int czr = decltype(czc)::value;
+      sm.scat.xrow[czr + 1][1][ty][tx] = RPair<R>{clsPA, clsPB};
+      sm.scat.xrow[-czr + 1][0][ty][tx] = RPair<R>{clsNA, clsNB};
+      clsPA = clsPB = clsNA = clsNB = R(0);
+    }
+  };
+
   for (int z = z0; z < z1; ++z) {
     // prefetch the plane the next iteration needs into registers; it goes to
     // the spare ring slot at the end of this iteration (one barrier per plane)
-    const bool more = T::RZ && z + 1 < z1;
+    const bool more = !BOOT && T::RZ && z + 1 < z1;
     R nxt[T::NPER];
     if (more) fetch_plane<T>(nxt, z + 1 + T::RZ, phi, x0, y0, a, tid);
     const int zc = plane_slot(z, T::NPL);
@@ -915,10 +1185,41 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
     asm volatile("" : "+s"(finA), "+s"(foutA));
     const S* finB = finA + (TOT ? 0 : a.QN);
     S* foutB = foutA + (TOT ? 0 : a.QN);
-    if (MLP || valid_xy) {
+    if constexpr (BOOT) {
+      // ---- bootstrap: the site's own stored values (canonical layout), in
+      // the collision pass's emit order
+      const Nbr n = make_nbr(min(x, a.nx - 1), min(y, a.ny - 1), z, a);
+      const bool open = wave_open(n);
+      const bool live = valid_xy;
+      const R hshift = (R)a.half_rho0, rho0 = R(2) * hshift;
+      [[maybe_unused]] float sc_a = 0.f, sc_bx = 0.f, sc_by = 0.f, sc_bz = 0.f;
+      if constexpr (TOT) {
+        sc_a = scout[n.site];
+        sc_bx = scout[a.N + n.site];
+        sc_by = scout[2 * (size_t)a.N + n.site];
+        sc_bz = scout[3 * (size_t)a.N + n.site];
+      }
+      auto own = [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const uint32_t vo = own_reversed_index<L, L::opp[I]>(n, a.N) * (uint32_t)sizeof(S);
+        if constexpr (TOT) {
+          const float tv = total_bload<S>(pair_rsrc<L, I>(finA, a.N), vo);
+          const R cA = colour_of_total<L, I>(tv, sc_a, sc_bx, sc_by, sc_bz, rho0, hshift);
+          route(ic, cA, (R)tv - cA, n, open, live);
+        } else {
+          route(ic, Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finA, a.N), vo, hshift),
+                Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), vo, hshift), n, open, live);
+        }
+      };
+      own(std::integral_constant<int, 0>{});
+      ro_pairs<L>([&](auto ic) {
+        own(ic);
+        own(std::integral_constant<int, L::opp[decltype(ic)::value]>{});
+      }, flush);
+    } else if (ALL || valid_xy) {
       // ---- issue the pull first so that its latency overlaps the stencil
       // work below: both colours (shifted by w_i rho0/2 each), or the total
-      const Nbr n = make_nbr(MLP ? min(x, a.nx - 1) : x, MLP ? min(y, a.ny - 1) : y, z, a);
+      const Nbr n = make_nbr(ALL ? min(x, a.nx - 1) : x, ALL ? min(y, a.ny - 1) : y, z, a);
       R va[L::Q], vb[TOT ? 1 : L::Q];
       // rows away from the walls (most of them) skip the bounce-back selects
       auto pull = [&](auto open) {
@@ -938,7 +1239,8 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       // (the odd in-place kind reads its own slots either way; it keeps the
       // branch so that all streaming modes compile to the same code shape
       // around the arithmetic, and the compiler fuses it alike)
-      if (wave_open(n)) pull(std::true_type{});
+      const bool open = wave_open(n);
+      if (open) pull(std::true_type{});
       else pull(std::false_type{});
       const int p0 = zc * T::PL;
       constexpr int dz1 = T::RZ ? 1 : 0;   // 2D: a single plane
@@ -995,7 +1297,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         }
       }
       if constexpr (NC) {
-        if (flag && has_g && (!MLP || (valid_xy && !use_net))) {
+        if (flag && has_g && (!ALL || valid_xy) && (!MLP || !use_net)) {
           int hit = 0;
           if constexpr (T::RAD >= 4) {
             hit = nc_scan_ring<L, T, R>(ring, c0, zc, x, y, z, gx, gy, gz, gg, phiI, a);
@@ -1013,8 +1315,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       }
       // lanes outside the lattice (closure mode only) store nothing: one
       // branch around the whole collision keeps it a single block of
-      // arithmetic, as in the other modes
-      if (!MLP || valid_xy) {
+      // arithmetic, as in the other modes.  RO: every lane collides (on a
+      // clamped site) and only lanes inside the lattice store.
+      const bool live = valid_xy;
+      if (!MLP || RO || valid_xy) {
         // ---- moments of the pulled populations
         R d[L::Q];  // d_i = f_i - w_i rho0, total over both colours
         R sa = 0, sb = 0;
@@ -1069,6 +1373,11 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         const R fa_frac = ra * inv_rho;                  // rho_A / rho
         const R coef = beta * ra * rb * inv_rho;         // beta rho_A rho_B / rho
         const R half_phi_rho0 = (sa - sb) * inv_rho * hshift;  // rho0 phi / 2
+        // total layout: the recolouring scalars as stored (FP32)
+        const R bs = coef * inv_gn;
+        [[maybe_unused]] const R sc_a = (R)(float)fa_frac;
+        [[maybe_unused]] const R sc_bx = (R)(float)(bs * gx), sc_by = (R)(float)(bs * gy),
+                                 sc_bz = (R)(float)(bs * gz);
         // ---- collide and recolour.  With cu = c.u, cF = c.F, cg = c.g, the
         // shifted post-collision value of direction i is
         //   f*_i - w rho0 = (1 - omega) d_i + w_i t_i - A |g| B_i,
@@ -1098,25 +1407,37 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           }
           if constexpr (TOT) {
             const auto rs = pair_rsrc<L, I>((const S*)foutA, a.N);
-            if constexpr (SR)
-              __builtin_amdgcn_raw_buffer_store_b16(sround_bits<S>((float)ds, sround_word(sr_base, I, (float)ds)),
-                                                    rs, vo, so, CPOL_NT);
-            else
-              total_bstore<S>(rs, vo, so, (float)ds);
+            [[maybe_unused]] float tv;  // the stored total as a load returns it
+            if constexpr (SR) {
+              const unsigned short bits = sround_bits<S>((float)ds, sround_word(sr_base, I, (float)ds));
+              if (!RO || live) __builtin_amdgcn_raw_buffer_store_b16(bits, rs, vo, so, CPOL_NT);
+              if constexpr (RO) tv = (float)__builtin_bit_cast(S, bits);
+            } else {
+              if (!RO || live) total_bstore<S>(rs, vo, so, (float)ds);
+              if constexpr (RO) tv = total_rt<S>((float)ds);
+            }
+            if constexpr (RO) {
+              // the colours of the stored total, rebuilt from it and this
+              // site's stored scalars as the next step's pull rebuilds them
+              const R cA = colour_of_total<L, I>(tv, sc_a, sc_bx, sc_by, sc_bz, rho0, hshift);
+              route(ic, cA, (R)tv - cA, n, open, live);
+            }
           } else {
             const R wi = (R)L::w[I];
             const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
             const R db = ds - da;
-            Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
-            Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
+            if (!RO || live) {
+              Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
+              Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
+            }
+            if constexpr (RO)
+              route(ic, Storage<S>::template rt<I, L>(da, hshift), Storage<S>::template rt<I, L>(db, hshift), n,
+                    open, live);
           }
         };
-        {
-          const R w0 = (R)L::w[0];
-          emit(std::integral_constant<int, 0>{}, one_m_om * d[0] + w0 * K0 - Agn * (R)B_coef<L>(0), R(0));
-        }
-        static_for<0, (L::Q - 1) / 2>([&](auto pc) {
-          constexpr int I = pair_first<L>(decltype(pc)::value);
+        // one velocity pair: shared dot products, even / odd split
+        auto emit_pair = [&](auto ic) {
+          constexpr int I = decltype(ic)::value;
           constexpr int J = L::opp[I];
           constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
           const R wi = (R)L::w[I];
@@ -1132,16 +1453,28 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           const R rodd = Kr * (R)inv_norm<L>(I) * cg;
           emit(std::integral_constant<int, I>{}, ds_i, rodd);
           emit(std::integral_constant<int, J>{}, ds_j, -rodd);
-        });
-        if (TOT) {
+        };
+        {
+          const R w0 = (R)L::w[0];
+          emit(std::integral_constant<int, 0>{}, one_m_om * d[0] + w0 * K0 - Agn * (R)B_coef<L>(0), R(0));
+        }
+        if constexpr (RO) {
+          // pairs grouped by class pair; a group's row-changing sums go to LDS
+          // as soon as they are complete
+          ro_pairs<L>(emit_pair, flush);
+        } else {
+          static_for<0, (L::Q - 1) / 2>([&](auto pc) {
+            emit_pair(std::integral_constant<int, pair_first<L>(decltype(pc)::value)>{});
+          });
+        }
+        if (TOT && (!RO || live)) {
           // recolouring scalars of this site for the next pull
-          const R bs = coef * inv_gn;
           __builtin_nontemporal_store((float)fa_frac, scout + n.site);
           __builtin_nontemporal_store((float)(bs * gx), scout + a.N + n.site);
           __builtin_nontemporal_store((float)(bs * gy), scout + 2 * (size_t)a.N + n.site);
           __builtin_nontemporal_store((float)(bs * gz), scout + 3 * (size_t)a.N + n.site);
         }
-        if (FIELDS) {
+        if (FIELDS && (!RO || live)) {
           R* rA = (R*)fo.rho_a;
           R* rB = (R*)fo.rho_b;
           R* U = (R*)fo.u;
@@ -1157,32 +1490,153 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         }
       }
     }
+    if constexpr (RO) {
+      // ---- scatter: the row-changing sums and x-spills of this plane are in LDS
+      __syncthreads();
+      constexpr int C0 = L::D == 3 ? 0 : 1, C1 = L::D == 3 ? 2 : 1;
+#pragma unroll
+      for (int c = C0; c <= C1; ++c) {
+        if (ty >= 1 && ty < wy) {
+          const RPair<R> v = sm.scat.xrow[c][1][ty - 1][tx];
+          accA[c] += v.a; accB[c] += v.b;
+        }
+        if (ty + 1 < wy) {
+          const RPair<R> v = sm.scat.xrow[c][0][ty + 1][tx];
+          accA[c] += v.a; accB[c] += v.b;
+        }
+      }
+      if (ring_ok) {
+#pragma unroll
+        for (int c = C0; c <= C1; ++c) {
+          RPair<R> v{0, 0};
+          if (rhy == 0 || rhy == wy + 1) {
+            // rows just outside the tile: the edge row's row-changing sums
+            const int cyi = rhy == 0 ? 0 : 1, ly = rhy == 0 ? 0 : wy - 1;
+            if (rhx == 0) v = sm.scat.xsp[c][cyi == 0 ? 0 : 2][ly][0];
+            else if (rhx == wx + 1) v = sm.scat.xsp[c][cyi == 0 ? 0 : 2][ly][1];
+            else v = sm.scat.xrow[c][cyi][ly][rhx - 1];
+          } else {
+            // columns just outside the tile: x-spills of up to three rows
+            const int side = rhx == 0 ? 0 : 1;
+#pragma unroll
+            for (int cy = -1; cy <= 1; ++cy) {
+              const int ly = rhy - 1 - cy;
+              if (ly >= 0 && ly < wy) {
+                const RPair<R> s = sm.scat.xsp[c][cy + 1][ly][side];
+                v.a += s.a; v.b += s.b;
+              }
+            }
+          }
+          RPair<R>& acc = sm.scat.racc[(z + c - 1 + 3) % 3][tid];
+          acc.a += v.a; acc.b += v.b;
+        }
+      }
+      // plane z-1 is complete: the tile's own sites to P (the first march
+      // plane's lower neighbour plane to the halo block), then rotate
+      if constexpr (L::D == 3) {
+        if (z == z0) {
+          if (valid_xy) halo_blk[geo.cap_lo(tx + 1, ty + 1)] = RPair<R>{accA[0], accB[0]};
+          ring_emit(z - 1, true, false);
+        } else {
+          if (valid_xy) {
+            const uint32_t s = (uint32_t)x + (uint32_t)a.nx * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)(z - 1));
+            __builtin_nontemporal_store(accA[0], part + s);
+            __builtin_nontemporal_store(accB[0], part + a.N + s);
+          }
+          ring_emit(z - 1, false, false);
+        }
+        accA[0] = accA[1]; accA[1] = accA[2]; accA[2] = R(0);
+        accB[0] = accB[1]; accB[1] = accB[2]; accB[2] = R(0);
+      }
+    }
     if (more) commit_plane<T>(ring, plane_slot(z + 1 + T::RZ, T::NPL), nxt, tid);
     __syncthreads();
+  }
+  if constexpr (RO) {
+    // the march's last plane and the plane above it
+    const int zl = z1 - 1;
+    const int cur = L::D == 3 ? 0 : 1;  // 2D keeps its single plane in slot 1
+    if (valid_xy) {
+      const uint32_t s = (uint32_t)x + (uint32_t)a.nx * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)zl);
+      __builtin_nontemporal_store(accA[cur], part + s);
+      __builtin_nontemporal_store(accB[cur], part + a.N + s);
+    }
+    ring_emit(zl, false, false);
+    if constexpr (L::D == 3) {
+      if (valid_xy) halo_blk[geo.cap_hi(tx + 1, ty + 1)] = RPair<R>{accA[1], accB[1]};
+      ring_emit(z1, false, true);
+    }
   }
 }
 
 // SR: stochastic rounding of the stored 16-bit totals (FP16 / BF16 total layouts)
-template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool SR = false>
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool SR = false,
+          bool RO = false>
 __global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::real* __restrict__ phi,
                                                     float* __restrict__ scout,
-                                                    FieldPtrs fo, StepArgs a) {
+                                                    FieldPtrs fo, StepArgs a, ScatterOut sout) {
   static_assert(!SR || (TOT && sizeof(S) == 2 && !std::is_same_v<S, F16C>), "stochastic rounding: FP16/BF16 totals");
-  __shared__ CollideSmem<L, S, T, TOT> sm;
-  const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
-  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM, SR>(fin, fout, phi, scout, fo, a, tc, sm);
+  __shared__ CollideSmem<L, S, T, TOT, false, RO> sm;
+  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
+  const TileCoord tc = tile_coord(t, a, T::TX, T::TY);
+  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM, SR, RO>(fin, fout, phi, scout, fo, a, tc, sm, nullptr, t, sout);
 }
 
 // collision pass with the learned near-contact closure
-template <class L, class S, class T, bool FIELDS, bool TOT, int STREAM = STREAM_AB>
+template <class L, class S, class T, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool RO = false>
 __global__ void __launch_bounds__(T::NT, 3) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
                                                            const typename Storage<S>::real* __restrict__ phi,
                                                            float* __restrict__ scout,
-                                                        FieldPtrs fo, StepArgs a, const MlpPacked* __restrict__ net) {
-  __shared__ CollideSmem<L, S, T, TOT, true> sm;
-  const TileCoord tc = tile_coord(xcd_tile_index(blockIdx.x, gridDim.x), a, T::TX, T::TY);
-  collide_tile<L, S, T, true, FIELDS, TOT, true, STREAM>(fin, fout, phi, scout, fo, a, tc, sm, net);
+                                                        FieldPtrs fo, StepArgs a, const MlpPacked* __restrict__ net,
+                                                        ScatterOut sout) {
+  __shared__ CollideSmem<L, S, T, TOT, true, RO> sm;
+  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
+  const TileCoord tc = tile_coord(t, a, T::TX, T::TY);
+  collide_tile<L, S, T, true, FIELDS, TOT, true, STREAM, false, RO>(fin, fout, phi, scout, fo, a, tc, sm, net, t, sout);
+}
+
+// Bootstrap of the read-once step: the scatter of a stored state (canonical
+// layout; scalars of the total layout at sc), as the collision pass that
+// stored it would have scattered it
+template <class L, class S, class T, bool TOT>
+__global__ void __launch_bounds__(T::NT) k_boot_scatter(const S* __restrict__ f, const float* __restrict__ sc,
+                                                        StepArgs a, ScatterOut sout) {
+  __shared__ CollideSmem<L, S, T, TOT, false, true> sm;
+  const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
+  const TileCoord tc = tile_coord(t, a, T::TX, T::TY);
+  collide_tile<L, S, T, false, false, TOT, false, STREAM_AB, false, true, true>(
+      f, nullptr, nullptr, const_cast<float*>(sc), FieldPtrs{}, a, tc, sm, nullptr, t, sout);
+}
+
+// Read-once step, second launch: the next step's phase field from the
+// partial densities P and the halo entries the neighbouring tile-marches hold
+// for each site (scatter_geom.hpp), in a fixed order.  TX, TY: the collision
+// tile; a: the collision launch's arguments (tiling and march depth).
+template <class L, class R, int TX, int TY>
+__global__ void __launch_bounds__(256) k_combine(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
+                                                 R* __restrict__ phi, StepArgs a) {
+  const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+  if (s >= a.N) return;
+  const uint32_t nxy = (uint32_t)a.nx * (uint32_t)a.ny;
+  const int z = s / nxy;
+  const uint32_t r = s - (uint32_t)z * nxy;
+  const int y = r / (uint32_t)a.nx, x = r - (uint32_t)y * a.nx;
+  HaloGeom g;
+  g.TX = TX; g.TY = TY; g.zb = a.z_per_block;
+  g.nx = a.nx; g.ny = a.ny; g.nz = a.nz;
+  g.wall_x = a.wall_x; g.wall_y = a.wall_y; g.wall_z = a.wall_z;
+  g.dims = L::D;
+  g.tiles_x = a.tiles_x; g.tiles_y = a.tiles_y;
+  g.marches = (a.nz + a.z_per_block - 1) / a.z_per_block;
+  R sa = part[s], sb = part[a.N + s];
+  halo_sources(g, x, y, z, [&](uint64_t e) {
+    const RPair<R> v = halo[e];
+    sa += v.a;
+    sb += v.b;
+  });
+  const R h = (R)a.half_rho0;
+  phi[s] = (sa - sb) / (R(2) * h + (sa + sb));
 }
 
 // The canonical layout (slot (i, x) = f_i(x)) of one colour block from the

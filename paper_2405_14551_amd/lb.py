@@ -23,6 +23,7 @@ NC_MODE = {"off": 0, "explicit": 1, "mlp": 2}
 STREAMING = {"two_copies": 0, "in_place": 1}
 SCHEME = {"populations": 0, "moments": 1}
 ROUNDING = {"nearest": 0, "stochastic": 1}
+PHASE_PASS = {"scatter": 0, "pass": 1}
 N_MOMENTS = 15
 MLP_PARAMS = 6339
 MLP_ROW = 32
@@ -61,6 +62,7 @@ class LbParams(ctypes.Structure):
         ("tau_b", ctypes.c_double),
         ("scheme", ctypes.c_int),
         ("rounding", ctypes.c_int),
+        ("phase_pass", ctypes.c_int),
     ]
 
 
@@ -102,7 +104,7 @@ def lib():
     L.lb_destroy.argtypes = [vp]
     L.lb_lattice_table.argtypes = [i, P(i), P(i), P(d), P(i), P(d)]
     L.lb_profile_begin.argtypes = [vp]
-    L.lb_profile_end.argtypes = [vp, P(d), P(d), P(i), P(i)]
+    L.lb_profile_end.argtypes = [vp, P(d), P(d), P(d), P(i), P(i), P(i)]
     L.lb_channel_count.argtypes = [vp, P(i)]
     L.lb_get_tuning.argtypes = [vp, P(LbTuning)]
     L.lb_set_tuning.argtypes = [vp, P(LbTuning)]
@@ -156,7 +158,7 @@ def lattice_table(name):
 def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), walls=(0, 0, 0),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
                 nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0,
-                streaming="two_copies", tau_b=0.0, scheme="populations", rounding="nearest"):
+                streaming="two_copies", tau_b=0.0, scheme="populations", rounding="nearest", phase="scatter"):
     p = LbParams()
     lib().lb_params_default(ctypes.byref(p))
     p.lattice = LATTICE[lattice]
@@ -175,6 +177,7 @@ def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), wa
     p.tau_b = float(tau_b)
     p.scheme = SCHEME[scheme]
     p.rounding = ROUNDING[rounding]
+    p.phase_pass = PHASE_PASS[phase]
     return p
 
 
@@ -242,16 +245,26 @@ class Simulation:
     def sync(self):
         check(lib().lb_sync(self.h))
 
+    def set_z_per_block(self, zb):
+        """Planes per collision march (lb_set_tuning on a single lattice)."""
+        t = LbTuning()
+        check(lib().lb_get_tuning(self.h, ctypes.byref(t)))
+        t.z_per_block = int(zb)
+        check(lib().lb_set_tuning(self.h, ctypes.byref(t)))
+        return self
+
     def profile_begin(self):
         check(lib().lb_profile_begin(self.h))
 
     def profile_end(self):
-        """Returns dict(ms_phase, ms_collide, n_phase, n_collide) summed over launches."""
-        a, b = ctypes.c_double(), ctypes.c_double()
-        na, nb = ctypes.c_int(), ctypes.c_int()
-        check(lib().lb_profile_end(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(na),
-                                   ctypes.byref(nb)))
-        return dict(ms_phase=a.value, ms_collide=b.value, n_phase=na.value, n_collide=nb.value)
+        """Returns dict(ms_phase, ms_collide, ms_combine, n_phase, n_collide, n_combine)
+        summed over launches (combine: the read-once step's second launch)."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        na, nb, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().lb_profile_end(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(na),
+                                   ctypes.byref(nb), ctypes.byref(nc)))
+        return dict(ms_phase=a.value, ms_collide=b.value, ms_combine=c.value, n_phase=na.value,
+                    n_collide=nb.value, n_combine=nc.value)
 
     @property
     def t(self):
@@ -587,8 +600,9 @@ class Ensemble:
         check(lib().lb_profile_begin(self.h))
 
     def profile_end(self):
-        a, b = ctypes.c_double(), ctypes.c_double()
-        na, nb = ctypes.c_int(), ctypes.c_int()
-        check(lib().lb_profile_end(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(na),
-                                   ctypes.byref(nb)))
-        return dict(ms_phase=a.value, ms_collide=b.value, n_phase=na.value, n_collide=nb.value)
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        na, nb, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().lb_profile_end(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(na),
+                                   ctypes.byref(nb), ctypes.byref(nc)))
+        return dict(ms_phase=a.value, ms_collide=b.value, ms_combine=c.value, n_phase=na.value,
+                    n_collide=nb.value, n_combine=nc.value)
