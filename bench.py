@@ -1,15 +1,21 @@
 """Benchmark of the two-component colour-gradient LB step on one MI355X.
 
-Default workload: the D3Q27 channel (256x128x128, no-slip y/z walls, body
+Headline workload: the D3Q27 channel (256x128x128, no-slip y/z walls, body
 force 1e-6 along x, 64 droplets R=10 at seeded random centres, near-contact
-range 3 / strength 0.02, tau 1, FP32 storage and arithmetic).  A step is one
-pass of the whole hot path (phase-field pass + collision pass) over the
-lattice, with the populations already resident in HBM.
+range 3 / strength 0.02, tau 1, FP32 storage and arithmetic, the plain
+two-colour layout).  A step is one pass of the whole hot path over the
+lattice: the read-once collision pass (pull, colour gradient, flags,
+near-contact force, BGK + Guo, perturbation, recolouring, store, and the
+scatter of the next step's colour densities) and the combine pass that
+finishes the next phase field, with the populations resident in HBM.
 
-Prints ONE JSON line: MLUPS (million lattice-site updates per second), the
-roofline of the dominant kernel (the collision pass) from HIP events recorded
-on the library's stream around each launch, and the FP64 CPU oracle timed on
-a bounded crop of the same physics.
+Prints ONE JSON line: MLUPS (million lattice-site updates per second) of the
+headline, timed with HIP events around the steps only; the roofline of the
+dominant kernel (the collision pass) from per-launch events in a separate
+profiled run; and beside it every other workload the benchmark is stated
+for (512x256x256 in 16-bit storage, the 96-channel ensemble, the dense
+emulsion with the learned near-contact closure trained on channel rows), and
+the FP64 CPU oracle timed on the same inputs as GPU runs quoted next to it.
 """
 from __future__ import annotations
 
@@ -32,14 +38,19 @@ TOTAL = ("f32t", "f16t", "bf16t", "f16ct")
 NSC_BYTES = 16  # recolouring scalars of the total layout, per site
 
 
+def say(*a):
+    print("#", *a, file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes(q, storage):
     """Per lattice update of the layout in use: (step, collision pass, phase
     pass).  Step: the state read once and written once, plus the phase field
-    written once (pass 1) and read once (pass 2); the plain per-colour FP32
-    D3Q27 step is 440 B.  Phase pass: state read + phase written.  Collision
-    pass: populations read + state written + phase read (per-colour: the
-    whole state both ways; total layout: the scalars are written, not read,
-    since rho_A follows from phi)."""
+    written once and read once; the plain per-colour FP32 D3Q27 step is 440 B.
+    Phase pass: state read + phase written.  Collision pass: populations read
+    + state written + phase read (per-colour: the whole state both ways;
+    total layout: the scalars are written, not read, since rho_A follows from
+    phi).  The read-once step's collision pass has the collision-pass bytes;
+    its combine pass writes the phase field (the step's remaining 4 B)."""
     s = ELEM[storage]
     r = 8 if storage == "f64" else 4
     if storage in TOTAL:
@@ -58,13 +69,16 @@ def plain_state_bytes(q, storage):
     return 2 * q * s * 2 + 2 * r
 
 
+KERNEL_SOURCES = ("step_kernels.hpp", "lattice_ops.hpp", "collide_launch.hpp", "scatter_geom.hpp")
+
+
 def kernel_source_hash():
     """Hash of the sources that fix the passes' code and launch shapes (the
     kernels and their launch wrappers): a traffic figure measured for other
     sources is not reported."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("step_kernels.hpp", "lattice_ops.hpp"):
+    for name in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2405_14551_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -73,7 +87,6 @@ def traffic_from_profiles(kernel_tag, workload_tag):
     """HBM bytes per launch measured with rocprofv3 counters, if a summary for
     this kernel source is committed (profiles/traffic_<kernel>_<workload>.txt
     holds key = value lines incl. the source hash); None otherwise."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}_{workload_tag}.txt")
     if not os.path.exists(path):
         return None
@@ -82,197 +95,294 @@ def traffic_from_profiles(kernel_tag, workload_tag):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    h = kernel_source_hash()
-    if kv.get("source_hash") != h or "bytes_per_launch" not in kv:
+    if kv.get("source_hash") != kernel_source_hash() or "bytes_per_launch" not in kv:
         return None
     return float(kv["bytes_per_launch"])
 
 
-def cpu_baseline(seconds_target=10.0):
-    """The FP64 oracle, single-threaded, on a 64^3 crop of the channel physics
-    (walls y/z, body force, near contact, 4 droplets R=10)."""
-    from threadpoolctl import threadpool_limits
-    from oracle.sim import OracleSim, OracleParams
-    from paper_2405_14551_amd import workloads as W
-    shape = (64, 64, 64)
-    w = W.channel_3d(shape=shape, count=4, radius=10.0)
-    p = OracleParams(lattice="D3Q27", nx=64, ny=64, nz=64, walls=(False, True, True), tau=1.0,
-                     A=0.01, beta=0.7, body_force=(1e-6, 0, 0), nc=True, nc_A=0.02,
-                     nc_hmin=2.0, nc_hmax=3.0)
-    with threadpool_limits(1):
-        sim = OracleSim(p).init_droplets(w["centres"], w["radii"])
-        steps = 0
-        t0 = time.perf_counter()
-        while True:
-            sim.step(1)
-            steps += 1
-            el = time.perf_counter() - t0
-            if el >= seconds_target or steps >= 50:
-                break
-    n = shape[0] * shape[1] * shape[2]
-    return {"value": n * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 numpy oracle, 1 thread, 64x64x64 crop of the channel physics "
-                      f"(walls y/z, force 1e-6, near contact on, 4 droplets R=10), {steps} steps "
-                      f"in {el:.1f} s on {platform.processor() or platform.machine()} "
-                      f"(host nproc {os.cpu_count()})"}
-
-
-def time_storage(kw, cen, rad, storage, steps, warmup, streaming="two_copies", scheme="populations",
-                 rounding="nearest"):
-    """MLUPS and per-launch pass times of the same workload with another
-    storage layout or streaming (HIP events on the library's stream), and the
-    device memory the population state takes per site (both copies with
-    two-copy streaming)."""
+# ------------------------------------------------------------------ GPU runs
+def timed(sim, steps, profile=False):
+    """ms per step of `steps` steps (HIP events on the library's stream); with
+    profile, also the per-launch averages of the passes from a second run of
+    the same length with per-launch events."""
     import torch
-    from paper_2405_14551_amd import lb
-    sim = lb.Simulation(**dict(kw, storage=storage, streaming=streaming, scheme=scheme,
-                               rounding=rounding)).init_droplets(cen, rad)
-    copies = 1 if streaming == "in_place" else 2
-    state_per_site = copies * sim.state_bytes() / (kw["shape"][0] * kw["shape"][1] * kw["shape"][2])
-    sim.step(warmup)
-    sim.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    sim.profile_begin()
+    sim.sync()
     with torch.cuda.stream(sim.stream):
         e0.record(sim.stream)
         sim.step(steps)
         e1.record(sim.stream)
-    prof = sim.profile_end()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    nx, ny, nz = kw["shape"]
+    ms = e0.elapsed_time(e1) / steps
+    if not profile:
+        return ms, None
+    sim.profile_begin()
+    sim.step(steps)
+    p = sim.profile_end()
+    per = {k: (p["ms_" + k] / p["n_" + k] if p["n_" + k] else 0.0) for k in ("collide", "phase", "combine")}
+    return ms, per
+
+
+def run_variant(kw, cen, rad, steps, warmup, **over):
+    """MLUPS and per-launch pass times of a workload with other settings."""
+    from paper_2405_14551_amd import lb
+    k = dict(kw, **over)
+    sim = lb.Simulation(**k).init_droplets(cen, rad)
+    copies = 1 if k.get("streaming") == "in_place" else 2
+    n = int(np.prod(k["shape"]))
+    state = copies * sim.state_bytes() / n
+    sim.step(warmup)
+    ms, per = timed(sim, steps, profile=True)
+    d = sim.diagnostics()
     sim.close()
-    return {"MLUPS": round(nx * ny * nz * steps / (ms / 1e3) / 1e6, 1),
-            "collide_ms": round(prof["ms_collide"] / max(prof["n_collide"], 1), 5),
-            "phase_ms": round(prof["ms_phase"] / max(prof["n_phase"], 1), 5),
-            "state_bytes_per_site": round(state_per_site, 1)}
+    return {"MLUPS": round(n / ms / 1e3, 1), "ms_per_step": round(ms, 5),
+            "collide_ms": round(per["collide"], 5), "phase_ms": round(per["phase"], 5),
+            "combine_ms": round(per["combine"], 5), "state_bytes_per_site": round(state, 1),
+            "droplets": int(d[6])}
 
 
-def time_closure(kw, cen, rad, steps, warmup, explicit):
-    """The learned near-contact closure on the same workload: rows collected
-    after the warm-up with the explicit force, 500 Adam steps, then the step
-    with the closure in the collision pass.  Reports its collision-pass time
-    beside the explicit one and the share of interface sites the network
-    served."""
+def headline(args):
+    from paper_2405_14551_amd import lb, workloads as W
+    w = W.channel_3d(storage=args.storage)
+    kw, cen, rad = W.sim_kwargs(w)
+    n = int(np.prod(kw["shape"]))
+    say(f"headline channel_3d {args.storage} {kw['shape']}")
+    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    sim.step(args.warmup)
+    ms, _ = timed(sim, args.steps)
+    _, per = timed(sim, args.steps, profile=True)
+    diag = sim.diagnostics()
+    sim.close()
+    return kw, cen, rad, n, ms, per, diag
+
+
+def big_lattice(steps, warmup):
+    """The 512 x 256 x 256 lattice (1024 droplets R = 8): plain FP32 against
+    the 16-bit storages (paper Sec. IV.A second group; shifted totals)."""
+    from paper_2405_14551_amd import workloads as W
+    w = W.big_3d(storage="f32")
+    kw, cen, rad = W.sim_kwargs(w)
+    out = {}
+    for name, over in (("f32", {}), ("f16t", dict(storage="f16t")), ("f16t_sround", dict(storage="f16t", rounding="stochastic")),
+                       ("bf16t", dict(storage="bf16t")), ("f16ct", dict(storage="f16ct"))):
+        say(f"big_3d {name}")
+        out[name] = run_variant(kw, cen, rad, steps, warmup, **over)
+    for name in out:
+        out[name]["vs_f32"] = round(out[name]["MLUPS"] / out["f32"]["MLUPS"], 3)
+    return out
+
+
+def channel_variants(kw, cen, rad, steps, warmup, ref_mlups):
+    out = {}
+    for name, over in (("f32_phase_pass", dict(phase="pass")), ("f32t", dict(storage="f32t")),
+                       ("f16t", dict(storage="f16t")), ("f16t_sround", dict(storage="f16t", rounding="stochastic")),
+                       ("bf16t", dict(storage="bf16t")), ("f16ct", dict(storage="f16ct")),
+                       ("f32_in_place", dict(streaming="in_place")),
+                       ("f16t_in_place", dict(storage="f16t", streaming="in_place")),
+                       ("moments_f32", dict(scheme="moments"))):
+        say(f"channel variant {name}")
+        out[name] = run_variant(kw, cen, rad, steps, warmup, **over)
+        out[name]["vs_plain_f32"] = round(out[name]["MLUPS"] / ref_mlups, 3)
+    return out
+
+
+def train_closure_on_channel(target_rows=10_000_000, every=400, max_steps=10_000):
+    """The learned near-contact closure trained as the benchmark states it: on
+    stencil / force rows the explicit model generates in channel runs (FP32,
+    snapshots every `every` steps until `target_rows` rows or `max_steps`
+    steps), 20k Adam steps of 256 rows (half force-active), the learning rate
+    stepped down; the force error on a held-out snapshot of a second channel
+    run (another droplet placement), per near-contact distance class."""
     import torch
     from paper_2405_14551_amd import lb, workloads as W
-    src = lb.Simulation(**dict(kw, nc="explicit")).init_droplets(cen, rad)
-    src.step(warmup)
-    rows, tg, na, nf = src.nc_collect()
-    src.close()
-    tr = lb.Simulation(lattice=kw["lattice"], storage="f32", nc="explicit", shape=(16, 16, 16))
-    tr.mlp_set_weights(W.closure_init_weights())
-    tr.mlp_train(rows, tg, torch.from_numpy(W.closure_batches(na, nf, 500, 256)), lr=2e-3)
-    th, ranges = tr.mlp_get_weights(), tr.mlp_get_ranges()
-    tr.close()
-    sim = lb.Simulation(**dict(kw, nc="mlp"))
-    sim.mlp_set_weights(th)
-    sim.mlp_set_ranges(*ranges)
-    sim.init_droplets(cen, rad)
-    sim.step(warmup)
-    sim.sync()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    sim.profile_begin()
-    with torch.cuda.stream(sim.stream):
-        e0.record(sim.stream)
-        sim.step(steps)
-        e1.record(sim.stream)
-    prof = sim.profile_end()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    fl = sim.fields(("flags",))["flags"]
-    n_if = int(((fl & 1) > 0).sum())
-    n_net = int(((fl & 2) > 0).sum())
-    nx, ny, nz = kw["shape"]
+    w = W.channel_3d()
+    kw, cen, rad = W.sim_kwargs(w)
+    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    act, free = [], []
+    na_tot = nf_tot = 0
+    t = 0
+    t0 = time.perf_counter()
+    while na_tot + nf_tot < target_rows and t < max_steps:
+        sim.step(every)
+        t += every
+        r, g, na, nf = sim.nc_collect()
+        act.append((r[:na].clone(), g[:na].clone()))
+        free.append((r[na:].clone(), g[na:].clone()))
+        na_tot += na
+        nf_tot += nf
     sim.close()
-    col = prof["ms_collide"] / max(prof["n_collide"], 1)
-    return {"MLUPS": round(nx * ny * nz * steps / (ms / 1e3) / 1e6, 1), "collide_ms": round(col, 5),
-            "explicit_collide_ms": explicit, "collide_time_vs_explicit": round(col / explicit, 3),
-            "training_rows": {"active": na, "free": nf}, "interface_sites": n_if,
-            "network_share": round(n_net / max(n_if, 1), 4)}
+    rows = torch.cat([a[0] for a in act] + [f[0] for f in free])
+    tgs = torch.cat([a[1] for a in act] + [f[1] for f in free])
+    del act, free
+    collect_s = time.perf_counter() - t0
+    say(f"closure rows: {na_tot} active, {nf_tot} free from {t} channel steps")
+    tr = lb.Simulation(lattice="D3Q27", storage="f32", nc="explicit", shape=(16, 16, 16))
+    tr.mlp_set_weights(W.closure_init_weights())
+    t1 = time.perf_counter()
+    losses = []
+    for k, (n_steps, lr) in enumerate(((12000, 2e-3), (6000, 5e-4), (2000, 1e-4))):
+        order = W.closure_batches(na_tot, nf_tot, n_steps, 256, seed=k + 1)
+        losses.append(float(tr.mlp_train(rows, tgs, torch.from_numpy(order), lr=lr)[-200:].mean()))
+    train_s = time.perf_counter() - t1
+    theta, ranges = tr.mlp_get_weights(), tr.mlp_get_ranges()
+    del rows, tgs
+    # held-out snapshot: the same channel with another droplet placement
+    wh = W.channel_3d(seed=W.SEED + 1)
+    kwh, ch, rh = W.sim_kwargs(wh)
+    sh = lb.Simulation(**kwh).init_droplets(ch, rh)
+    sh.step(2000)
+    r, g, na, nf = sh.nc_collect()
+    sh.close()
+    pred = tr.mlp_infer(r).double()
+    tr.close()
+    n = r[:, 27:30].double()
+    gn = r[:, 30:31].double()
+    T = g.double()
+    F = gn * torch.clamp((pred * n).sum(1, keepdim=True), min=0.0) * n   # the force the step applies
+    Fraw = gn * pred
+    Fexp = gn * T
+    mag = torch.linalg.norm(T, dim=1)
+    act_m = mag > 0
+
+    def err(Fx, m):
+        d = torch.linalg.norm(Fexp[m])
+        return float(torch.linalg.norm(Fx[m] - Fexp[m]) / d) if m.any() and d > 0 else None
+    classes = {"active": act_m, "h<=2": (mag - 0.5).abs() < 1e-3, "h=3": (mag - 0.5 * (2 / 3) ** 3).abs() < 1e-3,
+               "all": torch.ones_like(act_m)}
+    return theta, ranges, {
+        "recipe": f"channel 256x128x128 FP32 explicit force, rows every {every} steps",
+        "rows": {"active": na_tot, "free": nf_tot, "total": na_tot + nf_tot, "stated": 10_000_000,
+                 "channel_steps": t},
+        "adam_steps": 20000, "batch": 256, "loss_end": losses,
+        "collect_s": round(collect_s, 2), "train_s": round(train_s, 2),
+        "held_out": {"workload": "channel_3d, droplet seed + 1, step 2000", "rows_active": na, "rows_free": nf,
+                     "force_error_applied": {k: err(F, m) for k, m in classes.items()},
+                     "force_error_raw": {k: err(Fraw, m) for k, m in classes.items()}},
+    }
 
 
-def ensemble_bench(args):
-    """Batched ensemble of 96 independent D3Q19 channels (sizes 64..160 x
-    64..96 x 64..96, tau 0.6..1.2, 4..40 droplets each; FP32, near contact):
-    autotuned launch configuration, aggregate MLUPS, the collision launch's
-    roofline, and the same channels run one after another as stand-alone
-    simulations."""
+def closure_speed(kw, cen, rad, theta, ranges, steps, warmup):
+    """Collision-pass time and MLUPS with the explicit near-contact scan and
+    with the learned closure on the same workload; droplets after the run."""
+    from paper_2405_14551_amd import lb
+    out = {}
+    for mode in ("explicit", "mlp"):
+        sim = lb.Simulation(**dict(kw, nc=mode))
+        if mode == "mlp":
+            sim.mlp_set_weights(theta)
+            sim.mlp_set_ranges(*ranges)
+        sim.init_droplets(cen, rad)
+        sim.step(warmup)
+        ms, per = timed(sim, steps, profile=True)
+        n = int(np.prod(kw["shape"]))
+        fl = sim.fields(("flags",))["flags"]
+        d = sim.diagnostics()
+        out[mode] = {"MLUPS": round(n / ms / 1e3, 1), "collide_ms": round(per["collide"], 5),
+                     "combine_ms": round(per["combine"], 5), "droplets": int(d[6]), "umax": round(float(d[5]), 5),
+                     "interface_sites": int(((fl & 1) > 0).sum())}
+        if mode == "mlp":
+            out[mode]["network_share"] = round(int(((fl & 2) > 0).sum()) / max(out[mode]["interface_sites"], 1), 4)
+        sim.close()
+    out["collide_time_closure_vs_explicit"] = round(out["mlp"]["collide_ms"] / out["explicit"]["collide_ms"], 3)
+    return out
+
+
+def ensemble(steps, warmup):
+    """96 independent D3Q19 channels (sizes 64..160 x 64..96 x 64..96, tau
+    0.6..1.2, 4..40 droplets each; FP32, near contact): autotuned launch
+    configuration and aggregate MLUPS."""
     import torch
     from paper_2405_14551_amd import lb, workloads as W
     w = W.ensemble_channels()
     chans = w["channels"]
-    N = int(sum(np.prod(c["shape"]) for c in chans))
+    n = int(sum(np.prod(c["shape"]) for c in chans))
     plain = [{k: v for k, v in c.items() if k not in ("centres", "radii")} for c in chans]
     ens = lb.Ensemble(plain, lattice=w["lattice"], storage=w["storage"], nc=w["nc"])
     for k, c in enumerate(chans):
         ens.init_droplets(k, c["centres"], c["radii"])
     best, table = ens.autotune(steps=4)
-    print(f"# ensemble autotune best {best}", file=sys.stderr, flush=True)
-    for k, c in enumerate(chans):      # restart from the initial state after tuning
+    for k, c in enumerate(chans):
         ens.init_droplets(k, c["centres"], c["radii"])
-    ens.step(args.warmup)
+    ens.step(warmup)
     ens.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(ens.stream):
         e0.record(ens.stream)
-        ens.step(args.steps)
+        ens.step(steps)
         e1.record(ens.stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    prof_steps = 20
+    ms = e0.elapsed_time(e1) / steps
     ens.profile_begin()
-    ens.step(prof_steps)
-    prof = ens.profile_end()
-    ens.sync()
-    # collision and phase time per step: one launch each in the batched mode,
-    # one per channel in the per-channel mode
-    col_ms = prof["ms_collide"] / prof_steps
-    ph_ms = prof["ms_phase"] / prof_steps
-    launches = max(prof["n_collide"], 1) // prof_steps
+    ens.step(steps)
+    p = ens.profile_end()
     ens.close()
-    q = 19
-    b_step, b_col, b_phase = algorithmic_bytes(q, "f32")
-    mlups = N * args.steps / (ms / 1e3) / 1e6
-    achieved = b_col * N / (col_ms / 1e3) / 1e9
-    # stand-alone runs of the same channels, one after another
-    sa_steps = min(args.steps, 50)
-    t_sum = 0.0
-    for c in chans:
-        kw = dict(c)
-        cen, rad = kw.pop("centres"), kw.pop("radii")
-        sim = lb.Simulation(lattice=w["lattice"], storage=w["storage"], nc=w["nc"], **kw).init_droplets(cen, rad)
-        sim.step(5)
-        sim.sync()
-        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(sim.stream):
-            a0.record(sim.stream)
-            sim.step(sa_steps)
-            a1.record(sim.stream)
-        torch.cuda.synchronize()
-        t_sum += a0.elapsed_time(a1)
+    b_step, b_col, _ = algorithmic_bytes(19, "f32")
+    col_ms = p["ms_collide"] / steps
+    return {"workload": "ensemble_96_d3q19", "channels": len(chans), "sites": n,
+            "MLUPS": round(n / ms / 1e3, 1), "ms_per_step": round(ms, 4), "tuning": best,
+            "collision_ms_per_step": round(col_ms, 4),
+            "collision_frac": round(b_col * n / (col_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "step_frac": round(n / ms / 1e3 * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
+            "autotune": table}
+
+
+def same_inputs_gpu(steps_c0=1000, steps_crop=50):
+    """GPU MLUPS on the inputs the oracle is timed on: the 2D Laplace droplet
+    (FP64) and the 64^3 crop of the 512 x 256 x 256 workload (FP64 and FP32)."""
+    from paper_2405_14551_amd import lb, workloads as W
+    out = {}
+    w = W.laplace_2d(on_site=True)
+    kw, cen, rad = W.sim_kwargs(w)
+    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    sim.step(10)
+    ms, _ = timed(sim, steps_c0)
+    sim.close()
+    out["laplace_2d_f64"] = {"MLUPS": round(128 * 64 / ms / 1e3, 2), "steps": steps_c0}
+    for st in ("f64", "f32"):
+        w = W.big_3d_crop(storage=st)
+        kw, cen, rad = W.sim_kwargs(w)
+        sim = lb.Simulation(**kw).init_droplets(cen, rad)
+        sim.step(10)
+        ms, _ = timed(sim, max(steps_crop, 200))
         sim.close()
-    sa_mlups = N * sa_steps / (t_sum / 1e3) / 1e6
-    out = {
-        "metric": "MLUPS (aggregate over the ensemble)", "value": round(mlups, 2), "unit": "MLUPS",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded channel sizes, tau and droplet placement)",
-        "config": {"workload": "ensemble_96_d3q19", "channels": len(chans), "sites": N, "lattice": "D3Q19",
-                   "storage": "f32", "near_contact": "explicit", "tuning": best},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "ensemble collision launch" if best["mode"] == "batched" else "per-channel collision launches",
-                     "bytes_per_site": b_col, "avg_launch_ms": round(col_ms, 5),
-                     "launches_per_step": launches},
-        "step_roofline": {"bytes_per_site": b_step, "frac": round(mlups * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
-                          "phase_launch_ms": round(ph_ms, 5)},
-        "standalone": {"MLUPS": round(sa_mlups, 1), "steps": sa_steps,
-                       "note": "the 96 channels as separate simulations, one after another"},
-        "autotune_table": table,
-    }
-    print(json.dumps(out), flush=True)
-    return 0
+        out[f"crop_64_{st}"] = {"MLUPS": round(64 ** 3 / ms / 1e3, 1)}
+    return out
+
+
+def cpu_baseline():
+    """The FP64 numpy oracle, single-threaded, on the same inputs as GPU runs
+    in this benchmark: the 2D Laplace droplet (D2Q9 128 x 64, 1000 steps) and
+    the 64^3 crop of the 512 x 256 x 256 workload (D3Q27, walls y/z, body
+    force, near contact, its droplets; 30 steps).  About 20 s of CPU work."""
+    from threadpoolctl import threadpool_limits
+    from oracle.sim import OracleSim, OracleParams
+    from paper_2405_14551_amd import workloads as W
+    res = {}
+    with threadpool_limits(1):
+        w = W.laplace_2d(on_site=True)
+        p = OracleParams(lattice="D2Q9", nx=128, ny=64, nz=1, tau=1.0, A=0.01, beta=0.7)
+        sim = OracleSim(p).init_droplets(w["centres"], w["radii"])
+        t0 = time.perf_counter()
+        sim.step(1000)
+        el = time.perf_counter() - t0
+        res["laplace_2d"] = {"MLUPS": round(128 * 64 * 1000 / el / 1e6, 4), "steps": 1000, "seconds": round(el, 2)}
+        w = W.big_3d_crop(storage="f64")
+        p = OracleParams(lattice="D3Q27", nx=64, ny=64, nz=64, walls=tuple(bool(v) for v in w["walls"]), tau=1.0,
+                         A=0.01, beta=0.7, body_force=tuple(w["body_force"]), nc=True, nc_A=0.02, nc_hmin=2.0,
+                         nc_hmax=3.0)
+        sim = OracleSim(p).init_droplets(w["centres"], w["radii"])
+        steps = 30
+        t0 = time.perf_counter()
+        sim.step(steps)
+        el = time.perf_counter() - t0
+        res["crop_64"] = {"MLUPS": round(64 ** 3 * steps / el / 1e6, 4), "steps": steps, "seconds": round(el, 2)}
+    host = f"{platform.processor() or platform.machine()}, host nproc {os.cpu_count()}"
+    return {"value": res["crop_64"]["MLUPS"], "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy oracle, 1 thread ({host}): the 64^3 crop of the 512x256x256 workload "
+                      f"(D3Q27, walls y/z, body force 1e-6, near contact on, {len(w['radii'])} droplets R=8), "
+                      f"{res['crop_64']['steps']} steps in {res['crop_64']['seconds']} s (value); the 2D Laplace "
+                      f"droplet (D2Q9 128x64, 1000 steps) in {res['laplace_2d']['seconds']} s",
+            "runs": res}
 
 
 def copy_calibration(nbytes=1 << 30, reps=10):
@@ -295,13 +405,13 @@ def copy_calibration(nbytes=1 << 30, reps=10):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--workload", default="channel_3d", choices=["channel_3d", "big_3d", "dense_3d", "ensemble"])
-    ap.add_argument("--storage", default=None, help="f32 (default), f16, bf16, f64")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the channel workload (for profiling runs)")
+    ap.add_argument("--storage", default="f32", choices=sorted(ELEM),
+                    help="storage of the channel workload (profiling runs; the headline is f32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true",
-                    help="skip the 16-bit storage and learned-closure variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -313,47 +423,17 @@ def main():
         return 2
 
     import torch
-    from paper_2405_14551_amd import lb, workloads as W
-
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
-    if args.workload == "ensemble":
-        return ensemble_bench(args)
-    wl = {"channel_3d": W.channel_3d, "big_3d": W.big_3d, "dense_3d": W.dense_3d}[args.workload]
-    w = wl(storage=args.storage) if args.storage else wl()
-    if args.storage:
-        w["storage"] = args.storage
-    kw, cen, rad = W.sim_kwargs(w)
-    storage = kw["storage"]
-    print(f"# workload {args.workload} storage {storage} shape {kw['shape']}", file=sys.stderr, flush=True)
-    sim = lb.Simulation(**kw)
-    sim.init_droplets(cen, rad)
-    nx, ny, nz = kw["shape"]
-    N = nx * ny * nz
-    q = sim.q
-    sim.step(args.warmup)
-    sim.sync()
-    stream = sim.stream
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    sim.profile_begin()
-    with torch.cuda.stream(stream):
-        t_start.record(stream)
-        sim.step(args.steps)
-        t_end.record(stream)
-    prof = sim.profile_end()
-    torch.cuda.synchronize()
-    ms = t_start.elapsed_time(t_end)
-    ms_per_step = ms / args.steps
-    mlups = N * args.steps / (ms / 1e3) / 1e6
-    b_step, b_col, b_phase = algorithmic_bytes(q, storage)
-    col_ms = prof["ms_collide"] / max(prof["n_collide"], 1)
-    ph_ms = prof["ms_phase"] / max(prof["n_phase"], 1)
-    achieved = b_col * N / (col_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles("collide", f"{args.workload}_{storage}")
-    diag = sim.diagnostics()
+
+    kw, cen, rad, n, ms, per, diag = headline(args)
+    q = 27
+    mlups = n / ms / 1e3
+    b_step, b_col, _ = algorithmic_bytes(q, args.storage)
+    col_ms = per["collide"]
+    achieved = b_col * n / (col_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles("collide", f"channel_3d_{args.storage}")
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -361,54 +441,46 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(ms, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if storage == "f64" else "f32",
+        "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic (seeded droplet placement)",
-        "config": {"workload": args.workload, "lattice": kw["lattice"], "storage": storage,
+        "config": {"workload": "channel_3d", "lattice": "D3Q27", "storage": args.storage,
+                   "step": "read-once" if per["combine"] > 0 else "phase pass + collision",
                    "shape": list(kw["shape"]), "walls": list(kw["walls"]), "droplets": int(len(rad)),
-                   "near_contact": kw["nc"], "sites": N},
+                   "near_contact": kw["nc"], "sites": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "traffic_vs_algorithmic": (round(traffic / (b_col * N), 3) if traffic else None),
-                     "kernel": "k_collide (collision pass)",
-                     "bytes_per_site": b_col, "avg_launch_ms": round(col_ms, 5)},
-        "step_roofline": {"bytes_per_site": b_step, "frac": round(mlups * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
-                          "plain_state_bytes_per_site": plain_state_bytes(q, storage),
-                          "frac_vs_plain_state": round(mlups * 1e6 * plain_state_bytes(q, storage) / 1e9
-                                                       / HBM_PEAK_GBS, 4),
-                          "phase_pass_ms": round(ph_ms, 5), "phase_pass_GBs": round(b_phase * N / (ph_ms / 1e3) / 1e9, 1)},
+                     "traffic_vs_algorithmic": (round(traffic / (b_col * n), 3) if traffic else None),
+                     "kernel": "k_collide (read-once collision pass)" if per["combine"] > 0
+                               else "k_collide (collision pass)", "bytes_per_site": b_col,
+                     "avg_launch_ms": round(col_ms, 5),
+                     "step_frac": round(mlups * 1e6 * b_step / 1e9 / HBM_PEAK_GBS, 4),
+                     "step_bytes_per_site": b_step,
+                     "combine_launch_ms": round(per["combine"], 5),
+                     "phase_launch_ms": round(per["phase"], 5)},
         "sanity": {"droplets_end": int(diag[6]), "umax": float(diag[5])},
     }
-    sim.close()
-    if not args.no_variants and storage == "f32":
-        # same workload: total-population layouts (FP32 / FP16 / BF16 storage,
-        # FP32 arithmetic), in-place streaming (one copy of the state) and the
-        # learned near-contact closure
-        vs = min(args.steps, 200)
-        var = {}
-        for st, mode in (("f32t", "two_copies"), ("f16t", "two_copies"), ("bf16t", "two_copies"),
-                         ("f16ct", "two_copies"), ("f32", "in_place"), ("f16t", "in_place")):
-            name = st if mode == "two_copies" else f"{st}_in_place"
-            var[name] = time_storage(kw, cen, rad, st, vs, args.warmup, mode)
-            var[name]["vs_plain_f32"] = round(var[name]["MLUPS"] / mlups, 3)
-            print(f"# variant {name}: {var[name]}", file=sys.stderr, flush=True)
-        # FP16 total layout with stochastic rounding of the stored totals
-        var["f16t_sround"] = time_storage(kw, cen, rad, "f16t", vs, args.warmup, rounding="stochastic")
-        var["f16t_sround"]["vs_plain_f32"] = round(var["f16t_sround"]["MLUPS"] / mlups, 3)
-        print(f"# variant f16t_sround: {var['f16t_sround']}", file=sys.stderr, flush=True)
-        # the moment-based (regularised) scheme: 15 moments per site
-        var["moments_f32"] = time_storage(kw, cen, rad, "f32", vs, args.warmup, scheme="moments")
-        var["moments_f32"]["vs_plain_f32"] = round(var["moments_f32"]["MLUPS"] / mlups, 3)
-        print(f"# variant moments_f32: {var['moments_f32']}", file=sys.stderr, flush=True)
-        if kw.get("nc") == "explicit":
-            var["closure_f32"] = time_closure(kw, cen, rad, vs, args.warmup, col_ms)
-            print(f"# variant closure: {var['closure_f32']}", file=sys.stderr, flush=True)
-        out["variants"] = var
+    if not args.headline_only:
+        vs = min(args.steps, 50)
+        wu = min(args.warmup, 10)
+        out["variants"] = channel_variants(kw, cen, rad, vs, wu, mlups)
+        out["big_3d"] = big_lattice(min(args.steps, 20), 3)
+        theta, ranges, tr = train_closure_on_channel()
+        out["closure"] = tr
+        out["closure"]["channel_3d"] = closure_speed(kw, cen, rad, theta, ranges, vs, wu)
+        from paper_2405_14551_amd import workloads as W
+        wd = W.dense_3d()
+        kwd, cend, radd = W.sim_kwargs(wd)
+        say("dense_3d explicit vs closure")
+        out["closure"]["dense_3d"] = closure_speed(kwd, cend, radd, theta, ranges, min(args.steps, 20), 100)
+        say("ensemble")
+        out["ensemble"] = ensemble(min(args.steps, 20), 5)
+        out["same_inputs_gpu"] = same_inputs_gpu()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -139,21 +139,28 @@ typedef enum lb_scheme { LB_SCHEME_POPULATIONS = 0, LB_SCHEME_MOMENTS = 1 } lb_s
 typedef enum lb_rounding { LB_ROUND_NEAREST = 0, LB_ROUND_STOCHASTIC = 1 } lb_rounding;
 
 /* How a step forms the phase field its colour gradient needs, that of the
- * neighbours after streaming (Sec. III.C.1).  Both give the same step up to
- * the rounding order of the colour sums.
- *  LB_PHASE_SCATTER  read-once step (the default): the collision pass of step
- *                    t adds every post-collision value, as storage will return
- *                    it, to the colour densities of the site that pulls it at
- *                    step t+1 (x + c_i, or x itself when x + c_i is solid), so
- *                    the populations are read once per step; values that
- *                    leave a collision tile are summed into its halo block
- *                    and a small combine pass finishes the phase field.  The
- *                    first step after lb_init_droplets / lb_set_state runs the
- *                    phase pass once.  Single lattices with the population
- *                    scheme; ensembles and the moment scheme use the phase pass.
+ * neighbours after streaming (Sec. III.C.1).  Both ways give the same step up
+ * to the rounding order of the colour sums.
+ *  LB_PHASE_SCATTER  read-once step: the collision pass of step t adds every
+ *                    post-collision value, as storage will return it, to the
+ *                    colour densities of the site that pulls it at step t+1
+ *                    (x + c_i, or x itself when x + c_i is solid), so the
+ *                    populations are read once per step; values that leave a
+ *                    collision tile are summed into its halo block and a
+ *                    small combine pass finishes the phase field.  The first
+ *                    step after lb_init_droplets / lb_set_state first scatters
+ *                    the stored state (a bootstrap pass that forms exactly the
+ *                    sums the collision pass storing it formed), so restarts
+ *                    repeat uninterrupted runs bit for bit.  Single lattices
+ *                    with the population scheme.
  *  LB_PHASE_PASS     a separate pass pulls the populations a second time each
- *                    step and forms the phase field before the collision pass. */
-typedef enum lb_phase_mode { LB_PHASE_SCATTER = 0, LB_PHASE_PASS = 1 } lb_phase_mode;
+ *                    step and forms the phase field before the collision pass
+ *                    (ensembles and the moment scheme always work this way).
+ *  LB_PHASE_AUTO     (the default) the read-once step for the per-colour
+ *                    layouts and LB_F32_TOTAL, the phase pass for the 16-bit
+ *                    total layouts, whose collision pass is bound by
+ *                    instruction issue and measured slower with the scatter. */
+typedef enum lb_phase_mode { LB_PHASE_AUTO = 0, LB_PHASE_SCATTER = 1, LB_PHASE_PASS = 2 } lb_phase_mode;
 
 /* field selection bits for lb_fields; dst[k] belongs to bit k */
 enum {

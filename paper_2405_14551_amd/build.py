@@ -16,9 +16,12 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(PKG, "liblbmi.so")
+# LB_BUILD_DIR / LB_LIB_OUT: another object directory and library path (for
+# builds with other compile-time settings, LB_EXTRA_CFLAGS, e.g. -DLB_RO_PIPELINE=0)
+BUILD = os.environ.get("LB_BUILD_DIR", os.path.join(ROOT, "_build"))
+LIB = os.environ.get("LB_LIB_OUT", os.path.join(PKG, "liblbmi.so"))
 ARCH = os.environ.get("LB_OFFLOAD_ARCH", "gfx950")
+EXTRA = os.environ.get("LB_EXTRA_CFLAGS", "").split()
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
@@ -34,6 +37,7 @@ CFLAGS = [
     # no packed FP32 instructions in generated device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
+    *EXTRA,
 ]
 
 

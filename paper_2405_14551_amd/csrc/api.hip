@@ -119,7 +119,7 @@ struct lb_handle {
   int pcur = 0, pfield = 0;
   void* phi_at(int k) const { return k ? phi2 : phi; }
   void* phi_field() const { return phi_at(pfield); }
-  // read-once step (lb_params.phase_pass == LB_PHASE_SCATTER): the collision
+  // read-once step (lb_params.phase_pass, lb_phase_mode): the collision
   // pass scatters the next step's colour densities into ro_part (2 x N) and
   // ro_halo (per tile-march halo blocks, marches of ro_zb planes); phi_ready
   // says that phi_at(pcur) already holds the phase field of the next pull
@@ -304,7 +304,7 @@ static int validate(const lb_params* p) {
     if (p->nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "the moment-based scheme takes nc_mode off or explicit");
     if (p->streaming != LB_STREAM_TWO_COPIES) return fail(LB_EINVAL, "the moment-based scheme streams with two copies");
   }
-  if (p->phase_pass != LB_PHASE_SCATTER && p->phase_pass != LB_PHASE_PASS)
+  if (p->phase_pass != LB_PHASE_AUTO && p->phase_pass != LB_PHASE_SCATTER && p->phase_pass != LB_PHASE_PASS)
     return fail(LB_EINVAL, "unknown phase_pass %d", p->phase_pass);
   if (p->rounding != LB_ROUND_NEAREST && p->rounding != LB_ROUND_STOCHASTIC)
     return fail(LB_EINVAL, "unknown rounding %d", p->rounding);
@@ -464,7 +464,11 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
     if (!h->in_place()) ALLOC(h->sc[1], sizeof(float) * NSC * N);
   }
   ALLOC(h->phi, N * h->rsize);
-  h->ro = !channel && !h->moments() && p->phase_pass == LB_PHASE_SCATTER;
+  {
+    const bool total16 = p->storage == LB_F16_TOTAL || p->storage == LB_BF16_TOTAL || p->storage == LB_F16C_TOTAL;
+    const int mode = p->phase_pass == LB_PHASE_AUTO ? (total16 ? LB_PHASE_PASS : LB_PHASE_SCATTER) : p->phase_pass;
+    h->ro = !channel && !h->moments() && mode == LB_PHASE_SCATTER;
+  }
   if (h->ro) {
     ALLOC(h->phi2, N * h->rsize);
     ALLOC(h->ro_part, 2 * N * h->rsize);

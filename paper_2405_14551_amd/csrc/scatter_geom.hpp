@@ -87,13 +87,12 @@ LB_HD int neighbour_tile(int t, int d, int count, int wall) {
   return u;
 }
 
-// Calls f(entry) for every H entry holding a value for site (x, y, z) from a
+// Calls f(entry) for every H entry holding a value for the site at local
+// position (lx, ly, lz) of tile-march (tx, ty, tm) (widths wx, wy, wz) from a
 // neighbouring tile-march, in a fixed order (dz, dy, dx from -1 to +1).
 template <class F>
-LB_HD void halo_sources(const HaloGeom& g, int x, int y, int z, F&& f) {
-  const int tx = x / g.TX, ty = y / g.TY, tm = z / g.zb;
-  const int lx = x - tx * g.TX, ly = y - ty * g.TY, lz = z - tm * g.zb;
-  const int wx = g.width_x(tx), wy = g.width_y(ty), wz = g.width_z(tm);
+LB_HD void halo_sources_at(const HaloGeom& g, int tx, int ty, int tm, int lx, int ly, int lz, int wx, int wy, int wz,
+                           F&& f) {
   const int zlo = g.dims == 3 ? -1 : 0, zhi = g.dims == 3 ? 1 : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
     if (dz == -1 && lz != 0) continue;
@@ -123,6 +122,14 @@ LB_HD void halo_sources(const HaloGeom& g, int x, int y, int z, F&& f) {
       }
     }
   }
+}
+
+// the same for site (x, y, z)
+template <class F>
+LB_HD void halo_sources(const HaloGeom& g, int x, int y, int z, F&& f) {
+  const int tx = x / g.TX, ty = y / g.TY, tm = z / g.zb;
+  halo_sources_at(g, tx, ty, tm, x - tx * g.TX, y - ty * g.TY, z - tm * g.zb, g.width_x(tx), g.width_y(ty),
+                  g.width_z(tm), f);
 }
 
 }  // namespace lbm

@@ -1118,12 +1118,15 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   [[maybe_unused]] R clsPA = 0, clsPB = 0, clsNA = 0, clsNB = 0;
   // RO: send the stored values (cA, cB) of direction I of the site of n to
   // the site that pulls them next step
-  [[maybe_unused]] auto route = [&](auto ic, R cA, R cB, const Nbr& n, bool open, bool live) {
+  // (ragged: the wave has lanes outside the lattice, whose values are dropped)
+  [[maybe_unused]] auto route = [&](auto ic, R cA, R cB, const Nbr& n, bool open, bool live, bool ragged) {
     if constexpr (RO) {
       constexpr int I = decltype(ic)::value;
       constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
-      cA = live ? cA : R(0);
-      cB = live ? cB : R(0);
+      if (ragged) {
+        cA = live ? cA : R(0);
+        cB = live ? cB : R(0);
+      }
       if constexpr (I != 0) {
         if (!open) {
           // halfway bounce-back: a value sent into a wall returns to the site
@@ -1169,6 +1172,44 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
     }
   };
 
+  // pulled populations: both colours (shifted by w_i rho0/2 each), or the
+  // total.  RO pipelines the pull: plane z+1's loads are issued as soon as
+  // plane z has been collided, so that they are in flight during the
+  // scatter's exchange and the barriers.
+// (measured on the 256 x 128 x 128 channel: the pipelined pull spills at
+// three waves per SIMD and gains nothing at two; off by default)
+#ifndef LB_RO_PIPELINE
+#define LB_RO_PIPELINE 0
+#endif
+  constexpr bool PIPE = RO && !BOOT && LB_RO_PIPELINE;
+  R va[L::Q], vb[TOT ? 1 : L::Q];
+  auto do_pull = [&](const Nbr& nn, bool op, const S* fA, const S* fB) {
+    // rows away from the walls (most of them) skip the bounce-back selects
+    auto pull = [&](auto open) {
+      static_for<0, L::Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        uint32_t vo;
+        if constexpr (STREAM == STREAM_ODD) vo = own_reversed_index<L, I>(nn, a.N) * ES;
+        else vo = (decltype(open)::value ? pull_index_open<L, I>(nn, a.N) : pull_index<L, I>(nn, a.N)) * ES;
+        if constexpr (TOT) {
+          va[I] = (R)total_bload<S, LCP>(pair_rsrc<L, I>(fA, a.N), vo);
+        } else {
+          va[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(fA, a.N), vo, hshift);
+          vb[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(fB, a.N), vo, hshift);
+        }
+      });
+    };
+    // (the odd in-place kind reads its own slots either way; it keeps the
+    // branch so that all streaming modes compile to the same code shape
+    // around the arithmetic, and the compiler fuses it alike)
+    if (op) pull(std::true_type{});
+    else pull(std::false_type{});
+  };
+  if constexpr (PIPE) {
+    const Nbr n0 = make_nbr(min(x, a.nx - 1), min(y, a.ny - 1), z0, a);
+    do_pull(n0, wave_open(n0), fin, fin + (TOT ? 0 : a.QN));
+  }
+
   for (int z = z0; z < z1; ++z) {
     // prefetch the plane the next iteration needs into registers; it goes to
     // the spare ring slot at the end of this iteration (one barrier per plane)
@@ -1191,6 +1232,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       const Nbr n = make_nbr(min(x, a.nx - 1), min(y, a.ny - 1), z, a);
       const bool open = wave_open(n);
       const bool live = valid_xy;
+      const bool ragged = __ballot(!live) != 0;
       const R hshift = (R)a.half_rho0, rho0 = R(2) * hshift;
       [[maybe_unused]] float sc_a = 0.f, sc_bx = 0.f, sc_by = 0.f, sc_bz = 0.f;
       if constexpr (TOT) {
@@ -1205,10 +1247,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         if constexpr (TOT) {
           const float tv = total_bload<S>(pair_rsrc<L, I>(finA, a.N), vo);
           const R cA = colour_of_total<L, I>(tv, sc_a, sc_bx, sc_by, sc_bz, rho0, hshift);
-          route(ic, cA, (R)tv - cA, n, open, live);
+          route(ic, cA, (R)tv - cA, n, open, live, ragged);
         } else {
           route(ic, Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finA, a.N), vo, hshift),
-                Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), vo, hshift), n, open, live);
+                Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), vo, hshift), n, open, live, ragged);
         }
       };
       own(std::integral_constant<int, 0>{});
@@ -1220,28 +1262,8 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       // ---- issue the pull first so that its latency overlaps the stencil
       // work below: both colours (shifted by w_i rho0/2 each), or the total
       const Nbr n = make_nbr(ALL ? min(x, a.nx - 1) : x, ALL ? min(y, a.ny - 1) : y, z, a);
-      R va[L::Q], vb[TOT ? 1 : L::Q];
-      // rows away from the walls (most of them) skip the bounce-back selects
-      auto pull = [&](auto open) {
-        static_for<0, L::Q>([&](auto ic) {
-          constexpr int I = decltype(ic)::value;
-          uint32_t vo;
-          if constexpr (STREAM == STREAM_ODD) vo = own_reversed_index<L, I>(n, a.N) * ES;
-          else vo = (decltype(open)::value ? pull_index_open<L, I>(n, a.N) : pull_index<L, I>(n, a.N)) * ES;
-          if constexpr (TOT) {
-            va[I] = (R)total_bload<S, LCP>(pair_rsrc<L, I>(finA, a.N), vo);
-          } else {
-            va[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(finA, a.N), vo, hshift);
-            vb[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(finB, a.N), vo, hshift);
-          }
-        });
-      };
-      // (the odd in-place kind reads its own slots either way; it keeps the
-      // branch so that all streaming modes compile to the same code shape
-      // around the arithmetic, and the compiler fuses it alike)
       const bool open = wave_open(n);
-      if (open) pull(std::true_type{});
-      else pull(std::false_type{});
+      if constexpr (!PIPE) do_pull(n, open, finA, finB);
       const int p0 = zc * T::PL;
       constexpr int dz1 = T::RZ ? 1 : 0;   // 2D: a single plane
       const int pm = ring_slot(zc, -dz1, T::NPL) * T::PL;
@@ -1318,6 +1340,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       // arithmetic, as in the other modes.  RO: every lane collides (on a
       // clamped site) and only lanes inside the lattice store.
       const bool live = valid_xy;
+      [[maybe_unused]] const bool ragged = RO && __ballot(!live) != 0;
       if (!MLP || RO || valid_xy) {
         // ---- moments of the pulled populations
         R d[L::Q];  // d_i = f_i - w_i rho0, total over both colours
@@ -1420,7 +1443,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
               // the colours of the stored total, rebuilt from it and this
               // site's stored scalars as the next step's pull rebuilds them
               const R cA = colour_of_total<L, I>(tv, sc_a, sc_bx, sc_by, sc_bz, rho0, hshift);
-              route(ic, cA, (R)tv - cA, n, open, live);
+              route(ic, cA, (R)tv - cA, n, open, live, ragged);
             }
           } else {
             const R wi = (R)L::w[I];
@@ -1432,7 +1455,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
             }
             if constexpr (RO)
               route(ic, Storage<S>::template rt<I, L>(da, hshift), Storage<S>::template rt<I, L>(db, hshift), n,
-                    open, live);
+                    open, live, ragged);
           }
         };
         // one velocity pair: shared dot products, even / odd split
@@ -1488,6 +1511,12 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           const bool fallback = MLP && flag && has_g && !use_net;
           fo.flags[n.site] = (uint8_t)((flag ? 1 : 0) | (use_net ? 2 : 0) | (fallback ? 4 : 0));
         }
+      }
+    }
+    if constexpr (PIPE) {
+      if (z + 1 < z1) {
+        const Nbr n1 = make_nbr(min(x, a.nx - 1), min(y, a.ny - 1), z + 1, a);
+        do_pull(n1, wave_open(n1), finA, finB);
       }
     }
     if constexpr (RO) {
@@ -1569,10 +1598,24 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   }
 }
 
+// waves per SIMD the read-once passes with FP32 arithmetic are held to
+// (per-colour and total layouts): the register budget that decides between
+// keeping the pipelined pull in registers and running more waves
+#ifndef LB_RO_WAVES_COLOUR
+#define LB_RO_WAVES_COLOUR 3
+#endif
+#ifndef LB_RO_WAVES_TOTAL
+#define LB_RO_WAVES_TOTAL 3
+#endif
+template <class S, bool TOT, bool RO>
+constexpr int collide_min_waves() {
+  return (RO && sizeof(typename Storage<S>::real) == 4) ? (TOT ? LB_RO_WAVES_TOTAL : LB_RO_WAVES_COLOUR) : 1;
+}
+
 // SR: stochastic rounding of the stored 16-bit totals (FP16 / BF16 total layouts)
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool SR = false,
           bool RO = false>
-__global__ void __launch_bounds__(T::NT) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
+__global__ void __launch_bounds__(T::NT, (collide_min_waves<S, TOT, RO>())) k_collide(const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::real* __restrict__ phi,
                                                     float* __restrict__ scout,
                                                     FieldPtrs fo, StepArgs a, ScatterOut sout) {
@@ -1611,17 +1654,22 @@ __global__ void __launch_bounds__(T::NT) k_boot_scatter(const S* __restrict__ f,
 
 // Read-once step, second launch: the next step's phase field from the
 // partial densities P and the halo entries the neighbouring tile-marches hold
-// for each site (scatter_geom.hpp), in a fixed order.  TX, TY: the collision
-// tile; a: the collision launch's arguments (tiling and march depth).
+// for each site (scatter_geom.hpp), in a fixed order.  One workgroup per
+// tile (TX x TY threads) and COMBINE_PLANES consecutive planes, whose P
+// values each thread loads before it uses any (enough bytes in flight for a
+// pass this short); a: the collision launch's arguments (tiling and march
+// depth).  Only sites on a tile-march face look up halo entries.
+constexpr int COMBINE_PLANES = 4;
 template <class L, class R, int TX, int TY>
-__global__ void __launch_bounds__(256) k_combine(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
-                                                 R* __restrict__ phi, StepArgs a) {
-  const uint32_t s = blockIdx.x * 256u + threadIdx.x;
-  if (s >= a.N) return;
-  const uint32_t nxy = (uint32_t)a.nx * (uint32_t)a.ny;
-  const int z = s / nxy;
-  const uint32_t r = s - (uint32_t)z * nxy;
-  const int y = r / (uint32_t)a.nx, x = r - (uint32_t)y * a.nx;
+__global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
+                                                     R* __restrict__ phi, StepArgs a) {
+  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
+  const int zg = blockIdx.x / txy;
+  const uint32_t r = blockIdx.x - zg * txy;
+  const int ty = r / a.tiles_x, tx = r - ty * a.tiles_x;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = tx * TX + lx, y = ty * TY + ly;
+  if (x >= a.nx || y >= a.ny) return;
   HaloGeom g;
   g.TX = TX; g.TY = TY; g.zb = a.z_per_block;
   g.nx = a.nx; g.ny = a.ny; g.nz = a.nz;
@@ -1629,14 +1677,45 @@ __global__ void __launch_bounds__(256) k_combine(const R* __restrict__ part, con
   g.dims = L::D;
   g.tiles_x = a.tiles_x; g.tiles_y = a.tiles_y;
   g.marches = (a.nz + a.z_per_block - 1) / a.z_per_block;
-  R sa = part[s], sb = part[a.N + s];
-  halo_sources(g, x, y, z, [&](uint64_t e) {
-    const RPair<R> v = halo[e];
-    sa += v.a;
-    sb += v.b;
-  });
+  const int wx = g.width_x(tx), wy = g.width_y(ty);
+  const bool edge_xy = lx == 0 || lx == wx - 1 || ly == 0 || ly == wy - 1;
   const R h = (R)a.half_rho0;
-  phi[s] = (sa - sb) / (R(2) * h + (sa + sb));
+  const uint32_t nxy = (uint32_t)a.nx * (uint32_t)a.ny;
+  const int zbeg = zg * COMBINE_PLANES;
+  const int np = min(COMBINE_PLANES, a.nz - zbeg);
+  const uint32_t s0 = (uint32_t)x + (uint32_t)a.nx * (uint32_t)y + nxy * (uint32_t)zbeg;
+  R sa[COMBINE_PLANES], sb[COMBINE_PLANES], ha[COMBINE_PLANES], hb[COMBINE_PLANES];
+#pragma unroll
+  for (int k = 0; k < COMBINE_PLANES; ++k) {
+    const uint32_t s = s0 + nxy * (uint32_t)min(k, np - 1);
+    sa[k] = part[s];
+    sb[k] = part[a.N + s];
+  }
+  // the halo entries sum apart from P, so that their loads need not wait
+  // for P's
+#pragma unroll
+  for (int k = 0; k < COMBINE_PLANES; ++k) {
+    ha[k] = R(0);
+    hb[k] = R(0);
+    if (k < np) {
+      const int z = zbeg + k;
+      const int tm = z / a.z_per_block, lz = z - tm * a.z_per_block;
+      const int wz = g.width_z(tm);
+      if (edge_xy || (L::D == 3 && (lz == 0 || lz == wz - 1)))
+        halo_sources_at(g, tx, ty, tm, lx, ly, lz, wx, wy, wz, [&](uint64_t e) {
+          const RPair<R> v = halo[e];
+          ha[k] += v.a;
+          hb[k] += v.b;
+        });
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < COMBINE_PLANES; ++k) {
+    if (k < np) {
+      const R A = sa[k] + ha[k], B = sb[k] + hb[k];
+      phi[s0 + nxy * (uint32_t)k] = (A - B) / (R(2) * h + (A + B));
+    }
+  }
 }
 
 // The canonical layout (slot (i, x) = f_i(x)) of one colour block from the

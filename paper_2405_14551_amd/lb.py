@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "liblbmi.so")
+# LB_LIBRARY: a library built with other compile-time settings
+LIB_PATH = os.environ.get("LB_LIBRARY", os.path.join(PKG, "liblbmi.so"))
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENUMERIC, LB_ENODEV, LB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 LATTICE = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
@@ -23,7 +24,7 @@ NC_MODE = {"off": 0, "explicit": 1, "mlp": 2}
 STREAMING = {"two_copies": 0, "in_place": 1}
 SCHEME = {"populations": 0, "moments": 1}
 ROUNDING = {"nearest": 0, "stochastic": 1}
-PHASE_PASS = {"scatter": 0, "pass": 1}
+PHASE_PASS = {"auto": 0, "scatter": 1, "pass": 2}
 N_MOMENTS = 15
 MLP_PARAMS = 6339
 MLP_ROW = 32
@@ -158,7 +159,7 @@ def lattice_table(name):
 def make_params(lattice="D3Q27", storage="f32", nc="off", shape=(64, 64, 64), walls=(0, 0, 0),
                 tau=1.0, A=0.01, beta=0.7, rho0=1.0, body_force=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
                 nc_A=0.02, nc_hmin=2.0, nc_hmax=3.0, phi_interface=0.9, diag_every=0,
-                streaming="two_copies", tau_b=0.0, scheme="populations", rounding="nearest", phase="scatter"):
+                streaming="two_copies", tau_b=0.0, scheme="populations", rounding="nearest", phase="auto"):
     p = LbParams()
     lib().lb_params_default(ctypes.byref(p))
     p.lattice = LATTICE[lattice]
