@@ -358,6 +358,18 @@ int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int c
 int lb_nc_collect(lb_handle* h, int channel, float* rows, float* targets, long long cap,
                   long long* m_active, long long* m_free);
 
+/* lb_nc_collect for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight collection loops, harnesses that forbid
+ * hipMalloc): the same rows, targets and counts, with the per-workgroup
+ * counts and offsets in a static device array of the library (about 6 MB per
+ * GPU, held until the process ends) and their scan done on the device.  Makes
+ * no hipMalloc / hipFree call.  Lattices of at most 67,108,864 sites
+ * (LB_EINVAL beyond).  Every call on one GPU uses that GPU's array: calls
+ * that overlap on one GPU (handles on different streams or threads) race.
+ * Synchronises. */
+int lb_nc_collect_noalloc(lb_handle* h, int channel, float* rows, float* targets, long long cap,
+                          long long* m_active, long long* m_free);
+
 /* Network parameters (host pointers, n == LB_MLP_PARAMS).  Setting them
  * keeps the input ranges (initially empty: every site takes the explicit
  * scan until lb_mlp_set_ranges or lb_mlp_train sets them). */

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1534,7 +1535,102 @@ static int collect_t(lb_handle* h, float* rows, float* targets, long long cap, l
   return LB_OK;
 }
 
+// ------------------------------------------------ allocation-free collection
+// Scratch of lb_nc_collect_noalloc: per-workgroup counts (2 x uint32 per
+// workgroup of 256 sites, packed two per uint64 element), their offsets
+// (2 x uint64 per workgroup) and the two totals, for lattices of up to
+// COLLECT_MAX_BLOCKS x 256 sites.  Each GPU holds its own copy; host code
+// reaches it only through the address hipGetSymbolAddress gives on that
+// device (collect_scratch_ptr).
+constexpr uint32_t COLLECT_MAX_BLOCKS = 1u << 18;  // 67,108,864 sites
+constexpr size_t COLLECT_SCRATCH_WORDS = (size_t)COLLECT_MAX_BLOCKS + 2 * (size_t)COLLECT_MAX_BLOCKS + 2;
+static __device__ __align__(256) uint64_t scratch[COLLECT_SCRATCH_WORDS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+// the device address of this GPU's scratch array (looked up once per device,
+// with that device current)
+static int collect_scratch_ptr(int device, uint64_t** out) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(LB_EUNSUPPORTED, "device index %d beyond %d", device, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(LB_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = (uint64_t*)g_scratch_ptr[device];
+  return LB_OK;
+}
+
+template <class L, class R>
+static int collect_noalloc_t(lb_handle* h, float* rows, float* targets, long long cap, long long* m_active,
+                             long long* m_free) {
+  CollectArgs a{};
+  a.nx = h->p.nx; a.ny = h->p.ny; a.nz = h->p.nz;
+  a.wall_x = h->p.wall[0]; a.wall_y = h->p.wall[1]; a.wall_z = h->p.wall[2];
+  a.N = h->N;
+  a.phi_I = h->p.phi_interface;
+  a.inv_ncA = 1.0 / h->p.nc_A;
+  const uint32_t nblk = (h->N + 255) / 256;
+  uint64_t* base = nullptr;
+  int rc = collect_scratch_ptr(h->device, &base);
+  if (rc) return rc;
+  uint32_t* counts = (uint32_t*)base;                       // 2 x nblk uint32
+  uint64_t* offs = base + COLLECT_MAX_BLOCKS;               // 2 x nblk uint64
+  uint64_t* totals = offs + 2 * (size_t)COLLECT_MAX_BLOCKS;  // 2 uint64
+  const R* phi = (const R*)h->phi_field();
+  const R* fnc = (const R*)h->fnc;
+  // every entry the kernels read is written first in this call: counts and
+  // offsets of workgroups 0 .. nblk-1, and the totals
+  k_collect_count<L, R><<<nblk, 256, 0, h->stream>>>(phi, fnc, a, counts);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_collect_scan<<<1, 1024, 0, h->stream>>>(counts, nblk, offs, totals);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && cap > 0) {
+    k_collect_write<L, R><<<nblk, 256, 0, h->stream>>>(phi, fnc, a, offs, cap, rows, targets);
+    e = hipGetLastError();
+  }
+  uint64_t tot[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(tot, totals, sizeof tot, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(LB_EHIP, "closure row collection: %s", hipGetErrorString(e));
+  *m_active = (long long)tot[0];
+  *m_free = (long long)tot[1];
+  return LB_OK;
+}
+
 extern "C" {
+
+int lb_nc_collect_noalloc(lb_handle* h, int channel, float* rows, float* targets, long long cap,
+                          long long* m_active, long long* m_free) {
+  if (!h || !m_active || !m_free) return fail(LB_EINVAL, "NULL argument");
+  if (h->ensemble()) {
+    if (channel < 0 || channel >= (int)h->chans.size()) return fail(LB_EINVAL, "channel %d out of range", channel);
+    return lb_nc_collect_noalloc(h->chans[channel], 0, rows, targets, cap, m_active, m_free);
+  }
+  if (channel != 0) return fail(LB_EINVAL, "channel %d out of range", channel);
+  if (cap < 0 || (cap > 0 && (!rows || !targets))) return fail(LB_EINVAL, "bad output buffers");
+  if (h->d != 3) return fail(LB_EINVAL, "the learned closure is 3D only");
+  if (h->p.nc_mode != LB_NC_EXPLICIT) return fail(LB_EINVAL, "collection needs a step with LB_NC_EXPLICIT");
+  if (!h->fields_valid || h->t == 0) return fail(LB_EINVAL, "take a step first: rows come from the last step");
+  if ((h->N + 255) / 256 > COLLECT_MAX_BLOCKS)
+    return fail(LB_EINVAL, "%u sites: the allocation-free collection takes at most %u sites (its static scratch)",
+                h->N, COLLECT_MAX_BLOCKS * 256u);
+  (void)hipSetDevice(h->device);
+  const bool f64 = h->p.storage == LB_F64;
+  if (h->p.lattice == LB_D3Q19)
+    return f64 ? collect_noalloc_t<D3Q19, double>(h, rows, targets, cap, m_active, m_free)
+               : collect_noalloc_t<D3Q19, float>(h, rows, targets, cap, m_active, m_free);
+  return f64 ? collect_noalloc_t<D3Q27, double>(h, rows, targets, cap, m_active, m_free)
+             : collect_noalloc_t<D3Q27, float>(h, rows, targets, cap, m_active, m_free);
+}
 
 int lb_nc_collect(lb_handle* h, int channel, float* rows, float* targets, long long cap, long long* m_active,
                   long long* m_free) {

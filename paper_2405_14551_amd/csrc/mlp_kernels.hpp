@@ -383,4 +383,48 @@ __global__ void __launch_bounds__(256) k_collect_write(const R* __restrict__ phi
   targets[row * MLP_OUT + 2] = (float)(fnc[2 * (size_t)a.N + s] * inv / gn);
 }
 
+// Exclusive scan of the per-workgroup counts of k_collect_count on the
+// device, one workgroup of 1024 threads: offs[2b] = active rows of
+// workgroups before b, offs[2b+1] = all active rows + free rows of
+// workgroups before b (the layout k_collect_write takes); totals[0], [1] =
+// the active and free row counts.  Thread t sums a contiguous chunk of
+// workgroups, the 1024 chunk sums are scanned in LDS, and each thread then
+// writes its chunk's offsets; every sum is taken in a fixed order.
+__global__ void __launch_bounds__(1024) k_collect_scan(const uint32_t* __restrict__ counts, uint32_t nblk,
+                                                       uint64_t* __restrict__ offs, uint64_t* __restrict__ totals) {
+  __shared__ uint64_t sa[1024], sf[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (nblk + 1023) / 1024;
+  const uint32_t b0 = min(t * per, nblk), b1 = min(b0 + per, nblk);
+  uint64_t ca = 0, cf = 0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    ca += counts[2 * b];
+    cf += counts[2 * b + 1];
+  }
+  sa[t] = ca;
+  sf[t] = cf;
+  __syncthreads();
+  // inclusive scan of the chunk sums (Hillis-Steele, in place with a barrier
+  // between the read and the write of each round)
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    const uint64_t va = t >= d ? sa[t - d] : 0, vf = t >= d ? sf[t - d] : 0;
+    __syncthreads();
+    sa[t] += va;
+    sf[t] += vf;
+    __syncthreads();
+  }
+  const uint64_t na = sa[1023];
+  uint64_t ra = sa[t] - ca, rf = na + sf[t] - cf;
+  for (uint32_t b = b0; b < b1; ++b) {
+    offs[2 * b] = ra;
+    offs[2 * b + 1] = rf;
+    ra += counts[2 * b];
+    rf += counts[2 * b + 1];
+  }
+  if (t == 0) {
+    totals[0] = na;
+    totals[1] = sf[1023];
+  }
+}
+
 }  // namespace lbm

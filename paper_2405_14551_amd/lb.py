@@ -74,8 +74,8 @@ EXPORTED = [
     "lb_diagnostics", "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count",
     "lb_sync", "lb_destroy", "lb_lattice_table", "lb_error_string", "lb_last_error",
     "lb_profile_begin", "lb_profile_end", "lb_channel_count", "lb_get_tuning", "lb_set_tuning",
-    "lb_autotune", "lb_nc_collect", "lb_mlp_set_weights", "lb_mlp_get_weights", "lb_mlp_set_ranges",
-    "lb_mlp_get_ranges", "lb_mlp_train", "lb_mlp_gradient", "lb_mlp_infer",
+    "lb_autotune", "lb_nc_collect", "lb_nc_collect_noalloc", "lb_mlp_set_weights", "lb_mlp_get_weights",
+    "lb_mlp_set_ranges", "lb_mlp_get_ranges", "lb_mlp_train", "lb_mlp_gradient", "lb_mlp_infer",
 ]
 
 
@@ -113,6 +113,7 @@ def lib():
     ll = ctypes.c_longlong
     fp = P(ctypes.c_float)
     L.lb_nc_collect.argtypes = [vp, i, vp, vp, ll, P(ll), P(ll)]
+    L.lb_nc_collect_noalloc.argtypes = [vp, i, vp, vp, ll, P(ll), P(ll)]
     L.lb_mlp_set_weights.argtypes = [vp, fp, ll]
     L.lb_mlp_get_weights.argtypes = [vp, fp, ll]
     L.lb_mlp_set_ranges.argtypes = [vp, fp, fp, ctypes.c_float]
@@ -128,7 +129,7 @@ def lib():
                  "lb_state_bytes", "lb_get_state", "lb_set_state", "lb_step_count", "lb_sync",
                  "lb_destroy", "lb_lattice_table", "lb_profile_begin", "lb_profile_end",
                  "lb_channel_count", "lb_get_tuning", "lb_set_tuning", "lb_autotune", "lb_nc_collect",
-                 "lb_mlp_set_weights", "lb_mlp_get_weights", "lb_mlp_set_ranges", "lb_mlp_get_ranges",
+                 "lb_nc_collect_noalloc", "lb_mlp_set_weights", "lb_mlp_get_weights", "lb_mlp_set_ranges", "lb_mlp_get_ranges",
                  "lb_mlp_train", "lb_mlp_gradient", "lb_mlp_infer"]:
         getattr(L, name).restype = i
     _lib = L
@@ -368,6 +369,24 @@ class Simulation:
         check(L.lb_nc_collect(self.h, 0, ctypes.c_void_p(rows.data_ptr()), ctypes.c_void_p(tg.data_ptr()), m,
                               ctypes.byref(na), ctypes.byref(nf)))
         return rows[:m], tg[:m], na.value, nf.value
+
+    def nc_collect_into(self, rows, targets):
+        """Allocation-free collection into caller-owned float32 device tensors
+        rows (cap, 32) and targets (cap, 3): the library allocates no device
+        memory for it.  Rows beyond cap are not written.  Returns (m_active,
+        m_free)."""
+        if rows.dtype != self.torch.float32 or targets.dtype != self.torch.float32:
+            raise ValueError("rows and targets must be float32")
+        if not (rows.is_contiguous() and targets.is_contiguous()):
+            raise ValueError("rows and targets must be contiguous")
+        if rows.dim() != 2 or rows.shape[1] != MLP_ROW or targets.dim() != 2 or targets.shape[1] != 3 \
+                or targets.shape[0] != rows.shape[0]:
+            raise ValueError(f"expected rows (cap, {MLP_ROW}) and targets (cap, 3)")
+        na, nf = ctypes.c_longlong(), ctypes.c_longlong()
+        check(lib().lb_nc_collect_noalloc(self.h, 0, ctypes.c_void_p(rows.data_ptr()),
+                                          ctypes.c_void_p(targets.data_ptr()), rows.shape[0],
+                                          ctypes.byref(na), ctypes.byref(nf)))
+        return na.value, nf.value
 
     def mlp_set_weights(self, theta):
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(-1))

@@ -152,6 +152,7 @@ def test_closure_calls_reject_null_arguments():
     L = lb.lib()
     na, nf = ctypes.c_longlong(), ctypes.c_longlong()
     assert L.lb_nc_collect(None, 0, None, None, 0, ctypes.byref(na), ctypes.byref(nf)) == lb.LB_EINVAL
+    assert L.lb_nc_collect_noalloc(None, 0, None, None, 0, ctypes.byref(na), ctypes.byref(nf)) == lb.LB_EINVAL
     assert L.lb_mlp_set_weights(None, None, lb.MLP_PARAMS) == lb.LB_EINVAL
     assert L.lb_mlp_get_weights(None, None, lb.MLP_PARAMS) == lb.LB_EINVAL
     assert L.lb_mlp_train(None, None, None, 1, None, 1, 32, 1e-3, None) == lb.LB_EINVAL
