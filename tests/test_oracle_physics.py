@@ -2,9 +2,14 @@
 equilibrium moments, brute force on tiny lattices, translation invariance,
 the textbook single-component limit, conservation, shear-wave viscosity,
 Poiseuille flow between halfway walls, the gradient stencil's Taylor
-expansion, the Laplace law with the paper's surface tension and the
+expansion, the mirrored wall ghosts of the gradient, the Laplace law with
+the paper's surface tension (2D and 3D slopes over R = 8 .. 16), the
+near-contact force's A_h(h) on flat films in closed form and the
 near-contact coalescence criterion."""
 import math
+import multiprocessing
+import os
+from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 import pytest
@@ -301,6 +306,93 @@ def test_gradient_taylor_expansion_cubic(name):
     _ = lap
 
 
+@pytest.mark.parametrize("name,walls", [("D2Q9", (1, 0, 0)), ("D2Q9", (1, 1, 0)), ("D3Q19", (0, 0, 1)),
+                                        ("D3Q27", (1, 1, 1)), ("D3Q27", (0, 1, 0))])
+def test_gradient_wall_ghosts_linear_field(name, walls):
+    """Sec. III.D: the phase field's ghost layer mirrors the fluid across the
+    wall plane (ghost at -1-k equals fluid site k), i.e. zero normal
+    derivative on the plane halfway between the last fluid and the first
+    solid site.  For phi = a + sum_a b_a x_a the isotropy sum_i w_i c_ia c_ib =
+    delta_ab / 3 gives the closed form: g_a = b_a in the interior and on
+    periodic axes, and b_a / 2 on the first and last fluid layer of a walled
+    axis (the central difference (phi(x+1) - phi(x-1))/2 with phi(-1) =
+    phi(0)), independently per axis, corners included.  A wrapped or
+    zero-valued ghost, or a ghost mirrored about the site (phi(-1) = phi(1)),
+    fails."""
+    d = 3 if name != "D2Q9" else 2
+    n = (7, 6, 5 if d == 3 else 1)
+    p = OracleParams(lattice=name, nx=n[0], ny=n[1], nz=n[2], walls=tuple(bool(w) for w in walls))
+    sim = OracleSim(p)
+    x, y, z = [a.astype(float) for a in sim._coords()]
+    b = (0.3, -0.7, 0.45)
+    # periodic axes get no linear term (a ramp does not wrap)
+    bb = [b[a] if walls[a] else 0.0 for a in range(3)]
+    phi = 0.1 + bb[0] * x + bb[1] * y + bb[2] * z
+    g = sim.gradient(phi)
+    coords = (x, y, z)
+    for a in range(d):
+        want = np.full(sim.shape, bb[a])
+        if walls[a]:
+            edge = (coords[a] == 0) | (coords[a] == n[a] - 1)
+            want[edge] = bb[a] / 2
+        np.testing.assert_allclose(g[a], want, rtol=0, atol=1e-15)
+    if d == 2:
+        assert np.all(g[2] == 0)
+
+
+# the film profile along x of the A_h pins: phi = +1 apart from three films of
+# phase B between interface sites at phi = 1/2 (flagged, |phi| < 0.9)
+#   film h = 3: sites 5 (1/2), 6, 7 (-1), 8 (1/2)
+#   film h = 2: sites 13 (1/2), 14 (-1), 15 (1/2)
+#   film h = 4: sites 20 (1/2), 21, 22, 23 (-1), 24 (1/2)
+FILM_NX = 32
+FILM_PHI = {5: 0.5, 6: -1.0, 7: -1.0, 8: 0.5, 13: 0.5, 14: -1.0, 15: 0.5,
+            20: 0.5, 21: -1.0, 22: -1.0, 23: -1.0, 24: 0.5}
+FILM_GAP = {5: 3, 8: 3, 13: 2, 15: 2, 20: 4, 24: 4}
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("hmin,hmax", [(2.0, 3.0), (1.5, 3.0), (1.0, 2.0)])
+def test_near_contact_Ah_on_flat_films_closed_form(name, hmin, hmax):
+    """Eq. near_cont_force on flat films whose separation h is fixed by
+    construction.  The gradient of a profile phi(x) is, by the isotropy
+    sum_{c_x = 1} w_i = 1/6, g_x = (phi(x+1) - phi(x-1))/2 and g_y = g_z = 0;
+    at a film's interface site it is -1 (left) or +1 (right), and the scan
+    along -g/|g| first meets the opposing interface at s = h.  So the force is
+    F = A_h(h) g / 2 with A_h = nc_A for h <= h_min and nc_A (h_min/h)^3 above,
+    and zero for h > h_max and away from the films: at h = 3, h_min = 2 that is
+    F_x = -+ nc_A (2/3)^3 / 2.  A wrong exponent, an inverted ratio, a scan
+    that stops one site short or runs one too far, or a force along -g, fails."""
+    d = 3 if name != "D2Q9" else 2
+    nA = 0.02
+    p = OracleParams(lattice=name, nx=FILM_NX, ny=4, nz=4 if d == 3 else 1, nc=True, nc_A=nA,
+                     nc_hmin=hmin, nc_hmax=hmax)
+    sim = OracleSim(p)
+    prof = np.ones(FILM_NX)
+    for k, v in FILM_PHI.items():
+        prof[k] = v
+    phi = np.broadcast_to(prof, sim.shape).copy()
+    g = sim.gradient(phi)
+    gx_want = 0.5 * (np.roll(prof, -1) - np.roll(prof, 1))
+    np.testing.assert_allclose(g[0], np.broadcast_to(gx_want, sim.shape), rtol=0, atol=1e-15)
+    assert np.abs(g[1:]).max() < 1e-15
+    flags = np.abs(phi) < 0.9
+    F = sim.near_contact_force(phi, g, flags)
+    want = np.zeros(FILM_NX)
+    for k, h in FILM_GAP.items():
+        if h > hmax:
+            continue
+        Ah = nA if h <= hmin else nA * (hmin / h) ** 3
+        want[k] = 0.5 * Ah * gx_want[k]
+    # the numbers themselves for the default range: h = 3 -> -+0.01 * 8/27
+    if (hmin, hmax) == (2.0, 3.0):
+        assert want[5] == pytest.approx(-0.01 * 8 / 27, rel=1e-15)
+        assert want[8] == pytest.approx(0.01 * 8 / 27, rel=1e-15)
+        assert want[13] == pytest.approx(-0.01, rel=1e-15)
+    np.testing.assert_allclose(F[0], np.broadcast_to(want, sim.shape), rtol=1e-14, atol=1e-18)
+    assert np.abs(F[1:]).max() < 1e-15
+
+
 # ----------------------------------------------------------------- Laplace
 def _laplace_dp(name, R, n, steps, A=0.01, tau=1.0):
     d3 = name != "D2Q9"
@@ -334,6 +426,41 @@ def test_laplace_3d_single_radius():
     """3D: Delta p = 2 sigma / R (D3Q27), within 10% for one radius."""
     dp = _laplace_dp("D3Q27", 7.0, 26, 500)
     assert abs(dp / (2 * surface_tension(0.01, 1.0) / 7.0) - 1) < 0.10, dp
+
+
+def _laplace_3d_series(R):
+    """Delta p every 10 steps over steps 310 .. 600 for a D3Q19 droplet of
+    radius R centred in a periodic cube of side 2R + 8."""
+    n = int(2 * R + 8)
+    p = OracleParams(lattice="D3Q19", nx=n, ny=n, nz=n, tau=1.0, A=0.01, beta=0.7)
+    sim = OracleSim(p).init_droplets([(n // 2, n // 2, n // 2)], [R])
+    sim.step(300)
+    out = []
+    for _ in range(30):
+        sim.step(10)
+        fl = sim.fields()
+        rho = fl["rho_a"] + fl["rho_b"]
+        out.append((rho[fl["phi"] > 0.9].mean() - rho[fl["phi"] < -0.9].mean()) / 3.0)
+    return np.array(out)
+
+
+@pytest.mark.slow
+def test_laplace_law_3d_slope():
+    """3D: Delta p = 2 sigma / R with sigma = (4/9) A tau (Eq. sigmaA, the
+    extended Young-Laplace law at pi = 0), fitted over R = 8, 10, 12, 16: the
+    slope within 5% of 2 sigma and every radius within 3%.  A droplet started
+    from rest at uniform density oscillates (period about 80 steps at R = 16,
+    damped over several hundred); Delta p is averaged over steps 310 .. 600,
+    several periods.  The four runs go to separate processes."""
+    Rs = np.array([8.0, 10.0, 12.0, 16.0])
+    workers = max(1, min(4, os.cpu_count() or 1))
+    with ProcessPoolExecutor(workers, mp_context=multiprocessing.get_context("fork")) as ex:
+        series = list(ex.map(_laplace_3d_series, Rs))
+    dps = np.array([s.mean() for s in series])
+    sigma = surface_tension(0.01, 1.0)
+    slope, icpt = np.polyfit(1 / Rs, dps, 1)
+    assert abs(slope / (2 * sigma) - 1) < 0.05, (slope, 2 * sigma, dps)
+    np.testing.assert_allclose(dps * Rs / (2 * sigma), 1.0, rtol=0.03)
 
 
 # -------------------------------------------------------------- near contact
