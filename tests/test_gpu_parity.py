@@ -596,6 +596,97 @@ def test_stochastic_rounding_full_size_sampled_sites(storage, frac_bits):
     sim.close()
 
 
+def _half_step(v, frac_bits, min_exp):
+    """Half the spacing of a binary format with ``frac_bits`` fraction bits
+    and smallest normal exponent ``min_exp`` at the value v (subnormals keep
+    the spacing of the smallest binade)."""
+    e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** min_exp)))
+    return 2.0 ** (e - frac_bits - 1)
+
+
+@pytest.mark.parametrize("storage,frac_bits,min_exp", [("f16t", 10, -14), ("bf16t", 7, -126),
+                                                       ("f16", 10, -14), ("bf16", 7, -126)])
+def test_rounded_16bit_full_size_sampled_sites(storage, frac_bits, min_exp):
+    """The channel workload in a 16-bit storage rounded to nearest (Sec.
+    IV.A, Eqs. shift_f, shift-lbm): one GPU step from a developed state
+    against the oracle's windowed step on the colours the stored values
+    define.  Total layouts store T_i = f*_i - w_i rho0; the per-colour
+    layouts store f^k_i - w_i rho0 / 2.  Each stored value is the oracle's
+    value rounded to the format: within half a step of it, plus the FP32
+    arithmetic's 2e-6 of the population scale.
+
+    Per-colour 16-bit storage leaves the absent colour at a density of about
+    1e-4 in the bulk (its populations are stored to 2^-11 of w_i / 2), so
+    the recolouring there has a weight beta rho_A rho_B / rho of about 1e-4,
+    while the bulk's colour gradient can be as small as the FP32 rounding of
+    the phase field (1e-7): its direction, and with it the sign of the
+    recolouring term, is then decided by rounding, differently in FP32 and
+    FP64 (the same effect as at symmetric points).  In the bulk (|phi| >
+    0.99) the bound therefore adds the recolouring term's full range,
+    2 beta |rho_A rho_B| / rho w_i / |c_i|."""
+    from oracle.lattice import make_lattice
+    w = W.channel_3d(storage=storage)
+    kw, cen, rad = W.sim_kwargs(w)
+    total = storage.endswith("t")
+    say(f"case rounded 16-bit channel full size {storage}")
+    sim = lb.Simulation(**kw).init_droplets(cen, rad)
+    sim.step(30)
+    wq = make_lattice("D3Q27").w
+    w4 = wq.reshape(-1, 1, 1, 1)
+    if total:
+        sA, sB = total_to_colours(sim, sim.get_state())
+    else:
+        s0 = sim.get_state().double().cpu().numpy()
+        sA, sB = s0[0] + 0.5 * w4, s0[1] + 0.5 * w4
+        del s0
+    sim.step(1)
+    if total:
+        Tn, _ = sim.split_total_state(sim.get_state())
+        Sn = (total_T(sim, Tn),)
+    else:
+        s1 = sim.get_state().double().cpu().numpy()
+        Sn = (s1[0], s1[1])
+    nx, ny, nz = kw["shape"]
+    rng = np.random.default_rng(10)
+    g = gpu_fields(sim, ("f_nc", "flags", "u", "phi"))
+    fnc_sites = np.argwhere(np.abs(g["f_nc"]).sum(0) > 0)
+    assert len(fnc_sites) > 0
+    sites = [tuple(int(v) for v in fnc_sites[j][::-1])
+             for j in rng.choice(len(fnc_sites), size=min(12, len(fnc_sites)), replace=False)]
+    sites += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (63, 3, 7), (64, 4, 8), (200, 1, 1)]
+    for _ in range(24):
+        sites.append((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    p = oparams(kw, np.float32)
+    L = make_lattice("D3Q27")
+    inv_c = np.where(L.cnorm > 0, 1.0 / np.where(L.cnorm > 0, L.cnorm, 1.0), 0.0)
+    worst, exact, n, n_bulk = 0.0, 0, 0, 0
+    for (x, y, z) in sites:
+        a, b, ofl = step_window(p, sA, sB, (x, y, z))
+        want = (a + b - wq,) if total else (a - 0.5 * wq, b - 0.5 * wq)
+        slack = np.zeros_like(wq)
+        if not total and abs(float(ofl["phi"])) > 0.99:
+            ra, rb = float(ofl["rho_a"]), float(ofl["rho_b"])
+            slack = 2.0 * kw["beta"] * abs(ra * rb) / (ra + rb) * wq * inv_c
+            n_bulk += 1
+        for got_all, v in zip(Sn, want):
+            d = np.abs(got_all[:, z, y, x] - v)
+            excess = (d - _half_step(v, frac_bits, min_exp) - slack) / np.abs(a + b).max()
+            worst = max(worst, float(excess.max()))
+            if not np.all(excess < 2e-6):
+                i = int(np.argmax(excess))
+                raise AssertionError(f"site {(x, y, z)} direction {i}: stored {got_all[i, z, y, x]!r}, "
+                                     f"oracle {v[i]!r}, half step {_half_step(v, frac_bits, min_exp)[i]!r}, "
+                                     f"excess {excess[i]:.3e} of the population scale {np.abs(a + b).max():.4f}; "
+                                     f"f_nc {g['f_nc'][:, z, y, x]} (oracle {ofl['f_nc']}), flags "
+                                     f"{g['flags'][z, y, x]} (oracle {ofl['flags']}), u {g['u'][:, z, y, x]} "
+                                     f"(oracle {ofl['u']}), phi {g['phi'][z, y, x]!r} (oracle {ofl['phi']!r})")
+            exact += int((d <= _half_step(v, frac_bits, min_exp)).sum())
+            n += d.size
+    say(f"  {storage}: sampled {len(sites)} sites ({n_bulk} in the bulk), {n} stored values, {exact} within "
+        f"half a step, worst excess {worst:.2e}")
+    sim.close()
+
+
 def test_total_layout_checkpoint_roundtrip():
     w = W.channel_3d(storage="f16t", shape=(64, 40, 32), count=6, radius=6.0)
     kw, cen, rad = W.sim_kwargs(w)
