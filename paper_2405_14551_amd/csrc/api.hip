@@ -508,7 +508,10 @@ static int ro_plan(lb_handle* h) {
     // the grid runs in one round.  The march depth fixes which sums the
     // combine pass adds (tile-march edges), so both streaming modes use the
     // same rule and give the same results bit for bit.
-    if (bxy * ((p.nz + zb - 1) / zb) <= 1024 && 2 * zb <= p.nz) zb *= 2;
+#ifndef LB_RO_DOUBLE
+#define LB_RO_DOUBLE 1
+#endif
+    if (LB_RO_DOUBLE && bxy * ((p.nz + zb - 1) / zb) <= 1024 && 2 * zb <= p.nz) zb *= 2;
   }
   if (zb > p.nz) zb = p.nz;
   h->ro_zb = (int)zb;

@@ -116,7 +116,9 @@ struct Launch {
     b.tiles_x = (a.nx + TILE_X - 1) / TILE_X;
     b.tiles_y = (a.ny + TILE_Y - 1) / TILE_Y;
     dim3 block(TILE_X, TILE_Y, 1);
-    dim3 grid((unsigned)b.tiles_x * b.tiles_y * ((a.nz + COMBINE_PLANES - 1) / COMBINE_PLANES));
+    const unsigned marches = (unsigned)((a.nz + a.z_per_block - 1) / a.z_per_block);
+    const unsigned groups = (unsigned)((a.z_per_block + COMBINE_PLANES - 1) / COMBINE_PLANES);
+    dim3 grid((unsigned)b.tiles_x, (unsigned)b.tiles_y, marches * groups);
     if (st == ST_F64)
       k_combine<L, double, TILE_X, TILE_Y><<<grid, block, 0, s>>>((const double*)ro.part,
                                                                   (const RPair<double>*)ro.halo, (double*)phi, b);

@@ -274,6 +274,7 @@ __device__ __forceinline__ uint32_t xcd_tile_index(uint32_t b, uint32_t nb) {
 // tile t of a lattice cut into TX x TY columns and z-blocks (x fastest)
 struct TileCoord {
   int x0, y0, z0, z1;
+  int tx, ty, tm;  // tile and march indices
 };
 __device__ __forceinline__ TileCoord tile_coord(uint32_t t, const StepArgs& a, int TX, int TY) {
   const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
@@ -285,6 +286,9 @@ __device__ __forceinline__ TileCoord tile_coord(uint32_t t, const StepArgs& a, i
   c.y0 = tyi * TY;
   c.z0 = zb * a.z_per_block;
   c.z1 = min(c.z0 + a.z_per_block, a.nz);
+  c.tx = txi;
+  c.ty = tyi;
+  c.tm = zb;
   return c;
 }
 
@@ -893,6 +897,7 @@ struct ScatterSmem {
   RPair<R> xrow[3][2][T::TY][T::TX];  // [cz+1][cy=-1: 0, +1: 1][row][lane]: row sums that change row
   RPair<R> xsp[3][3][T::TY][2];       // [cz+1][cy+1][row][0: lane 0 along -x, 1: last lane along +x]
   RPair<R> racc[3][RING];             // ring accumulators, plane p in slot (p + 3) % 3
+  uint64_t side_e0[RING];             // a ring thread's halo entry on the march's first plane
 };
 template <class T, class R, bool RO>
 struct ScatterLds {};
@@ -1021,8 +1026,7 @@ struct CollideSmem<L, S, T, TOT, true, RO> : CollideSmem<L, S, T, TOT, false, RO
 // takes part (lanes outside the lattice compute on a clamped site and store
 // nothing).  RO: the read-once scatter, which also needs every lane (the DPP
 // shifts read neighbouring lanes).  STREAM selects two-copy or in-place
-// streaming (fin == fout for the in-place kinds).  tile_id: the tile's index
-// in the launch (RO: its halo block).  BOOT (with RO): no collision; the
+// streaming (fin == fout for the in-place kinds).  BOOT (with RO): no collision; the
 // stored state at fin (canonical layout, total layout's scalars at scout) is
 // scattered exactly as the collision pass that stored it would have
 // scattered it, which starts the read-once step after an initialisation or a
@@ -1034,7 +1038,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
                                              float* __restrict__ scout,
                                              const FieldPtrs& fo, const StepArgs& a, const TileCoord& tc,
                                              CollideSmem<L, S, T, TOT, MLP, RO>& sm,
-                                             const MlpPacked* __restrict__ net = nullptr, uint32_t tile_id = 0,
+                                             const MlpPacked* __restrict__ net = nullptr,
                                              ScatterOut sout = ScatterOut{nullptr, nullptr}) {
   static_assert(!MLP || (NC && L::D == 3), "the learned closure replaces the 3D near-contact scan");
   static_assert(!RO || (T::TX == 64), "the read-once scatter shifts along one 64-lane wave per row");
@@ -1051,15 +1055,23 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   [[maybe_unused]] int rhx = 0, rhy = 0;
   [[maybe_unused]] bool ring_ok = false;
   [[maybe_unused]] HaloGeom geo;
-  [[maybe_unused]] RPair<R>* halo_blk = nullptr;
+  [[maybe_unused]] RPair<R>* halo = nullptr;
   [[maybe_unused]] R* part = nullptr;
   [[maybe_unused]] R accA[3] = {0, 0, 0}, accB[3] = {0, 0, 0};
   if constexpr (RO) {
     geo = launch_geom<T>(a, L::D);
-    halo_blk = (RPair<R>*)sout.halo + (uint64_t)tile_id * geo.stride();
+    halo = (RPair<R>*)sout.halo;
     part = (R*)sout.part;
     constexpr int RING = ScatterSmem<T, R>::RING;
     ring_ok = tid < RING && geo.ring_pos(tid, wx, wy, rhx, rhy);
+    // in-plane rim positions: the receiving tile's side slot on plane 0
+    // (positions past a wall send nothing)
+    // (held in LDS: registers are the scarce resource of this pass)
+    if (ring_ok) {
+      uint64_t e = 0;
+      ring_ok = send_entry(geo, tc.tx, tc.ty, tc.tm, wx, wy, rhx, rhy, 0, 0, e);
+      sm.scat.side_e0[tid] = e;
+    }
     if (tid < RING)
       for (int c = 0; c < 3; ++c) sm.scat.racc[c][tid] = RPair<R>{0, 0};
     // spills of classes without an x-moving velocity (D3Q19 corners) stay zero
@@ -1096,17 +1108,25 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
   constexpr int LCP = STREAM == STREAM_EVEN ? LB_INPLACE_LOAD_CPOL_EVEN
                                             : (STREAM == STREAM_ODD ? LB_INPLACE_LOAD_CPOL_ODD : 0);
 
-  // RO: the ring threads' densities of plane zd go to the halo block
+  // RO: the ring threads' densities of plane zd go to the halo blocks of the
+  // tile-marches that own those sites
   [[maybe_unused]] auto ring_emit = [&](int zd, bool cap_lo_, bool cap_hi_) {
     if constexpr (RO) {
       if (tid < ScatterSmem<T, R>::RING) {
         RPair<R>& acc = sm.scat.racc[(zd + 3) % 3][tid];
-        if (ring_ok) {
-          uint32_t e;
-          if (cap_lo_) e = geo.cap_lo(rhx, rhy);
-          else if (cap_hi_) e = geo.cap_hi(rhx, rhy);
-          else e = geo.side(zd - z0, tid);
-          halo_blk[e] = acc;
+        if (cap_lo_ || cap_hi_) {
+          // the cap planes' owners lie in the same tile column as the
+          // in-plane owner, one march down or up: the same slot in the cap
+          // set, whose slots follow the TX x TY own columns (a rim position
+          // whose in-plane owner lies past a wall has none on the cap planes)
+          const int nm = neighbour_tile(tc.tm, cap_lo_ ? -1 : 1, geo.marches, geo.wall_z);
+          if (ring_ok && nm >= 0) {
+            const int64_t d = (int64_t)(nm - tc.tm) * geo.tiles_x * geo.tiles_y * geo.stride() -
+                              2 * geo.cap() + (cap_lo_ ? geo.cap() : 0) + geo.TX * geo.TY;
+            halo[(uint64_t)((int64_t)sm.scat.side_e0[tid] + d)] = acc;
+          }
+        } else if (ring_ok) {
+          halo[sm.scat.side_e0[tid] + (uint64_t)(zd - z0) * (uint64_t)geo.ring()] = acc;
         }
         acc = RPair<R>{0, 0};
       }
@@ -1564,7 +1584,11 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       // plane's lower neighbour plane to the halo block), then rotate
       if constexpr (L::D == 3) {
         if (z == z0) {
-          if (valid_xy) halo_blk[geo.cap_lo(tx + 1, ty + 1)] = RPair<R>{accA[0], accB[0]};
+          // the plane below the march: the own columns of the march below
+          const int nm = neighbour_tile(tc.tm, -1, geo.marches, geo.wall_z);
+          if (valid_xy && nm >= 0)
+            halo[(uint64_t)geo.tile_index(tc.tx, tc.ty, nm) * geo.stride() + geo.from_above(geo.slot(0, 0, tx, ty, true))] =
+                RPair<R>{accA[0], accB[0]};
           ring_emit(z - 1, true, false);
         } else {
           if (valid_xy) {
@@ -1592,7 +1616,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
     }
     ring_emit(zl, false, false);
     if constexpr (L::D == 3) {
-      if (valid_xy) halo_blk[geo.cap_hi(tx + 1, ty + 1)] = RPair<R>{accA[1], accB[1]};
+      const int nm = neighbour_tile(tc.tm, 1, geo.marches, geo.wall_z);
+      if (valid_xy && nm >= 0)
+        halo[(uint64_t)geo.tile_index(tc.tx, tc.ty, nm) * geo.stride() + geo.from_below(geo.slot(0, 0, tx, ty, true))] =
+            RPair<R>{accA[1], accB[1]};
       ring_emit(z1, false, true);
     }
   }
@@ -1623,7 +1650,7 @@ __global__ void __launch_bounds__(T::NT, (collide_min_waves<S, TOT, RO>())) k_co
   __shared__ CollideSmem<L, S, T, TOT, false, RO> sm;
   const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
   const TileCoord tc = tile_coord(t, a, T::TX, T::TY);
-  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM, SR, RO>(fin, fout, phi, scout, fo, a, tc, sm, nullptr, t, sout);
+  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM, SR, RO>(fin, fout, phi, scout, fo, a, tc, sm, nullptr, sout);
 }
 
 // collision pass with the learned near-contact closure
@@ -1636,7 +1663,7 @@ __global__ void __launch_bounds__(T::NT, 3) k_collide_mlp(const S* __restrict__ 
   __shared__ CollideSmem<L, S, T, TOT, true, RO> sm;
   const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
   const TileCoord tc = tile_coord(t, a, T::TX, T::TY);
-  collide_tile<L, S, T, true, FIELDS, TOT, true, STREAM, false, RO>(fin, fout, phi, scout, fo, a, tc, sm, net, t, sout);
+  collide_tile<L, S, T, true, FIELDS, TOT, true, STREAM, false, RO>(fin, fout, phi, scout, fo, a, tc, sm, net, sout);
 }
 
 // Bootstrap of the read-once step: the scatter of a stored state (canonical
@@ -1649,27 +1676,33 @@ __global__ void __launch_bounds__(T::NT) k_boot_scatter(const S* __restrict__ f,
   const uint32_t t = xcd_tile_index(blockIdx.x, gridDim.x);
   const TileCoord tc = tile_coord(t, a, T::TX, T::TY);
   collide_tile<L, S, T, false, false, TOT, false, STREAM_AB, false, true, true>(
-      f, nullptr, nullptr, const_cast<float*>(sc), FieldPtrs{}, a, tc, sm, nullptr, t, sout);
+      f, nullptr, nullptr, const_cast<float*>(sc), FieldPtrs{}, a, tc, sm, nullptr, sout);
 }
 
-// Read-once step, second launch: the next step's phase field from the
-// partial densities P and the halo entries the neighbouring tile-marches hold
-// for each site (scatter_geom.hpp), in a fixed order.  One workgroup per
-// tile (TX x TY threads) and COMBINE_PLANES consecutive planes, whose P
-// values each thread loads before it uses any (enough bytes in flight for a
-// pass this short); a: the collision launch's arguments (tiling and march
-// depth).  Only sites on a tile-march face look up halo entries.
+// Combine pass of the read-once step: phi of every site from its partial
+// densities P and the halo entries its neighbours wrote into its tile-march's
+// block (receive layout, scatter_geom.hpp), each sum in the fixed order of
+// halo_sources_at.  The grid is the collision launch's tiling (a: its tiles
+// and march depth): block (tx, ty, tm * G + j) takes planes j CP ..
+// j CP + CP - 1 of march tm (G = ceil(march depth / CP)), one thread per
+// column of the tile.  The block's side slots of those planes (contiguous)
+// and, on a march's first and last plane, its cap sets are staged in LDS by
+// all threads with coalesced loads; the rim threads then add their slots
+// from LDS.  The CP planes' P values are loaded first.
 constexpr int COMBINE_PLANES = 4;
 template <class L, class R, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
                                                      R* __restrict__ phi, StepArgs a) {
-  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
-  const int zg = blockIdx.x / txy;
-  const uint32_t r = blockIdx.x - zg * txy;
-  const int ty = r / a.tiles_x, tx = r - ty * a.tiles_x;
-  const int lx = threadIdx.x, ly = threadIdx.y;
+  constexpr int CP = COMBINE_PLANES;
+  constexpr int NT = TX * TY;
+  constexpr int RING = 2 * TX + 2 * TY + 4, CAP = (TX + 2) * (TY + 2);
+  __shared__ RPair<R> hs_side[CP * RING];
+  __shared__ RPair<R> hs_cap[2][CAP];
+  const int tx = blockIdx.x, ty = blockIdx.y;
+  const int G = (a.z_per_block + CP - 1) / CP;
+  const int tm = blockIdx.z / G, j = blockIdx.z - tm * G;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + TX * ly;
   const int x = tx * TX + lx, y = ty * TY + ly;
-  if (x >= a.nx || y >= a.ny) return;
   HaloGeom g;
   g.TX = TX; g.TY = TY; g.zb = a.z_per_block;
   g.nx = a.nx; g.ny = a.ny; g.nz = a.nz;
@@ -1677,40 +1710,65 @@ __global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part,
   g.dims = L::D;
   g.tiles_x = a.tiles_x; g.tiles_y = a.tiles_y;
   g.marches = (a.nz + a.z_per_block - 1) / a.z_per_block;
-  const int wx = g.width_x(tx), wy = g.width_y(ty);
-  const bool edge_xy = lx == 0 || lx == wx - 1 || ly == 0 || ly == wy - 1;
-  const R h = (R)a.half_rho0;
+  const int wx = g.width_x(tx), wy = g.width_y(ty), wz = g.width_z(tm);
+  const int lz0 = j * CP;
+  if (lz0 >= wz) return;  // (uniform over the block)
+  const int np = min(CP, wz - lz0);
+  const bool valid = x < a.nx && y < a.ny;
   const uint32_t nxy = (uint32_t)a.nx * (uint32_t)a.ny;
-  const int zbeg = zg * COMBINE_PLANES;
-  const int np = min(COMBINE_PLANES, a.nz - zbeg);
-  const uint32_t s0 = (uint32_t)x + (uint32_t)a.nx * (uint32_t)y + nxy * (uint32_t)zbeg;
-  R sa[COMBINE_PLANES], sb[COMBINE_PLANES], ha[COMBINE_PLANES], hb[COMBINE_PLANES];
+  const uint32_t s0 = (uint32_t)min(x, a.nx - 1) + (uint32_t)a.nx * (uint32_t)min(y, a.ny - 1) +
+                      nxy * (uint32_t)(tm * a.z_per_block + lz0);
+  R sa[CP], sb[CP];
 #pragma unroll
-  for (int k = 0; k < COMBINE_PLANES; ++k) {
+  for (int k = 0; k < CP; ++k) {
     const uint32_t s = s0 + nxy * (uint32_t)min(k, np - 1);
     sa[k] = part[s];
     sb[k] = part[a.N + s];
   }
-  // the halo entries sum apart from P, so that their loads need not wait
-  // for P's
+  // stage the block's slots of these planes
+  const uint64_t base = (uint64_t)g.tile_index(tx, ty, tm) * g.stride();
+  const bool first = L::D == 3 && lz0 == 0 && neighbour_tile(tm, -1, g.marches, g.wall_z) >= 0;
+  const bool last = L::D == 3 && lz0 + np == wz && neighbour_tile(tm, 1, g.marches, g.wall_z) >= 0;
+  {
+    const RPair<R>* src = halo + base + g.side(lz0, 0);
+    for (int k = tid; k < np * RING; k += NT) hs_side[k] = src[k];
+    if (first)
+      for (int k = tid; k < CAP; k += NT) hs_cap[0][k] = halo[base + g.from_below(k)];
+    if (last)
+      for (int k = tid; k < CAP; k += NT) hs_cap[1][k] = halo[base + g.from_above(k)];
+  }
+  __syncthreads();
+  if (!valid) return;
+  R ha[CP], hb[CP];
 #pragma unroll
-  for (int k = 0; k < COMBINE_PLANES; ++k) {
-    ha[k] = R(0);
-    hb[k] = R(0);
+  for (int k = 0; k < CP; ++k) {
+    const int lz = lz0 + k;
+    R A = R(0), B = R(0);
     if (k < np) {
-      const int z = zbeg + k;
-      const int tm = z / a.z_per_block, lz = z - tm * a.z_per_block;
-      const int wz = g.width_z(tm);
-      if (edge_xy || (L::D == 3 && (lz == 0 || lz == wz - 1)))
-        halo_sources_at(g, tx, ty, tm, lx, ly, lz, wx, wy, wz, [&](uint64_t e) {
-          const RPair<R> v = halo[e];
-          ha[k] += v.a;
-          hb[k] += v.b;
+      if (lz == 0 && first)
+        halo_group_at(g, tx, ty, tm, lx, ly, wx, wy, -1, [&](int, uint64_t e) {
+          const RPair<R> v = hs_cap[0][e - base - g.from_below(0)];
+          A += v.a;
+          B += v.b;
+        });
+      halo_group_at(g, tx, ty, tm, lx, ly, wx, wy, 0, [&](int, uint64_t e) {
+        const RPair<R> v = hs_side[k * RING + (int)(e - base - g.side(0, 0))];
+        A += v.a;
+        B += v.b;
+      });
+      if (lz == wz - 1 && last)
+        halo_group_at(g, tx, ty, tm, lx, ly, wx, wy, 1, [&](int, uint64_t e) {
+          const RPair<R> v = hs_cap[1][e - base - g.from_above(0)];
+          A += v.a;
+          B += v.b;
         });
     }
+    ha[k] = A;
+    hb[k] = B;
   }
+  const R h = (R)a.half_rho0;
 #pragma unroll
-  for (int k = 0; k < COMBINE_PLANES; ++k) {
+  for (int k = 0; k < CP; ++k) {
     if (k < np) {
       const R A = sa[k] + ha[k], B = sb[k] + hb[k];
       phi[s0 + nxy * (uint32_t)k] = (A - B) / (R(2) * h + (A + B));

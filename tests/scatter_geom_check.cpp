@@ -3,10 +3,13 @@
 // For a lattice of the given size, walls, tile extent and march depth, every
 // site sends one integer value per direction to the site that pulls it at the
 // next step (x + c_i, or itself when x + c_i is solid).  A tile-march keeps
-// the values landing on its own sites in P and the others in its halo block,
-// indexed as the collision kernel indexes them; the combine rule then adds
-// each site's halo entries.  The result must equal the direct pull sum of the
-// same values at every site, and every halo index must stay inside its block.
+// the values landing on its own sites in P and sends the others to the halo
+// array, into the block of the tile-march that owns the destination, as the
+// collision kernel indexes them; the combine rule then adds each site's halo
+// entries.  The result must equal the direct pull sum of the same values at
+// every site, every halo index must stay inside the array, and no entry may
+// receive values from two different box positions (the kernel stores, it does
+// not add).
 // Prints "ok" or the first mismatch; exit status 0 on success.
 #include <cstdio>
 #include <cstdlib>
@@ -47,6 +50,7 @@ int main(int argc, char** argv) {
   auto site = [&](int x, int y, int z) { return (long)x + (long)g.nx * (y + (long)g.ny * z); };
   auto val = [&](long s, int i) { return (long long)((s * 131 + i * 7919) % 1000003); };
   std::vector<long long> P(N, 0), H(g.entries(), 0), truth(N, 0);
+  std::vector<long long> owner(g.entries(), -1);
   std::vector<char> owned(N, 0);
   const int n[3] = {g.nx, g.ny, g.nz};
   const int wall[3] = {g.wall_x, g.wall_y, g.wall_z};
@@ -85,7 +89,7 @@ int main(int argc, char** argv) {
       for (int tx = 0; tx < g.tiles_x; ++tx) {
         const int x0 = tx * g.TX, y0 = ty * g.TY, z0 = tm * g.zb;
         const int wx = g.width_x(tx), wy = g.width_y(ty), wz = g.width_z(tm);
-        const uint64_t base = (uint64_t)g.tile_index(tx, ty, tm) * g.stride();
+        const long long tid = g.tile_index(tx, ty, tm);
         for (int lz = 0; lz < wz; ++lz)
           for (int ly = 0; ly < wy; ++ly)
             for (int lx = 0; lx < wx; ++lx) {
@@ -106,20 +110,29 @@ int main(int argc, char** argv) {
                   P[site(d[0], d[1], d[2])] += val(s, i);
                   continue;
                 }
-                uint32_t e;
-                if (hz == 0) e = g.cap_lo(hx, hy);
-                else if (hz == wz + 1) e = g.cap_hi(hx, hy);
-                else {
-                  const int r = g.ring_index(hx, hy, wx, wy);
-                  int hx2, hy2;
-                  if (!g.ring_pos(r, wx, wy, hx2, hy2) || hx2 != hx || hy2 != hy) {
-                    std::printf("ring index %d of (%d, %d) does not invert\n", r, hx, hy);
-                    return 1;
+                const int dz = hz == 0 ? -1 : (hz == wz + 1 ? 1 : 0);
+                if (dz == 0) {
+                  // the rim position is one a ring thread holds
+                  bool found = false;
+                  for (int r = 0; r < 2 * (g.TX + 2) + 2 * g.TY && !found; ++r) {
+                    int hx2, hy2;
+                    if (g.ring_pos(r, wx, wy, hx2, hy2) && hx2 == hx && hy2 == hy) found = true;
                   }
-                  e = g.side(hz - 1, r);
+                  if (!found) { std::printf("rim position (%d, %d) held by no ring thread\n", hx, hy); return 1; }
                 }
-                if (e >= g.stride()) { std::printf("halo entry %u beyond the block (%u)\n", e, g.stride()); return 1; }
-                H[base + e] += val(s, i);
+                uint64_t e;
+                if (!send_entry(g, tx, ty, tm, wx, wy, hx, hy, dz, hz - 1, e)) {
+                  std::printf("value for (%d, %d, %d) sent nowhere\n", d[0], d[1], d[2]);
+                  return 1;
+                }
+                if (e >= g.entries()) { std::printf("halo entry %llu beyond the array\n", (unsigned long long)e); return 1; }
+                const long long key = ((tid * (g.TX + 2) + hx) * (g.TY + 2) + hy) * (g.zb + 2) + hz;
+                if (owner[e] >= 0 && owner[e] != key) {
+                  std::printf("halo entry %llu written from two box positions\n", (unsigned long long)e);
+                  return 1;
+                }
+                owner[e] = key;
+                H[e] += val(s, i);
               }
             }
       }
