@@ -473,6 +473,18 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
   if (h->ro) {
     ALLOC(h->phi2, N * h->rsize);
     ALLOC(h->ro_part, 2 * N * h->rsize);
+    // the read-once collision with FP32 arithmetic measured fastest with
+    // about 2048 workgroups, half the march depth of the rule above (256 x
+    // 128 x 128 channel: per-colour FP32 step 0.4616 -> 0.4478 ms, FP32 total
+    // layout 0.3272 -> 0.3029 ms; FP64 was fastest at 16 planes)
+    if (h->rsize == 4 && !std::getenv("LB_Z_PER_BLOCK")) {
+      const long bxy = (long)((p->nx + TILE_X - 1) / TILE_X) * ((p->ny + TILE_Y - 1) / TILE_Y);
+      long zb = (bxy * p->nz) / 2048;
+      if (zb < 1) zb = 1;
+      if (zb > 16) zb = 16;
+      if (zb > p->nz) zb = p->nz;
+      h->z_per_block = (int)zb;
+    }
   }
   ALLOC(h->rho_a, N * h->rsize);
   ALLOC(h->rho_b, N * h->rsize);
@@ -497,22 +509,11 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
 // (scatter_geom.hpp); grows the halo buffer when the depth needs more
 static int ro_plan(lb_handle* h) {
   const lb_params& p = h->p;
+  // the handle's march depth as it is (the default is chosen for the
+  // read-once pass at create).  The depth fixes which sums the combine pass
+  // adds (tile-march edges), so both streaming modes take the same one and
+  // give the same results bit for bit.
   long zb = h->z_per_block;
-  const long bxy = (long)((p.nx + TILE_X - 1) / TILE_X) * ((p.ny + TILE_Y - 1) / TILE_Y);
-  if (p.nc_mode == LB_NC_MLP) {
-    // the closure pass holds the network in LDS and runs three workgroups
-    // per CU; it measured faster with half the march depth
-    zb = zb > 1 ? zb / 2 : 1;
-  } else if (storage_bytes(p.storage) == 4 && !total_layout(p.storage)) {
-    // small grids (at most 1024 workgroups): marches twice as long, so that
-    // the grid runs in one round.  The march depth fixes which sums the
-    // combine pass adds (tile-march edges), so both streaming modes use the
-    // same rule and give the same results bit for bit.
-#ifndef LB_RO_DOUBLE
-#define LB_RO_DOUBLE 1
-#endif
-    if (LB_RO_DOUBLE && bxy * ((p.nz + zb - 1) / zb) <= 1024 && 2 * zb <= p.nz) zb *= 2;
-  }
   if (zb > p.nz) zb = p.nz;
   h->ro_zb = (int)zb;
   HaloGeom g{};
