@@ -119,12 +119,17 @@ struct Launch {
     const unsigned marches = (unsigned)((a.nz + a.z_per_block - 1) / a.z_per_block);
     const unsigned groups = (unsigned)((a.z_per_block + COMBINE_PLANES - 1) / COMBINE_PLANES);
     dim3 grid((unsigned)b.tiles_x, (unsigned)b.tiles_y, marches * groups);
+    // per-colour FP64 / FP32 storage scatter the stored populations
+    // themselves; every other layout scatters shifted values
     if (st == ST_F64)
-      k_combine<L, double, TILE_X, TILE_Y><<<grid, block, 0, s>>>((const double*)ro.part,
-                                                                  (const RPair<double>*)ro.halo, (double*)phi, b);
+      k_combine<L, double, TILE_X, TILE_Y, false><<<grid, block, 0, s>>>((const double*)ro.part,
+                                                                         (const RPair<double>*)ro.halo, (double*)phi, b);
+    else if (st == ST_F32)
+      k_combine<L, float, TILE_X, TILE_Y, false><<<grid, block, 0, s>>>((const float*)ro.part,
+                                                                        (const RPair<float>*)ro.halo, (float*)phi, b);
     else
-      k_combine<L, float, TILE_X, TILE_Y><<<grid, block, 0, s>>>((const float*)ro.part,
-                                                                 (const RPair<float>*)ro.halo, (float*)phi, b);
+      k_combine<L, float, TILE_X, TILE_Y, true><<<grid, block, 0, s>>>((const float*)ro.part,
+                                                                       (const RPair<float>*)ro.halo, (float*)phi, b);
     return hipGetLastError();
   }
 

@@ -99,6 +99,15 @@ struct Storage<double> {
   // the shifted value a load returns after bstore<I>(d)
   template <int I, class L>
   __device__ static __forceinline__ double rt(double d, double h) { return shift_down<I, L>(shift_up<I, L>(d, h), h); }
+  // the number stored for d (f itself, not shifted) and that number as a load
+  // returns it, for the read-once scatter's sums
+  static constexpr bool kStoredShifted = false;
+  template <int I, class L>
+  __device__ static __forceinline__ double stored(double d, double h) { return shift_up<I, L>(d, h); }
+  template <int I, class L>
+  __device__ static __forceinline__ double bload_stored(__amdgpu_buffer_rsrc_t r, uint32_t vo) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, 0));
+  }
   template <int I, class L>
   __device__ static __forceinline__ void store(double* p, double d, double h) {
     __builtin_nontemporal_store(shift_up<I, L>(d, h), p);
@@ -121,6 +130,13 @@ struct Storage<float> {
   __device__ static __forceinline__ float load(const float* p, float h) { return shift_down<I, L>(*p, h); }
   template <int I, class L>
   __device__ static __forceinline__ float rt(float d, float h) { return shift_down<I, L>(shift_up<I, L>(d, h), h); }
+  static constexpr bool kStoredShifted = false;
+  template <int I, class L>
+  __device__ static __forceinline__ float stored(float d, float h) { return shift_up<I, L>(d, h); }
+  template <int I, class L>
+  __device__ static __forceinline__ float bload_stored(__amdgpu_buffer_rsrc_t r, uint32_t vo) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, 0));
+  }
   template <int I, class L>
   __device__ static __forceinline__ void store(float* p, float d, float h) {
     __builtin_nontemporal_store(shift_up<I, L>(d, h), p);
@@ -143,6 +159,13 @@ struct Storage<_Float16> {
   __device__ static __forceinline__ float load(const _Float16* p, float) { return (float)(*p); }
   template <int I, class L>
   __device__ static __forceinline__ float rt(float d, float) { return (float)(_Float16)d; }
+  static constexpr bool kStoredShifted = true;
+  template <int I, class L>
+  __device__ static __forceinline__ float stored(float d, float h) { return rt<I, L>(d, h); }
+  template <int I, class L>
+  __device__ static __forceinline__ float bload_stored(__amdgpu_buffer_rsrc_t r, uint32_t vo) {
+    return bload<I, L>(r, vo, 0.f);
+  }
   template <int I, class L>
   __device__ static __forceinline__ void store(_Float16* p, float d, float) { *p = (_Float16)d; }
 };
@@ -163,6 +186,13 @@ struct Storage<__bf16> {
   __device__ static __forceinline__ float load(const __bf16* p, float) { return (float)(*p); }
   template <int I, class L>
   __device__ static __forceinline__ float rt(float d, float) { return (float)(__bf16)d; }
+  static constexpr bool kStoredShifted = true;
+  template <int I, class L>
+  __device__ static __forceinline__ float stored(float d, float h) { return rt<I, L>(d, h); }
+  template <int I, class L>
+  __device__ static __forceinline__ float bload_stored(__amdgpu_buffer_rsrc_t r, uint32_t vo) {
+    return bload<I, L>(r, vo, 0.f);
+  }
   template <int I, class L>
   __device__ static __forceinline__ void store(__bf16* p, float d, float) { *p = (__bf16)d; }
 };
@@ -191,6 +221,13 @@ struct Storage<F32S> {
   __device__ static __forceinline__ float load(const F32S* p, float) { return p->v; }
   template <int I, class L>
   __device__ static __forceinline__ float rt(float d, float) { return d; }
+  static constexpr bool kStoredShifted = true;
+  template <int I, class L>
+  __device__ static __forceinline__ float stored(float d, float) { return d; }
+  template <int I, class L>
+  __device__ static __forceinline__ float bload_stored(__amdgpu_buffer_rsrc_t r, uint32_t vo) {
+    return bload<I, L>(r, vo, 0.f);
+  }
   template <int I, class L>
   __device__ static __forceinline__ void store(F32S* p, float d, float) { __builtin_nontemporal_store(d, &p->v); }
 };
@@ -1269,8 +1306,8 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           const R cA = colour_of_total<L, I>(tv, sc_a, sc_bx, sc_by, sc_bz, rho0, hshift);
           route(ic, cA, (R)tv - cA, n, open, live, ragged);
         } else {
-          route(ic, Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finA, a.N), vo, hshift),
-                Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), vo, hshift), n, open, live, ragged);
+          route(ic, Storage<S>::template bload_stored<I, L>(pair_rsrc<L, I>(finA, a.N), vo),
+                Storage<S>::template bload_stored<I, L>(pair_rsrc<L, I>(finB, a.N), vo), n, open, live, ragged);
         }
       };
       own(std::integral_constant<int, 0>{});
@@ -1474,8 +1511,8 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
               Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
             }
             if constexpr (RO)
-              route(ic, Storage<S>::template rt<I, L>(da, hshift), Storage<S>::template rt<I, L>(db, hshift), n,
-                    open, live, ragged);
+              route(ic, Storage<S>::template stored<I, L>(da, hshift), Storage<S>::template stored<I, L>(db, hshift),
+                    n, open, live, ragged);
           }
         };
         // one velocity pair: shared dot products, even / odd split
@@ -1690,7 +1727,11 @@ __global__ void __launch_bounds__(T::NT) k_boot_scatter(const S* __restrict__ f,
 // all threads with coalesced loads; the rim threads then add their slots
 // from LDS.  The CP planes' P values are loaded first.
 constexpr int COMBINE_PLANES = 4;
-template <class L, class R, int TX, int TY>
+// SHIFTED: the scattered values are shifted populations (f - w_i rho0 / 2 per
+// colour: 16-bit and FP32-shifted per-colour storage, and the total layouts'
+// rebuilt colours), so the sums are rho_k - rho0 / 2; otherwise they are the
+// stored populations themselves and the sums are rho_k.
+template <class L, class R, int TX, int TY, bool SHIFTED>
 __global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
                                                      R* __restrict__ phi, StepArgs a) {
   constexpr int CP = COMBINE_PLANES;
@@ -1771,7 +1812,7 @@ __global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part,
   for (int k = 0; k < CP; ++k) {
     if (k < np) {
       const R A = sa[k] + ha[k], B = sb[k] + hb[k];
-      phi[s0 + nxy * (uint32_t)k] = (A - B) / (R(2) * h + (A + B));
+      phi[s0 + nxy * (uint32_t)k] = SHIFTED ? (A - B) / (R(2) * h + (A + B)) : (A - B) / (A + B);
     }
   }
 }
