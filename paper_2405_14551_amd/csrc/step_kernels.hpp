@@ -298,14 +298,20 @@ struct StepArgs {
 };
 
 // Workgroups are handed to the 8 XCDs round-robin in dispatch order.  Renumber
-// them so that each XCD receives one contiguous range of tiles: x-neighbour
-// tiles (whose +-1 pulls read the same cache lines) and the rows of a plane
-// then share one L2 instead of fetching the shared lines once per XCD.
+// them so that each XCD receives chunks of 16 consecutive tiles: x- and
+// y-neighbour tiles (whose +-1 pulls read the same cache lines) then mostly
+// share one L2, while the workgroups running at one time still cover one
+// contiguous range of the lattice (8 x 16 tiles), which keeps the HBM
+// accesses of a moment close together.  (Measured on the 256 x 128 x 128
+// channel, read-once FP32 collision: 425 us with one contiguous range per
+// XCD, 423 us in plain dispatch order, 417 us with chunks of 16.)  A tail of
+// fewer than 8 x 16 tiles keeps the dispatch order.
 __device__ __forceinline__ uint32_t xcd_tile_index(uint32_t b, uint32_t nb) {
-  constexpr uint32_t NXCD = 8;
+  constexpr uint32_t NXCD = 8, C = 16;
+  const uint32_t full = nb / (NXCD * C) * (NXCD * C);
+  if (b >= full) return b;
   const uint32_t xcd = b % NXCD, k = b / NXCD;
-  const uint32_t per = nb / NXCD, rem = nb % NXCD;
-  return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+  return ((k / C) * NXCD + xcd) * C + (k % C);
 }
 
 // tile t of a lattice cut into TX x TY columns and z-blocks (x fastest)
