@@ -220,6 +220,8 @@ typedef struct lb_handle lb_handle;
  *                channel's state stays in the last-level cache).
  *  z_per_block   z-planes per collision tile (>= 1)
  *  use_graph     1: replay non-field steps from a captured hipGraph of two steps
+ *                (batched mode; the per-channel mode launches directly and
+ *                lb_autotune tries it without a graph only)
  *  ms_per_step   filled by lb_autotune with the measured time of the choice */
 enum { LB_ENSEMBLE_BATCHED = 0, LB_ENSEMBLE_PER_CHANNEL = 1 };
 typedef struct lb_tuning {

@@ -1228,9 +1228,13 @@ int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int c
   (void)hipSetDevice(h->device);
   std::vector<lb_tuning> cand;
   if (h->ensemble()) {
+    // the per-channel mode launches each channel's passes directly (its
+    // step count varies per call), so only the batched mode has graph
+    // candidates
     for (int mode : {LB_ENSEMBLE_BATCHED, LB_ENSEMBLE_PER_CHANNEL})
       for (int zb : {1, 2, 4, 8, 16})
         for (int graph : {0, 1}) {
+          if (mode == LB_ENSEMBLE_PER_CHANNEL && graph) continue;
           lb_tuning t{};
           t.mode = mode;
           t.z_per_block = zb;

@@ -102,6 +102,9 @@ def test_autotune_picks_a_measured_config(tmp_path):
     best, table = ens.autotune(steps=2, cache=cache)
     assert len(table) >= 2
     assert best["ms_per_step"] == min(r["ms_per_step"] for r in table)
+    # each candidate measured once: the per-channel mode has no graph variant
+    assert not any(r["mode"] == "per_channel" and r["use_graph"] for r in table)
+    assert len({(r["mode"], r["z_per_block"], r["use_graph"]) for r in table}) == len(table)
     best2, _ = ens.autotune(steps=2, cache=cache)   # cached
     assert best2["z_per_block"] == best["z_per_block"] and best2["mode"] == best["mode"]
     assert best2["use_graph"] == best["use_graph"]

@@ -302,7 +302,11 @@ def test_trained_closure_keeps_droplets_apart():
     err = closure_force_error(applied_force(pred, r), t * gn, t)
     say("  held-out force error, network output: " + ", ".join(f"{k} {v:.3f}" for k, v in raw.items()))
     say("  held-out force error, applied force:  " + ", ".join(f"{k} {v:.3f}" for k, v in err.items()))
-    assert err["active"] < 0.6
+    # just above the measured 0.377 (applied) and 0.387 (raw): a 3x3x3
+    # stencil cannot see the opposing interface at h = 2..3, which bounds
+    # what any network of this input can reach
+    assert err["active"] < 0.42
+    assert raw["active"] < 0.43
     off = _pair3d("off", 3000)
     on = _pair3d("explicit", 3000)
     learned = _pair3d("mlp", 3000, net=th, ranges=ranges)
@@ -340,6 +344,8 @@ def test_trained_closure_keeps_the_dense_emulsion():
         f"closure {learned} (max|u| {u_net:.4f})")
     assert off < 100
     assert exp == 2000 and learned == 2000
-    # the closure's force error (tens of percent) shows in the flow; the bar
-    # catches a runaway, a third of the watchdog's limit
-    assert u_net < 0.1
+    # the closure's force error (tens of percent) shows in the flow: 0.028
+    # measured against 0.009 with the explicit force.  Runs that differ only
+    # in rounding (the read-once and two-pass steps) moved it by up to 2x, so
+    # the bar sits above that spread, well below the watchdog's 0.3
+    assert u_net < 0.06
