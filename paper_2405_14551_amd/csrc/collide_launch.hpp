@@ -84,9 +84,9 @@ struct CollideLaunch {
 
   // collision pass with the learned near-contact closure (3D lattices).
   // Without ro it marches half the planes of the other passes: it holds the
-  // network and its row queues in LDS, runs three workgroups per CU, and
-  // measured faster with twice as many, shorter marches.  With ro the caller
-  // applies the same rule when it sizes the halo blocks.
+  // network and its row queues in LDS and measured faster with twice as
+  // many, shorter marches.  With ro it takes the caller's depth (the one the
+  // halo blocks are sized for).
   template <class S, bool FIELDS, bool TOT>
   static hipError_t collide_mlp_t(const void* fin, void* fout, float* scout, const void* phi, const FieldPtrs& fo,
                                   const StepArgs& a, const MlpPacked* net, const ScatterOut* ro, hipStream_t s) {

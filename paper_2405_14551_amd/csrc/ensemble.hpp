@@ -70,7 +70,7 @@ template <class L, class S, class TS, bool TOT>
 __global__ void __launch_bounds__(TS::NT) k_ensemble_phase(const ChannelDev* __restrict__ chans,
                                                            const uint32_t* __restrict__ items, int parity) {
   using R = typename Storage<S>::real;
-  const uint32_t e = __builtin_amdgcn_readfirstlane(items[xcd_tile_index(blockIdx.x, gridDim.x)]);
+  const uint32_t e = __builtin_amdgcn_readfirstlane(items[xcd_range_index(blockIdx.x, gridDim.x)]);
   const uint32_t c = (e >> ITEM_CH_SHIFT) & ITEM_CH_MASK;
   const ChannelDev* C = chans + c;
   const StepArgs a = uniform_args(C->a);
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict
   using TS = Tile<T::TX, T::TY, 1, L::D>;
   __shared__ EnsembleSmem<L, S, T, TOT> sm;
   // consecutive items (x-neighbour tiles of one channel) go to one XCD
-  const uint32_t e = __builtin_amdgcn_readfirstlane(items[xcd_tile_index(blockIdx.x, gridDim.x)]);
+  const uint32_t e = __builtin_amdgcn_readfirstlane(items[xcd_range_index(blockIdx.x, gridDim.x)]);
   const uint32_t c = (e >> ITEM_CH_SHIFT) & ITEM_CH_MASK;
   const ChannelDev* C = chans + c;
   const StepArgs a = uniform_args(C->a);

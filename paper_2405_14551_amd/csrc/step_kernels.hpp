@@ -306,6 +306,16 @@ struct StepArgs {
 // channel, read-once FP32 collision: 425 us with one contiguous range per
 // XCD, 423 us in plain dispatch order, 417 us with chunks of 16.)  A tail of
 // fewer than 8 x 16 tiles keeps the dispatch order.
+// The ensemble's work lists use one contiguous range of items per XCD
+// (xcd_range_index): its items are ordered largest channel first, and the
+// chunked order measured slower there (96-channel ensemble, batched: 8.3 ms
+// against 9.5 ms per step).
+__device__ __forceinline__ uint32_t xcd_range_index(uint32_t b, uint32_t nb) {
+  constexpr uint32_t NXCD = 8;
+  const uint32_t xcd = b % NXCD, k = b / NXCD;
+  const uint32_t per = nb / NXCD, rem = nb % NXCD;
+  return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
 __device__ __forceinline__ uint32_t xcd_tile_index(uint32_t b, uint32_t nb) {
   constexpr uint32_t NXCD = 8, C = 16;
   const uint32_t full = nb / (NXCD * C) * (NXCD * C);
@@ -1326,7 +1336,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       // work below: both colours (shifted by w_i rho0/2 each), or the total
       const Nbr n = make_nbr(ALL ? min(x, a.nx - 1) : x, ALL ? min(y, a.ny - 1) : y, z, a);
       const bool open = wave_open(n);
-      if constexpr (!PIPE) do_pull(n, open, finA, finB);
+      // (with the learned closure the pull waits until the network has run:
+      // its loads would hold 2Q registers through the network's MFMAs)
+      constexpr bool LATE = MLP;
+      if constexpr (!PIPE && !LATE) do_pull(n, open, finA, finB);
       const int p0 = zc * T::PL;
       constexpr int dz1 = T::RZ ? 1 : 0;   // 2D: a single plane
       const int pm = ring_slot(zc, -dz1, T::NPL) * T::PL;
@@ -1398,6 +1411,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           }
         }
       }
+      if constexpr (LATE) do_pull(n, open, finA, finB);
       // lanes outside the lattice (closure mode only) store nothing: one
       // branch around the whole collision keeps it a single block of
       // arithmetic, as in the other modes.  RO: every lane collides (on a
@@ -1698,7 +1712,11 @@ __global__ void __launch_bounds__(T::NT, (collide_min_waves<S, TOT, RO>())) k_co
 
 // collision pass with the learned near-contact closure
 template <class L, class S, class T, bool FIELDS, bool TOT, int STREAM = STREAM_AB, bool RO = false>
-__global__ void __launch_bounds__(T::NT, 3) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
+// (two waves per SIMD: the register room keeps the network's fragments and the
+// read-once scatter out of scratch; measured against three waves with the
+// early pull on the 256 x 128 x 128 channel and the dense emulsion, FP32:
+// 489 -> 459 us and 3.02 -> 2.88 ms)
+__global__ void __launch_bounds__(T::NT, 2) k_collide_mlp(const S* __restrict__ fin, S* __restrict__ fout,
                                                            const typename Storage<S>::real* __restrict__ phi,
                                                            float* __restrict__ scout,
                                                         FieldPtrs fo, StepArgs a, const MlpPacked* __restrict__ net,
