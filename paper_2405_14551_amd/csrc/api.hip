@@ -152,7 +152,8 @@ struct lb_handle {
   ChannelDev* d_chans = nullptr;
   uint32_t* d_items_ph = nullptr;    // phase tiles of every channel
   uint32_t* d_items_co = nullptr;    // collision tiles of every channel
-  uint32_t n_items_ph = 0, n_items_co = 0;
+  uint32_t* d_items_cb = nullptr;    // read-once step: combine blocks of every channel
+  uint32_t n_items_ph = 0, n_items_co = 0, n_items_cb = 0;
   lb_tuning tune{};                  // ensemble launch configuration
   hipGraphExec_t graph = nullptr;    // two non-field steps (parity 0 then 1)
   bool ensemble() const { return !chans.empty(); }
@@ -326,7 +327,7 @@ int lb_destroy(lb_handle* h) {
   for (lb_handle* c : h->chans) lb_destroy(c);
   h->chans.clear();
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  for (void* b : {(void*)h->d_chans, (void*)h->d_items_ph, (void*)h->d_items_co})
+  for (void* b : {(void*)h->d_chans, (void*)h->d_items_ph, (void*)h->d_items_co, (void*)h->d_items_cb})
     if (b) (void)hipFree(b);
   for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
   void* bufs[] = {h->f[0], h->f[1], h->sc[0], h->sc[1], h->W, h->phi, h->phi2, h->ro_part, h->ro_halo, h->rho_a, h->rho_b, h->u, h->fnc, h->flags, h->labels,
@@ -374,6 +375,8 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
       return fail(LB_EINVAL, "channel %d: ensembles use the population scheme", c);
     if (p[c].rounding != LB_ROUND_NEAREST)
       return fail(LB_EINVAL, "channel %d: ensembles round to nearest (stochastic rounding is single-lattice)", c);
+    if (p[c].phase_pass != p[0].phase_pass)
+      return fail(LB_EINVAL, "channel %d: phase_pass must agree across channels", c);
   }
   if (p[0].nc_mode == LB_NC_MLP) return fail(LB_EINVAL, "ensembles take nc_mode LB_NC_OFF or LB_NC_EXPLICIT");
   if (!ensemble_storage(p[0].storage))
@@ -400,6 +403,7 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
     h->chans.push_back(sub);
     h->N += sub->N;
   }
+  h->ro = h->chans[0]->ro;
   h->tune.mode = LB_ENSEMBLE_BATCHED;
   h->tune.z_per_block = 4;
   h->tune.use_graph = 1;
@@ -410,8 +414,7 @@ int lb_create(const lb_params* p, int n_channels, void* hip_stream, lb_handle** 
   return LB_OK;
 }
 
-// channel: a channel of an ensemble (stepped by the ensemble's launches, which
-// keep the phase pass)
+// channel: a channel of an ensemble (stepped by the ensemble's launches)
 static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, bool channel) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
@@ -468,7 +471,7 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
   {
     const bool total16 = p->storage == LB_F16_TOTAL || p->storage == LB_BF16_TOTAL || p->storage == LB_F16C_TOTAL;
     const int mode = p->phase_pass == LB_PHASE_AUTO ? (total16 ? LB_PHASE_PASS : LB_PHASE_SCATTER) : p->phase_pass;
-    h->ro = !channel && !h->moments() && mode == LB_PHASE_SCATTER;
+    h->ro = !h->moments() && mode == LB_PHASE_SCATTER;
   }
   if (h->ro) {
     ALLOC(h->phi2, N * h->rsize);
@@ -645,9 +648,16 @@ static int ensemble_plan(lb_handle* h) {
   const int zb = h->tune.z_per_block;
   std::vector<ChannelDev> tab(nch);
   std::vector<uint32_t> tiles(nch);
+  std::vector<uint32_t> nblocks(nch, 0);  // read-once: combine blocks per channel
   for (int c = 0; c < nch; ++c) {
     lb_handle* s = h->chans[c];
     s->z_per_block = zb;  // also the per-channel launches' tiling
+    if (s->ro) {
+      // halo blocks for this march depth (the stream is drained first if
+      // they grow)
+      int rc = ro_plan(s);
+      if (rc) return rc;
+    }
     ChannelDev& d = tab[c];
     std::memset(&d, 0, sizeof d);
     d.a = s->step_args();
@@ -662,23 +672,36 @@ static int ensemble_plan(lb_handle* h) {
     d.sc[1] = s->sc[1];
     d.phi = s->phi;
     d.fo = s->field_ptrs();
+    if (s->ro) {
+      // the read-once launches use the march depth the halo blocks are sized for
+      d.a.z_per_block = s->ro_zb;
+      d.phis[0] = s->phi_at(0);
+      d.phis[1] = s->phi_at(1);
+      d.part = s->ro_part;
+      d.halo = s->ro_halo;
+      const uint32_t groups = (uint32_t)((s->ro_zb + COMBINE_PLANES - 1) / COMBINE_PLANES);
+      nblocks[c] = (uint32_t)d.a.tiles_x * d.a.tiles_y * nzb * groups;
+      if (nblocks[c] > ITEM_TILE_MASK + 1)
+        return fail(LB_EINVAL, "channel %d has too many combine blocks (%u)", c, nblocks[c]);
+    }
     tiles[c] = d.ntiles;
   }
   // largest channels first, so that the small ones fill the tail of a launch
   std::vector<int> order(nch);
   for (int c = 0; c < nch; ++c) order[c] = c;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return tiles[a] > tiles[b]; });
-  std::vector<uint32_t> ph, co;
+  std::vector<uint32_t> ph, co, cb;
   for (int k = 0; k < nch; ++k) {
     const uint32_t c = (uint32_t)order[k];
     for (uint32_t t = 0; t < tiles[c]; ++t) {
       ph.push_back((c << ITEM_CH_SHIFT) | t);
       co.push_back(ITEM_COLLIDE | (c << ITEM_CH_SHIFT) | t);
     }
+    for (uint32_t t = 0; t < nblocks[c]; ++t) cb.push_back((c << ITEM_CH_SHIFT) | t);
   }
   (void)hipSetDevice(h->device);
   HIP_TRY(hipStreamSynchronize(h->stream));
-  for (void** b : {(void**)&h->d_chans, (void**)&h->d_items_ph, (void**)&h->d_items_co})
+  for (void** b : {(void**)&h->d_chans, (void**)&h->d_items_ph, (void**)&h->d_items_co, (void**)&h->d_items_cb})
     if (*b) {
       HIP_TRY(hipFree(*b));
       *b = nullptr;
@@ -696,7 +719,59 @@ static int ensemble_plan(lb_handle* h) {
   HIP_TRY(hipMemcpy(h->d_items_co, co.data(), sizeof(uint32_t) * co.size(), hipMemcpyHostToDevice));
   h->n_items_ph = (uint32_t)ph.size();
   h->n_items_co = (uint32_t)co.size();
+  h->n_items_cb = (uint32_t)cb.size();
+  if (!cb.empty()) {
+    if ((rc = dev_alloc((void**)&h->d_items_cb, sizeof(uint32_t) * cb.size(), "work list"))) return rc;
+    HIP_TRY(hipMemcpy(h->d_items_cb, cb.data(), sizeof(uint32_t) * cb.size(), hipMemcpyHostToDevice));
+  }
   return LB_OK;
+}
+
+// read-once ensembles: a channel whose phase field is not ready (after an
+// initialisation or a restore), or not in the buffer of its state's parity,
+// scatters its stored state first (bit for bit what the collision pass that
+// stored it would have scattered) and combines it into phi_at(cur), so that
+// the phase field and the populations share one parity
+static int ensemble_ro_boot(lb_handle* h) {
+  for (lb_handle* c : h->chans) {
+    if (c->phi_ready && c->pcur == c->cur) continue;
+    StepArgs b = c->step_args();
+    b.z_per_block = c->ro_zb;
+    const ScatterOut so{c->ro_part, c->ro_halo};
+    HIP_TRY(h->ops->boot(h->p.storage, c->f[c->cur], c->sc[c->cur], so, b, h->stream));
+    HIP_TRY(h->ops->combine(h->p.storage, so, c->phi_at(c->cur), b, h->stream));
+    c->pcur = c->cur;
+    c->phi_ready = true;
+  }
+  return LB_OK;
+}
+
+// one step of channel c with the given parity (per-channel mode): the
+// read-once collision and combine passes, or the phase and collision passes
+static int channel_launch(lb_handle* h, lb_handle* c, bool fields, int parity, hipStream_t s) {
+  const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
+  const int st = h->p.storage;
+  const StepArgs a = c->step_args();
+  int rc = 0;
+  if (c->ro) {
+    StepArgs b = a;
+    b.z_per_block = c->ro_zb;
+    const ScatterOut so{c->ro_part, c->ro_halo};
+    if ((rc = prof_mark(h, 1, true))) return rc;
+    HIP_TRY(h->ops->collide(st, nc, fields, c->f[parity], c->f[1 - parity], c->sc[1 - parity], c->phi_at(parity),
+                            c->field_ptrs(), b, &so, s));
+    if ((rc = prof_mark(h, 1, false))) return rc;
+    if ((rc = prof_mark(h, 2, true))) return rc;
+    HIP_TRY(h->ops->combine(st, so, c->phi_at(1 - parity), b, s));
+    return prof_mark(h, 2, false);
+  }
+  if ((rc = prof_mark(h, 0, true))) return rc;
+  HIP_TRY(h->ops->phase(st, c->f[parity], c->sc[parity], c->phi, a, s));
+  if ((rc = prof_mark(h, 0, false))) return rc;
+  if ((rc = prof_mark(h, 1, true))) return rc;
+  HIP_TRY(h->ops->collide(st, nc, fields, c->f[parity], c->f[1 - parity], c->sc[1 - parity], c->phi,
+                          c->field_ptrs(), a, nullptr, s));
+  return prof_mark(h, 1, false);
 }
 
 // enqueue one ensemble step with the given parity on stream s; while
@@ -705,6 +780,16 @@ static int ensemble_plan(lb_handle* h) {
 static int ensemble_launch(lb_handle* h, bool fields, int parity, hipStream_t s) {
   const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
   int rc = 0;
+  if (h->tune.mode == LB_ENSEMBLE_BATCHED && h->ro) {
+    // read-once: every channel's collision tile-marches (with the scatter),
+    // then every channel's combine blocks
+    if ((rc = prof_mark(h, 1, true))) return rc;
+    HIP_TRY(h->ops->ensemble_ro(h->p.storage, nc, fields, false, h->d_chans, h->d_items_co, h->n_items_co, parity, s));
+    if ((rc = prof_mark(h, 1, false))) return rc;
+    if ((rc = prof_mark(h, 2, true))) return rc;
+    HIP_TRY(h->ops->ensemble_ro(h->p.storage, nc, fields, true, h->d_chans, h->d_items_cb, h->n_items_cb, parity, s));
+    return prof_mark(h, 2, false);
+  }
   if (h->tune.mode == LB_ENSEMBLE_BATCHED) {
     if ((rc = prof_mark(h, 0, true))) return rc;
     HIP_TRY(h->ops->ensemble(h->p.storage, nc, fields, true, h->d_chans, h->d_items_ph, h->n_items_ph, parity, s));
@@ -713,19 +798,11 @@ static int ensemble_launch(lb_handle* h, bool fields, int parity, hipStream_t s)
     HIP_TRY(h->ops->ensemble(h->p.storage, nc, fields, false, h->d_chans, h->d_items_co, h->n_items_co, parity, s));
     return prof_mark(h, 1, false);
   }
-  // channel after channel, each channel's collision pass right after its
-  // phase pass: the channel's state (a few hundred MB) is then still in the
-  // MI355X's 256 MB last-level cache in good part when the second pass reads it
-  for (lb_handle* c : h->chans) {
-    const StepArgs a = c->step_args();
-    if ((rc = prof_mark(h, 0, true))) return rc;
-    HIP_TRY(h->ops->phase(h->p.storage, c->f[parity], c->sc[parity], c->phi, a, s));
-    if ((rc = prof_mark(h, 0, false))) return rc;
-    if ((rc = prof_mark(h, 1, true))) return rc;
-    HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[1 - parity], c->phi,
-                            c->field_ptrs(), a, nullptr, s));
-    if ((rc = prof_mark(h, 1, false))) return rc;
-  }
+  // channel after channel, each channel's passes back to back: the channel's
+  // state (a few hundred MB) is then still in the MI355X's 256 MB last-level
+  // cache in good part when the second pass reads it
+  for (lb_handle* c : h->chans)
+    if ((rc = channel_launch(h, c, fields, parity, s))) return rc;
   return LB_OK;
 }
 
@@ -757,6 +834,11 @@ static void ensemble_advance(lb_handle* h, bool fields) {
   h->cur = 1 - h->cur;
   h->t += 1;
   for (lb_handle* c : h->chans) {
+    if (c->ro) {
+      // the step read phi_at(pcur) and its combine pass wrote the other one
+      if (fields) c->pfield = c->pcur;
+      c->pcur = 1 - c->pcur;
+    }
     c->cur = h->cur;
     c->t += 1;
     if (fields) c->fields_valid = true;
@@ -766,28 +848,20 @@ static void ensemble_advance(lb_handle* h, bool fields) {
 static int ensemble_step(lb_handle* h, int nsteps) {
   for (lb_handle* c : h->chans)
     if (!c->initialised) return fail(LB_EINVAL, "every channel must be initialised before stepping");
+  if (h->ro && nsteps > 0) {
+    int rc = ensemble_ro_boot(h);
+    if (rc) return rc;
+  }
   // per-channel mode without the watchdog: the channels are independent, so
   // each takes all nsteps before the next one starts.  A channel's state
   // (up to a few hundred MB) then stays largely in the 256 MB last-level
   // cache from one pass to the next.  The results are those of the
   // step-by-step order, bit for bit.
   if (h->tune.mode == LB_ENSEMBLE_PER_CHANNEL && h->p.diag_every <= 0 && nsteps > 1) {
-    const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
     int rc = 0;
-    for (lb_handle* c : h->chans) {
-      const StepArgs a = c->step_args();
-      for (int k = 0; k < nsteps; ++k) {
-        const int parity = (h->cur + k) & 1;
-        const bool fields = k == nsteps - 1;
-        if ((rc = prof_mark(h, 0, true))) return rc;
-        HIP_TRY(h->ops->phase(h->p.storage, c->f[parity], c->sc[parity], c->phi, a, h->stream));
-        if ((rc = prof_mark(h, 0, false))) return rc;
-        if ((rc = prof_mark(h, 1, true))) return rc;
-        HIP_TRY(h->ops->collide(h->p.storage, nc, fields, c->f[parity], c->f[1 - parity], c->sc[1 - parity],
-                                c->phi, c->field_ptrs(), a, nullptr, h->stream));
-        if ((rc = prof_mark(h, 1, false))) return rc;
-      }
-    }
+    for (lb_handle* c : h->chans)
+      for (int k = 0; k < nsteps; ++k)
+        if ((rc = channel_launch(h, c, k == nsteps - 1, (h->cur + k) & 1, h->stream))) return rc;
     for (int k = 0; k < nsteps; ++k) ensemble_advance(h, k == nsteps - 1);
     return LB_OK;
   }

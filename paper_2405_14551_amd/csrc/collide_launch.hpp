@@ -134,6 +134,51 @@ struct CollideLaunch {
   }
 };
 
+// read-once batched ensemble launches (two-copy streaming)
+template <class L>
+struct EnsembleRoLaunch {
+  template <class S, bool TOT>
+  static hipError_t run_s(bool nc, bool fields, bool combine, const ChannelDev* chans, const uint32_t* items,
+                          uint32_t nitems, int parity, hipStream_t s) {
+    using R = typename Storage<S>::real;
+    dim3 block(TILE_X, TILE_Y, 1), grid(nitems);
+    if (combine) {
+      // per-colour FP64 / FP32 scatter the stored populations themselves
+      constexpr bool SHIFTED = !(std::is_same_v<S, double> || (std::is_same_v<S, float> && !TOT));
+      k_ensemble_combine<L, R, TILE_X, TILE_Y, SHIFTED><<<grid, block, 0, s>>>(chans, items, parity);
+      return hipGetLastError();
+    }
+    if (nc) {
+      using T = Tile<TILE_X, TILE_Y, 4, L::D>;
+      if (fields) k_ensemble_ro<L, S, T, true, true, TOT><<<grid, block, 0, s>>>(chans, items, parity);
+      else k_ensemble_ro<L, S, T, true, false, TOT><<<grid, block, 0, s>>>(chans, items, parity);
+    } else {
+      using T = Tile<TILE_X, TILE_Y, 1, L::D>;
+      if (fields) k_ensemble_ro<L, S, T, false, true, TOT><<<grid, block, 0, s>>>(chans, items, parity);
+      else k_ensemble_ro<L, S, T, false, false, TOT><<<grid, block, 0, s>>>(chans, items, parity);
+    }
+    return hipGetLastError();
+  }
+  static hipError_t run(int st, bool nc, bool fields, bool combine, const ChannelDev* chans, const uint32_t* items,
+                        uint32_t nitems, int parity, hipStream_t s) {
+    switch (st) {
+      case ST_F64: return run_s<double, false>(nc, fields, combine, chans, items, nitems, parity, s);
+      case ST_F32: return run_s<float, false>(nc, fields, combine, chans, items, nitems, parity, s);
+      case ST_F32T: return run_s<float, true>(nc, fields, combine, chans, items, nitems, parity, s);
+      case ST_F16T: return run_s<_Float16, true>(nc, fields, combine, chans, items, nitems, parity, s);
+      case ST_BF16T: return run_s<__bf16, true>(nc, fields, combine, chans, items, nitems, parity, s);
+      case ST_F16CT: return run_s<F16C, true>(nc, fields, combine, chans, items, nitems, parity, s);
+    }
+    return hipErrorInvalidValue;
+  }
+};
+
+template <class L>
+hipError_t ensemble_ro_impl(int st, bool nc, bool fields, bool combine, const ChannelDev* chans,
+                            const uint32_t* items, uint32_t nitems, int parity, hipStream_t s) {
+  return EnsembleRoLaunch<L>::run(st, nc, fields, combine, chans, items, nitems, parity, s);
+}
+
 template <class L, int STREAM, bool RO>
 hipError_t collide_impl(int st, bool nc, bool fields, const void* fin, void* fout, float* scout, const void* phi,
                         const FieldPtrs& fo, const StepArgs& a, const ScatterOut* ro, hipStream_t s) {
@@ -158,4 +203,11 @@ hipError_t collide_mlp_impl(int st, bool fields, const void* fin, void* fout, fl
   template hipError_t collide_mlp_impl<LAT, STREAM, RO>(int, bool, const void*, void*, float*, const void*,     \
                                                         const FieldPtrs&, const StepArgs&, const MlpPacked*,    \
                                                         const ScatterOut*, hipStream_t);                        \
+  }
+
+// the read-once ensemble launches of one lattice (in its two-copy read-once unit)
+#define LB_INSTANTIATE_ENSEMBLE_RO(LAT)                                                                      \
+  namespace lbm {                                                                                          \
+  template hipError_t ensemble_ro_impl<LAT>(int, bool, bool, bool, const ChannelDev*, const uint32_t*,      \
+                                            uint32_t, int, hipStream_t);                                   \
   }

@@ -58,6 +58,11 @@ struct LatticeOps {
   // collision pass storing it would have made
   hipError_t (*boot)(int storage, const void* f, const float* sc, const ScatterOut& ro, const StepArgs& a,
                      hipStream_t s);
+  // read-once batched ensemble launch (storages as for `ensemble`): combine
+  // false: every item is a collision tile-march (collision with the
+  // scatter); combine true: every item is a combine block
+  hipError_t (*ensemble_ro)(int storage, bool nc, bool fields, bool combine, const ChannelDev* chans,
+                            const uint32_t* items, uint32_t nitems, int parity, hipStream_t s);
 };
 
 // One-copy (in-place) streaming: even and odd steps alternate, the even kind

@@ -27,6 +27,12 @@ struct ChannelDev {
   FieldPtrs fo;
   uint32_t ntiles;   // phase tiles (= collision tiles) of this channel
   uint32_t pad;
+  // read-once step: phase field buffers (phis[p] is read by the collision
+  // pass of a step of parity p, phis[1 - p] written by its combine pass), the
+  // partial densities and the halo blocks
+  void* phis[2];
+  void* part;
+  void* halo;
 };
 
 // item encoding: bit 31 = collision tile, bits 20..30 = channel, bits 0..19 = tile
@@ -118,6 +124,55 @@ __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict
     fo.flags = uniform_ptr(C->fo.flags);
     collide_tile<L, S, T, NC, FIELDS, TOT>(fin, fout, (const R*)phi, scout, fo, a, tc, sm.c);
   }
+}
+
+// Read-once ensemble step, first launch: every channel's collision tiles with
+// the read-once scatter (one tile-march per workgroup; the item names the
+// channel and the tile-march, as for the two-pass collision).
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
+__global__ void __launch_bounds__(T::NT, (collide_min_waves<S, TOT, true>()))
+    k_ensemble_ro(const ChannelDev* __restrict__ chans, const uint32_t* __restrict__ items, int parity) {
+  using R = typename Storage<S>::real;
+  __shared__ CollideSmem<L, S, T, TOT, false, true> sm;
+  const uint32_t e = __builtin_amdgcn_readfirstlane(items[xcd_range_index(blockIdx.x, gridDim.x)]);
+  const uint32_t c = (e >> ITEM_CH_SHIFT) & ITEM_CH_MASK;
+  const ChannelDev* C = chans + c;
+  const StepArgs a = uniform_args(C->a);
+  const TileCoord tc = tile_coord(e & ITEM_TILE_MASK, a, T::TX, T::TY);
+  const S* fin = uniform_ptr((const S*)C->f[parity]);
+  S* fout = uniform_ptr((S*)C->f[1 - parity]);
+  float* scout = uniform_ptr(C->sc[1 - parity]);
+  const R* phi = uniform_ptr((const R*)C->phis[parity]);
+  FieldPtrs fo;
+  fo.rho_a = uniform_ptr(C->fo.rho_a);
+  fo.rho_b = uniform_ptr(C->fo.rho_b);
+  fo.u = uniform_ptr(C->fo.u);
+  fo.fnc = uniform_ptr(C->fo.fnc);
+  fo.flags = uniform_ptr(C->fo.flags);
+  const ScatterOut so{uniform_ptr(C->part), uniform_ptr(C->halo)};
+  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM_AB, false, true>(fin, fout, phi, scout, fo, a, tc, sm, nullptr,
+                                                                        so);
+}
+
+// Read-once ensemble step, second launch: every channel's combine blocks.
+// Item index: ((tm G + j) tiles_y + ty) tiles_x + tx with G = ceil(march
+// depth / COMBINE_PLANES), the channel's own tiling.
+template <class L, class R, int TX, int TY, bool SHIFTED>
+__global__ void __launch_bounds__(TX * TY)
+    k_ensemble_combine(const ChannelDev* __restrict__ chans, const uint32_t* __restrict__ items, int parity) {
+  const uint32_t e = __builtin_amdgcn_readfirstlane(items[xcd_range_index(blockIdx.x, gridDim.x)]);
+  const uint32_t c = (e >> ITEM_CH_SHIFT) & ITEM_CH_MASK;
+  const ChannelDev* C = chans + c;
+  const StepArgs a = uniform_args(C->a);
+  const uint32_t idx = e & ITEM_TILE_MASK;
+  const int G = (a.z_per_block + COMBINE_PLANES - 1) / COMBINE_PLANES;
+  const uint32_t txy = (uint32_t)a.tiles_x * a.tiles_y;
+  const int zg = idx / txy;
+  const uint32_t r = idx - (uint32_t)zg * txy;
+  const int ty = r / a.tiles_x, tx = r - ty * a.tiles_x;
+  const int tm = zg / G, j = zg - tm * G;
+  combine_block<L, R, TX, TY, SHIFTED>(uniform_ptr((const R*)C->part), uniform_ptr((const RPair<R>*)C->halo),
+                                               uniform_ptr((R*)C->phis[1 - parity]), a, tx, ty, tm, j);
 }
 
 }  // namespace lbm

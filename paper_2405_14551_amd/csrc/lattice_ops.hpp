@@ -20,6 +20,9 @@ template <class L, int STREAM, bool RO>
 hipError_t collide_mlp_impl(int st, bool fields, const void* fin, void* fout, float* scout, const void* phi,
                             const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, const ScatterOut* ro,
                             hipStream_t s);
+template <class L>
+hipError_t ensemble_ro_impl(int st, bool nc, bool fields, bool combine, const ChannelDev* chans,
+                            const uint32_t* items, uint32_t nitems, int parity, hipStream_t s);
 
 template <class L>
 struct Launch {
@@ -219,7 +222,7 @@ struct Launch {
 
   static LatticeOps ops() {
     return LatticeOps{L::Q, L::D, &phase, &collide, &init, &ensemble, L::D == 3 ? &collide_mlp : nullptr, &combine,
-                      &boot};
+                      &boot, &ensemble_ro_impl<L>};
   }
 };
 

@@ -1756,16 +1756,13 @@ constexpr int COMBINE_PLANES = 4;
 // rebuilt colours), so the sums are rho_k - rho0 / 2; otherwise they are the
 // stored populations themselves and the sums are rho_k.
 template <class L, class R, int TX, int TY, bool SHIFTED>
-__global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
-                                                     R* __restrict__ phi, StepArgs a) {
+__device__ __forceinline__ void combine_block(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
+                                              R* __restrict__ phi, const StepArgs& a, int tx, int ty, int tm, int j) {
   constexpr int CP = COMBINE_PLANES;
   constexpr int NT = TX * TY;
   constexpr int RING = 2 * TX + 2 * TY + 4, CAP = (TX + 2) * (TY + 2);
   __shared__ RPair<R> hs_side[CP * RING];
   __shared__ RPair<R> hs_cap[2][CAP];
-  const int tx = blockIdx.x, ty = blockIdx.y;
-  const int G = (a.z_per_block + CP - 1) / CP;
-  const int tm = blockIdx.z / G, j = blockIdx.z - tm * G;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + TX * ly;
   const int x = tx * TX + lx, y = ty * TY + ly;
   HaloGeom g;
@@ -1839,6 +1836,14 @@ __global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part,
       phi[s0 + nxy * (uint32_t)k] = SHIFTED ? (A - B) / (R(2) * h + (A + B)) : (A - B) / (A + B);
     }
   }
+}
+
+template <class L, class R, int TX, int TY, bool SHIFTED>
+__global__ void __launch_bounds__(TX * TY) k_combine(const R* __restrict__ part, const RPair<R>* __restrict__ halo,
+                                                     R* __restrict__ phi, StepArgs a) {
+  const int G = (a.z_per_block + COMBINE_PLANES - 1) / COMBINE_PLANES;
+  const int tm = blockIdx.z / G, j = blockIdx.z - tm * G;
+  combine_block<L, R, TX, TY, SHIFTED>(part, halo, phi, a, blockIdx.x, blockIdx.y, tm, j);
 }
 
 // The canonical layout (slot (i, x) = f_i(x)) of one colour block from the
