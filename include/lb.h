@@ -155,11 +155,12 @@ typedef enum lb_rounding { LB_ROUND_NEAREST = 0, LB_ROUND_STOCHASTIC = 1 } lb_ro
  *                    step after lb_init_droplets / lb_set_state first scatters
  *                    the stored state (a bootstrap pass that forms exactly the
  *                    sums the collision pass storing it formed), so restarts
- *                    repeat uninterrupted runs bit for bit.  Single lattices
- *                    with the population scheme.
+ *                    repeat uninterrupted runs bit for bit.  Population
+ *                    scheme, single lattices and ensembles (all channels
+ *                    take the same phase_pass).
  *  LB_PHASE_PASS     a separate pass pulls the populations a second time each
  *                    step and forms the phase field before the collision pass
- *                    (ensembles and the moment scheme always work this way).
+ *                    (the moment scheme always works this way).
  *  LB_PHASE_AUTO     (the default) the read-once step for the per-colour
  *                    layouts and LB_F32_TOTAL, the phase pass for the 16-bit
  *                    total layouts, whose collision pass is bound by
@@ -211,10 +212,12 @@ typedef struct lb_handle lb_handle;
 
 /* Launch configuration of an ensemble step (n_channels > 1).
  *  mode          LB_ENSEMBLE_BATCHED: two launches per step over all channels
- *                (every channel's phase tiles, then every channel's collision
- *                tiles; one tile per workgroup).
- *                LB_ENSEMBLE_PER_CHANNEL: the single-lattice phase and
- *                collision launches, channel after channel; without the
+ *                (read-once step: every channel's collision tile-marches with
+ *                the scatter, then every channel's combine blocks; two-pass
+ *                step: every channel's phase tiles, then every channel's
+ *                collision tiles; one tile per workgroup).
+ *                LB_ENSEMBLE_PER_CHANNEL: the single-lattice launches of
+ *                each channel's step, channel after channel; without the
  *                watchdog, lb_step(n) takes each channel through all n steps
  *                before the next channel (same results, bit for bit; the
  *                channel's state stays in the last-level cache).
