@@ -69,7 +69,7 @@ def plain_state_bytes(q, storage):
     return 2 * q * s * 2 + 2 * r
 
 
-KERNEL_SOURCES = ("step_kernels.hpp", "lattice_ops.hpp", "collide_launch.hpp", "scatter_geom.hpp")
+KERNEL_SOURCES = ("step_kernels.hpp", "lattice_ops.hpp", "collide_launch.hpp", "scatter_geom.hpp", "api.hip")
 
 
 def kernel_source_hash():
@@ -145,6 +145,8 @@ def headline(args):
     from paper_2405_14551_amd import lb, workloads as W
     w = W.channel_3d(storage=args.storage)
     kw, cen, rad = W.sim_kwargs(w)
+    if args.phase != "auto":
+        kw = dict(kw, phase=args.phase)
     n = int(np.prod(kw["shape"]))
     say(f"headline channel_3d {args.storage} {kw['shape']}")
     sim = lb.Simulation(**kw).init_droplets(cen, rad)
@@ -411,6 +413,8 @@ def main():
                     help="only the channel workload (for profiling runs)")
     ap.add_argument("--storage", default="f32", choices=sorted(ELEM),
                     help="storage of the channel workload (profiling runs; the headline is f32)")
+    ap.add_argument("--phase", default="auto", choices=("auto", "scatter", "pass"),
+                    help="read-once or two-pass step for the channel workload (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
