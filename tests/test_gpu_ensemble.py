@@ -1,7 +1,8 @@
 """GPU tests of the batched ensemble (independent channels of different
 sizes, walls, tau and forces advanced together): each channel against the
 FP64 oracle in both launch modes, with and without the captured graph; graph
-replays against eager stepping; and the autotuner."""
+replays against eager stepping; the read-once step's launch modes, restart
+and stand-alone channels bit for bit; and the autotuner."""
 import sys
 
 import numpy as np
@@ -91,6 +92,52 @@ def test_graph_replays_match_eager(storage):
         b.step(chunk)
         b.sync()
         assert torch.equal(a.get_state(), b.get_state()), chunk
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32t"])
+def test_read_once_modes_restart_and_single_lattice_agree_bitwise(storage):
+    """Read-once ensembles (the default step for these storages): the batched
+    launches and the per-channel launches give the same state bit for bit; a
+    restart from a saved state (the bootstrap scatter) continues bit for bit;
+    and each channel equals the same lattice stepped on its own as a single
+    handle with the same march depth (the same tile code and sums)."""
+    say(f"case ensemble read-once bitwise {storage}")
+    a = make(storage)
+    b = make(storage)
+    a.set_tuning("batched", z_per_block=4, use_graph=1)
+    b.set_tuning("per_channel", z_per_block=4, use_graph=0)
+    a.step(9)
+    b.step(9)
+    a.sync()
+    b.sync()
+    assert torch.equal(a.get_state(), b.get_state())
+    # restart: save after 9 steps, run 6 more, restore, run 6 again
+    saved = a.get_state().clone()
+    a.step(6)
+    a.sync()
+    ref = a.get_state().clone()
+    a.set_state(saved)
+    a.step(6)
+    a.sync()
+    assert torch.equal(a.get_state(), ref)
+    # each channel alone (the ensemble's state is the channels' states in order)
+    raw = ref.view(torch.uint8).reshape(-1)
+    off = 0
+    for k, c in enumerate(CHANNELS):
+        kw = {n: v for n, v in c.items() if n not in ("centres", "radii")}
+        sim = lb.Simulation(lattice="D3Q19", storage=storage, nc="explicit", **kw)
+        sim.set_z_per_block(4)
+        sim.init_droplets(c["centres"], c["radii"])
+        sim.step(15)
+        sim.sync()
+        alone = sim.get_state().contiguous().view(torch.uint8).reshape(-1)
+        nb = alone.numel()
+        assert torch.equal(raw[off:off + nb], alone), k
+        off += nb
+        sim.close()
+    assert off == raw.numel()
     a.close()
     b.close()
 
