@@ -811,17 +811,21 @@ __device__ __forceinline__ void commit_scalars(float* __restrict__ sring, int sl
 // colour A of the pulled population i at the site of `n`, shifted by w_i rho0/2,
 // from the raw total T (already loaded from the upstream node, or from the
 // site itself in the opposite direction under bounce-back) and the upstream
-// node's scalars in the ring (centre position sc0, centre plane slot zcs)
-template <class L, class TS, int I, class R>
+// node's scalars in the ring (centre position sc0, centre plane slot zcs).
+// OPEN: no lane of the wave has a solid neighbour, so the upstream node is
+// always x - c_i and its ring position a fixed offset from the centre (no
+// per-direction selects)
+template <class L, class TS, int I, class R, bool OPEN = false>
 __device__ __forceinline__ R colour_a(R T, const float* __restrict__ sring, const Nbr& n, int zcs, int sc0,
                                       R rho0, R h) {
   constexpr int cx = L::cx[I], cy = L::cy[I], cz = L::cz[I];
   constexpr int ix = 1 - cx, iy = 1 - cy, iz = 1 - cz;
   // branch-free selects (see pull_index)
-  const uint32_t solid = (uint32_t)n.solid_x[ix] | (uint32_t)n.solid_y[iy] | (uint32_t)n.solid_z[iz];
+  const uint32_t solid =
+      OPEN ? 0u : ((uint32_t)n.solid_x[ix] | (uint32_t)n.solid_y[iy] | (uint32_t)n.solid_z[iz]);
   const int moving = ring_slot(zcs, -cz, TS::NPL) * ScalarRing<TS>::SLOT + sc0 - cy * TS::TXH - cx;
   const int bounced = zcs * ScalarRing<TS>::SLOT + sc0;
-  const int idx = moving ^ ((moving ^ bounced) & (int)(0u - solid));
+  const int idx = OPEN ? moving : moving ^ ((moving ^ bounced) & (int)(0u - solid));
   const float* q = sring + idx;
   const R aa = (R)q[0];
   R v = aa * T + (R)L::w[I] * (aa * rho0 - h);
@@ -832,7 +836,8 @@ __device__ __forceinline__ R colour_a(R T, const float* __restrict__ sring, cons
     if constexpr (cz != 0) cb += (R)cz * (R)q[3 * TS::PL];
     // the bounced population moved along -c_i before the wall reversed it
     const R t = (R)(L::w[I] * inv_norm<L>(I)) * cb;
-    v += solid ? -t : t;
+    if constexpr (OPEN) v += t;
+    else v += solid ? -t : t;
   }
   return v;
 }
@@ -865,26 +870,58 @@ __device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, cons
   for (int z = z0; z < z1; ++z) {
     const bool more = TS::RZ && z + 1 < z1;
     float nxt[ScalarRing<TS>::NPER];
-    if (more) fetch_scalars<TS>(nxt, z + 1 + TS::RZ, scin, x0, y0, a, tid);
+    if (more) {
+      // (the halo positions are formed again each plane rather than kept
+      // live across the loop)
+      int tido = tid;
+      asm volatile("" : "+v"(tido));
+      fetch_scalars<TS>(nxt, z + 1 + TS::RZ, scin, x0, y0, a, tido);
+    }
     // opaque base: the pair descriptors are built next to their use
     const S* finT = fin;
     asm volatile("" : "+s"(finT));
     if (valid_xy) {
-      const Nbr n = make_nbr(x, y, z, a);
-      float Tv[L::Q];
-      static_for<0, L::Q>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        const uint32_t e = OWN ? own_reversed_index<L, I>(n, a.N) : pull_index<L, I>(n, a.N);
-        Tv[I] = total_bload<S>(pair_rsrc<L, I>(finT, a.N), e * (uint32_t)sizeof(S));
-      });
+      // opaque coordinates: the per-site offsets are formed here each plane
+      // instead of being hoisted out of the loop (where they would stay live
+      // across it)
+      int xo = x, yo = y;
+      asm volatile("" : "+v"(xo), "+v"(yo));
+      const Nbr n = make_nbr(xo, yo, z, a);
       const int zcs = plane_slot(z, TS::NPL);
+      // rows away from the walls (most of them) skip the bounce-back selects
+      // of the pull and of the ring positions
       float sa = 0.f, sb = 0.f;
-      static_for<0, L::Q>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        const float da = colour_a<L, TS, I, float>(Tv[I], sring, n, zcs, sc0, rho0, h);
-        sa += da;
-        sb += Tv[I] - da;
-      });
+      // directions [I0, I1): loads, then their colour A
+      auto group = [&](auto open, auto i0, auto i1) {
+        constexpr bool OPEN = decltype(open)::value;
+        constexpr int I0 = decltype(i0)::value, I1 = decltype(i1)::value;
+        float Tv[L::Q];
+        static_for<I0, I1>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          const uint32_t e = OWN ? own_reversed_index<L, I>(n, a.N)
+                                 : (OPEN ? pull_index_open<L, I>(n, a.N) : pull_index<L, I>(n, a.N));
+          Tv[I] = total_bload<S>(pair_rsrc<L, I>(finT, a.N), e * (uint32_t)sizeof(S));
+        });
+        static_for<I0, I1>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          const float da = colour_a<L, TS, I, float, OPEN>(Tv[I], sring, n, zcs, sc0, rho0, h);
+          sa += da;
+          sb += Tv[I] - da;
+        });
+      };
+      using Ic0 = std::integral_constant<int, 0>;
+      using IcH = std::integral_constant<int, L::Q / 2>;
+      using IcQ = std::integral_constant<int, L::Q>;
+      if (wave_open(n)) {
+        group(std::true_type{}, Ic0{}, IcQ{});
+      } else {
+        // rows at a wall (few): two halves, so that this variant needs no
+        // more registers than the open one (the barrier keeps the second
+        // half's loads after the first half's arithmetic)
+        group(std::false_type{}, Ic0{}, IcH{});
+        asm volatile("" ::: "memory");
+        group(std::false_type{}, IcH{}, IcQ{});
+      }
       phi[n.site] = (sa - sb) / (rho0 + (sa + sb));
     }
     if (more) commit_scalars<TS>(sring, plane_slot(z + 1 + TS::RZ, TS::NPL), nxt, tid);
