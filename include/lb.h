@@ -224,7 +224,11 @@ typedef struct lb_handle lb_handle;
  *  z_per_block   z-planes per collision tile (>= 1)
  *  use_graph     1: replay non-field steps from a captured hipGraph of two steps
  *                (batched mode; the per-channel mode launches directly and
- *                lb_autotune tries it without a graph only)
+ *                lb_autotune tries it without a graph only).  Single lattices
+ *                (default 0) replay pairs of non-field steps at the buffer
+ *                parities they were captured at; not with the watchdog, while
+ *                profiling, before the read-once phase field is ready or with
+ *                stochastic rounding (its key is the step count)
  *  ms_per_step   filled by lb_autotune with the measured time of the choice */
 enum { LB_ENSEMBLE_BATCHED = 0, LB_ENSEMBLE_PER_CHANNEL = 1 };
 typedef struct lb_tuning {
@@ -321,7 +325,8 @@ int lb_sync(lb_handle* h);
 int lb_channel_count(const lb_handle* h, int* n);
 
 /* Current / new ensemble launch configuration (single-lattice handles use
- * only z_per_block).  lb_set_tuning validates and rebuilds the work lists. */
+ * z_per_block and use_graph).  lb_set_tuning validates and rebuilds the work
+ * lists (and drops a captured graph). */
 int lb_get_tuning(const lb_handle* h, lb_tuning* t);
 int lb_set_tuning(lb_handle* h, const lb_tuning* t);
 

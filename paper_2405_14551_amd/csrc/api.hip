@@ -155,7 +155,8 @@ struct lb_handle {
   uint32_t* d_items_cb = nullptr;    // read-once step: combine blocks of every channel
   uint32_t n_items_ph = 0, n_items_co = 0, n_items_cb = 0;
   lb_tuning tune{};                  // ensemble launch configuration
-  hipGraphExec_t graph = nullptr;    // two non-field steps (parity 0 then 1)
+  hipGraphExec_t graph = nullptr;    // two non-field steps (ensemble: parity 0 then 1)
+  int graph_key = 0;                 // single lattice: the parities it was captured at
   bool ensemble() const { return !chans.empty(); }
   // learned near-contact closure: FP32 parameters, Adam moments, training
   // scratch, input ranges and the network in MFMA operand order
@@ -899,6 +900,169 @@ static int ensemble_step(lb_handle* h, int nsteps) {
   return LB_OK;
 }
 
+// Enqueue one single-lattice step on stream s.  It reads the handle's state
+// (buffer parities, in-place kind, whether the read-once phase field is
+// ready) and changes none of it: single_advance does that.  Profiling marks
+// are recorded on the handle's stream (only when s is that stream).
+static int single_launch(lb_handle* h, bool fields, hipStream_t s) {
+  StepArgs a = h->step_args();
+  a.step = (uint32_t)h->t;  // keys the stochastic rounding of this step's stores
+  const FieldPtrs fo = h->field_ptrs();
+  const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
+  const bool mlp = h->p.nc_mode == LB_NC_MLP;
+  const int st = h->p.storage;
+  int r = prof_mark(h, 0, true);
+  if (r) return r;
+  if (h->moments()) {
+    // pass 1 rebuilds the pulled populations from the upstream moments,
+    // pass 2 writes the new moments into the other copy
+    HIP_TRY(h->llb->pull(st, h->f[h->cur], h->W, h->phi, a, s));
+    if ((r = prof_mark(h, 0, false))) return r;
+    if ((r = prof_mark(h, 1, true))) return r;
+    HIP_TRY(h->llb->collide(st, nc, fields, h->W, h->f[1 - h->cur], h->phi, fo, a, s));
+    return prof_mark(h, 1, false);
+  }
+  if (h->ro) {
+    // read-once step: the collision pass reads phi_at(pcur) and scatters
+    // the next step's colour densities; the combine pass turns them into
+    // the next phase field in the other buffer.  The first step after
+    // lb_init_droplets / lb_set_state scatters the stored state first (the
+    // bootstrap pass, bit for bit what the collision pass that stored it
+    // would have scattered), so restarts repeat uninterrupted runs exactly.
+    StepArgs b = a;
+    b.z_per_block = h->ro_zb;
+    const ScatterOut so{h->ro_part, h->ro_halo};
+    void* phin = h->phi_at(h->pcur);
+    void* phout = h->phi_at(1 - h->pcur);
+    if (h->in_place()) {
+      void* f = h->f[0];
+      float* sc = h->sc[0];
+      const int odd = h->ip_odd;
+      if (!h->phi_ready) {
+        // an initialised or restored state is canonical (odd == 0); the
+        // phase pass covers any other case
+        if (odd) {
+          HIP_TRY(h->ip->phase_odd(st, f, sc, phin, a, s));
+        } else {
+          HIP_TRY(h->ops->boot(st, f, sc, so, b, s));
+          HIP_TRY(h->ops->combine(st, so, phin, b, s));
+        }
+        if ((r = prof_mark(h, 0, false))) return r;
+      }
+      // (without the phase pass, the next mark reuses the open one)
+      if ((r = prof_mark(h, 1, true))) return r;
+      if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, phin, fo, b, h->mlp_net, &so, s));
+      else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, phin, fo, b, &so, s));
+    } else {
+      void* fin = h->f[h->cur];
+      void* fout = h->f[1 - h->cur];
+      if (!h->phi_ready) {
+        HIP_TRY(h->ops->boot(st, fin, h->sc[h->cur], so, b, s));
+        HIP_TRY(h->ops->combine(st, so, phin, b, s));
+        if ((r = prof_mark(h, 0, false))) return r;
+      }
+      if ((r = prof_mark(h, 1, true))) return r;
+      if (mlp)
+        HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], phin, fo, b, h->mlp_net, &so, s));
+      else
+        HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], phin, fo, b, &so, s));
+    }
+    if ((r = prof_mark(h, 1, false))) return r;
+    if ((r = prof_mark(h, 2, true))) return r;
+    HIP_TRY(h->ops->combine(st, so, phout, b, s));
+    return prof_mark(h, 2, false);
+  }
+  if (h->in_place()) {
+    // one copy: even steps pull and push, odd steps work on the site's own slots
+    void* f = h->f[0];
+    float* sc = h->sc[0];
+    const int odd = h->ip_odd;
+    if (odd) HIP_TRY(h->ip->phase_odd(st, f, sc, h->phi, a, s));
+    else HIP_TRY(h->ops->phase(st, f, sc, h->phi, a, s));
+    if ((r = prof_mark(h, 0, false))) return r;
+    if ((r = prof_mark(h, 1, true))) return r;
+    if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, h->phi, fo, a, h->mlp_net, nullptr, s));
+    else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, h->phi, fo, a, nullptr, s));
+    return prof_mark(h, 1, false);
+  }
+  void* fin = h->f[h->cur];
+  void* fout = h->f[1 - h->cur];
+  HIP_TRY(h->ops->phase(st, fin, h->sc[h->cur], h->phi, a, s));
+  if ((r = prof_mark(h, 0, false))) return r;
+  if ((r = prof_mark(h, 1, true))) return r;
+  if (mlp)
+    HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->mlp_net, nullptr, s));
+  else
+    HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, nullptr, s));
+  return prof_mark(h, 1, false);
+}
+
+// the state change of one single-lattice step
+static void single_advance(lb_handle* h, bool fields) {
+  if (h->in_place() && !h->moments()) h->ip_odd = 1 - h->ip_odd;
+  else h->cur = 1 - h->cur;
+  if (h->ro) {
+    if (fields) h->pfield = h->pcur;
+    h->pcur = 1 - h->pcur;
+    h->phi_ready = true;
+  }
+  h->t += 1;
+  if (fields) h->fields_valid = true;
+}
+
+// the buffer parities a single-lattice graph was captured at; two steps
+// bring them back
+static int single_graph_key(const lb_handle* h) { return h->cur | (h->pcur << 1) | (h->ip_odd << 2); }
+
+// capture two non-field single-lattice steps into a graph, starting at the
+// current buffer parities (the read-once phase field must be ready)
+static int single_graph(lb_handle* h) {
+  if (h->graph) return LB_OK;
+  hipStream_t cap = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  int rc = LB_OK;
+  // the launches read the handle's state: step it through the two steps
+  // while capturing and put it back afterwards
+  const int cur0 = h->cur, pcur0 = h->pcur, pfield0 = h->pfield, odd0 = h->ip_odd;
+  const bool ready0 = h->phi_ready, valid0 = h->fields_valid;
+  const long long t0 = h->t;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = fail(LB_EHIP, "hipStreamBeginCapture failed");
+  } else {
+    int r = single_launch(h, false, cap);
+    if (!r) {
+      single_advance(h, false);
+      r = single_launch(h, false, cap);
+    }
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    if (r) rc = r;
+    else if (e != hipSuccess || !g) rc = fail(LB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    else if (hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0) != hipSuccess)
+      rc = fail(LB_EHIP, "hipGraphInstantiate failed");
+  }
+  h->cur = cur0;
+  h->pcur = pcur0;
+  h->pfield = pfield0;
+  h->ip_odd = odd0;
+  h->phi_ready = ready0;
+  h->t = t0;
+  h->fields_valid = valid0;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
+  if (rc) h->graph = nullptr;
+  else h->graph_key = single_graph_key(h);
+  return rc;
+}
+
+static int single_graph_drop(lb_handle* h) {
+  if (!h->graph) return LB_OK;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipGraphExecDestroy(h->graph));
+  h->graph = nullptr;
+  return LB_OK;
+}
+
 int lb_step(lb_handle* h, int nsteps) {
   if (!h) return fail(LB_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
@@ -910,110 +1074,29 @@ int lb_step(lb_handle* h, int nsteps) {
   if (h->p.nc_mode == LB_NC_MLP && !h->mlp_weights)
     return fail(LB_EINVAL, "LB_NC_MLP needs network parameters (lb_mlp_set_weights or lb_mlp_train)");
   (void)hipSetDevice(h->device);
-  StepArgs a = h->step_args();
-  const FieldPtrs fo = h->field_ptrs();
-  const bool nc = h->p.nc_mode == LB_NC_EXPLICIT;
-  const bool mlp = h->p.nc_mode == LB_NC_MLP;
-  const int st = h->p.storage;
-  for (int s = 0; s < nsteps; ++s) {
-    a.step = (uint32_t)h->t;  // keys the stochastic rounding of this step's stores
+  // graph replays: pairs of non-field steps at the captured parities, without
+  // the watchdog, profiling or stochastic rounding (whose key is the step)
+  const bool graph_ok = h->tune.use_graph && h->p.diag_every <= 0 && h->p.rounding != LB_ROUND_STOCHASTIC;
+  int s = 0;
+  while (s < nsteps) {
     const bool diag_now = h->p.diag_every > 0 && ((h->t + 1) % h->p.diag_every) == 0;
     const bool fields = (s == nsteps - 1) || diag_now;
-    int r = prof_mark(h, 0, true);
-    if (r) return r;
-    if (h->moments()) {
-      // pass 1 rebuilds the pulled populations from the upstream moments,
-      // pass 2 writes the new moments into the other copy
-      HIP_TRY(h->llb->pull(st, h->f[h->cur], h->W, h->phi, a, h->stream));
-      if ((r = prof_mark(h, 0, false))) return r;
-      if ((r = prof_mark(h, 1, true))) return r;
-      HIP_TRY(h->llb->collide(st, nc, fields, h->W, h->f[1 - h->cur], h->phi, fo, a, h->stream));
-      if ((r = prof_mark(h, 1, false))) return r;
-      h->cur = 1 - h->cur;
-    } else if (h->ro) {
-      // read-once step: the collision pass reads phi_at(pcur) and scatters
-      // the next step's colour densities; the combine pass turns them into
-      // the next phase field in the other buffer.  The first step after
-      // lb_init_droplets / lb_set_state scatters the stored state first (the
-      // bootstrap pass, bit for bit what the collision pass that stored it
-      // would have scattered), so restarts repeat uninterrupted runs exactly.
-      StepArgs b = a;
-      b.z_per_block = h->ro_zb;
-      const ScatterOut so{h->ro_part, h->ro_halo};
-      void* phin = h->phi_at(h->pcur);
-      void* phout = h->phi_at(1 - h->pcur);
-      if (h->in_place()) {
-        void* f = h->f[0];
-        float* sc = h->sc[0];
-        const int odd = h->ip_odd;
-        if (!h->phi_ready) {
-          // an initialised or restored state is canonical (odd == 0); the
-          // phase pass covers any other case
-          if (odd) {
-            HIP_TRY(h->ip->phase_odd(st, f, sc, phin, a, h->stream));
-          } else {
-            HIP_TRY(h->ops->boot(st, f, sc, so, b, h->stream));
-            HIP_TRY(h->ops->combine(st, so, phin, b, h->stream));
-          }
-          if ((r = prof_mark(h, 0, false))) return r;
-        }
-        // (without the phase pass, the next mark reuses the open one)
-        if ((r = prof_mark(h, 1, true))) return r;
-        if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, phin, fo, b, h->mlp_net, &so, h->stream));
-        else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, phin, fo, b, &so, h->stream));
-        h->ip_odd = 1 - odd;
-      } else {
-        void* fin = h->f[h->cur];
-        void* fout = h->f[1 - h->cur];
-        if (!h->phi_ready) {
-          HIP_TRY(h->ops->boot(st, fin, h->sc[h->cur], so, b, h->stream));
-          HIP_TRY(h->ops->combine(st, so, phin, b, h->stream));
-          if ((r = prof_mark(h, 0, false))) return r;
-        }
-        if ((r = prof_mark(h, 1, true))) return r;
-        if (mlp)
-          HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], phin, fo, b, h->mlp_net, &so,
-                                      h->stream));
-        else
-          HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], phin, fo, b, &so, h->stream));
-        h->cur = 1 - h->cur;
+    if (graph_ok && !fields && s + 2 <= nsteps - 1 && !h->prof_on && (!h->ro || h->phi_ready)) {
+      int r = single_graph(h);
+      if (r) return r;
+      if (h->graph_key == single_graph_key(h)) {
+        HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+        single_advance(h, false);
+        single_advance(h, false);
+        s += 2;
+        continue;
       }
-      if ((r = prof_mark(h, 1, false))) return r;
-      if ((r = prof_mark(h, 2, true))) return r;
-      HIP_TRY(h->ops->combine(st, so, phout, b, h->stream));
-      if ((r = prof_mark(h, 2, false))) return r;
-      if (fields) h->pfield = h->pcur;
-      h->pcur = 1 - h->pcur;
-      h->phi_ready = true;
-    } else if (h->in_place()) {
-      // one copy: even steps pull and push, odd steps work on the site's own slots
-      void* f = h->f[0];
-      float* sc = h->sc[0];
-      const int odd = h->ip_odd;
-      if (odd) HIP_TRY(h->ip->phase_odd(st, f, sc, h->phi, a, h->stream));
-      else HIP_TRY(h->ops->phase(st, f, sc, h->phi, a, h->stream));
-      if ((r = prof_mark(h, 0, false))) return r;
-      if ((r = prof_mark(h, 1, true))) return r;
-      if (mlp) HIP_TRY(h->ip->collide_mlp(st, odd, fields, f, sc, h->phi, fo, a, h->mlp_net, nullptr, h->stream));
-      else HIP_TRY(h->ip->collide(st, odd, nc, fields, f, sc, h->phi, fo, a, nullptr, h->stream));
-      if ((r = prof_mark(h, 1, false))) return r;
-      h->ip_odd = 1 - odd;
-    } else {
-      void* fin = h->f[h->cur];
-      void* fout = h->f[1 - h->cur];
-      HIP_TRY(h->ops->phase(st, fin, h->sc[h->cur], h->phi, a, h->stream));
-      if ((r = prof_mark(h, 0, false))) return r;
-      if ((r = prof_mark(h, 1, true))) return r;
-      if (mlp)
-        HIP_TRY(h->ops->collide_mlp(st, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, h->mlp_net, nullptr,
-                                    h->stream));
-      else
-        HIP_TRY(h->ops->collide(st, nc, fields, fin, fout, h->sc[1 - h->cur], h->phi, fo, a, nullptr, h->stream));
-      if ((r = prof_mark(h, 1, false))) return r;
-      h->cur = 1 - h->cur;
+      // the other parity: one step directly brings it in line
     }
-    h->t += 1;
-    if (fields) h->fields_valid = true;
+    int r = single_launch(h, fields, h->stream);
+    if (r) return r;
+    single_advance(h, fields);
+    s += 1;
     if (diag_now) {
       r = run_diag(h);
       if (r) return r;
@@ -1269,6 +1352,7 @@ int lb_get_tuning(const lb_handle* h, lb_tuning* t) {
   } else {
     std::memset(t, 0, sizeof *t);
     t->z_per_block = h->z_per_block;
+    t->use_graph = h->tune.use_graph;
   }
   return LB_OK;
 }
@@ -1276,12 +1360,17 @@ int lb_get_tuning(const lb_handle* h, lb_tuning* t) {
 int lb_set_tuning(lb_handle* h, const lb_tuning* t) {
   if (!h || !t) return fail(LB_EINVAL, "NULL argument");
   if (t->z_per_block < 1 || t->z_per_block > 4096) return fail(LB_EINVAL, "z_per_block must lie in [1, 4096]");
+  if (t->use_graph != 0 && t->use_graph != 1) return fail(LB_EINVAL, "use_graph must be 0 or 1");
   if (!h->ensemble()) {
+    // the graph holds the launch shapes and the read-once halo buffers
+    (void)hipSetDevice(h->device);
+    int rc = single_graph_drop(h);
+    if (rc) return rc;
     h->z_per_block = t->z_per_block;
+    h->tune.use_graph = t->use_graph;
     return h->ro ? ro_plan(h) : LB_OK;
   }
   if (t->mode != LB_ENSEMBLE_BATCHED && t->mode != LB_ENSEMBLE_PER_CHANNEL) return fail(LB_EINVAL, "unknown mode");
-  if (t->use_graph != 0 && t->use_graph != 1) return fail(LB_EINVAL, "use_graph must be 0 or 1");
   const int zb_old = h->tune.z_per_block;
   h->tune = *t;
   h->tune.ms_per_step = 0.0;
@@ -1317,11 +1406,13 @@ int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int c
         }
   } else {
     for (int zb : {1, 2, 4, 8, 16})
-      if (zb <= h->p.nz) {
-        lb_tuning t{};
-        t.z_per_block = zb;
-        cand.push_back(t);
-      }
+      for (int graph : {0, 1})
+        if (zb <= h->p.nz) {
+          lb_tuning t{};
+          t.z_per_block = zb;
+          t.use_graph = graph;
+          cand.push_back(t);
+        }
   }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));

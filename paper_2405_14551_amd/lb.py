@@ -255,6 +255,15 @@ class Simulation:
         check(lib().lb_set_tuning(self.h, ctypes.byref(t)))
         return self
 
+    def set_graph(self, on=True):
+        """Replay pairs of non-field steps from a captured hipGraph
+        (lb_tuning.use_graph on a single lattice)."""
+        t = LbTuning()
+        check(lib().lb_get_tuning(self.h, ctypes.byref(t)))
+        t.use_graph = int(bool(on))
+        check(lib().lb_set_tuning(self.h, ctypes.byref(t)))
+        return self
+
     def profile_begin(self):
         check(lib().lb_profile_begin(self.h))
 
