@@ -155,6 +155,11 @@ struct lb_handle {
   uint32_t* d_items_cb = nullptr;    // read-once step: combine blocks of every channel
   uint32_t n_items_ph = 0, n_items_co = 0, n_items_cb = 0;
   lb_tuning tune{};                  // ensemble launch configuration
+  // read-once batched collision: store the populations through L2 (some
+  // channel's rows do not start on 64-byte boundaries, so neighbouring tiles
+  // write the two ends of one line; non-temporal stores would send each part
+  // to memory on its own)
+  bool ens_cached = false;
   hipGraphExec_t graph = nullptr;    // two non-field steps (ensemble: parity 0 then 1)
   int graph_key = 0;                 // single lattice: the parities it was captured at
   bool ensemble() const { return !chans.empty(); }
@@ -687,6 +692,14 @@ static int ensemble_plan(lb_handle* h) {
     }
     tiles[c] = d.ntiles;
   }
+  h->ens_cached = false;
+  for (lb_handle* s : h->chans)
+    if (((size_t)s->p.nx * h->esize) % 64 != 0) h->ens_cached = true;
+  if (const char* env = std::getenv("LB_ENSEMBLE_STORES")) {
+    // measurement override: "nt" (non-temporal) or "cached"
+    if (!std::strcmp(env, "nt")) h->ens_cached = false;
+    else if (!std::strcmp(env, "cached")) h->ens_cached = true;
+  }
   // largest channels first, so that the small ones fill the tail of a launch
   std::vector<int> order(nch);
   for (int c = 0; c < nch; ++c) order[c] = c;
@@ -785,10 +798,12 @@ static int ensemble_launch(lb_handle* h, bool fields, int parity, hipStream_t s)
     // read-once: every channel's collision tile-marches (with the scatter),
     // then every channel's combine blocks
     if ((rc = prof_mark(h, 1, true))) return rc;
-    HIP_TRY(h->ops->ensemble_ro(h->p.storage, nc, fields, false, h->d_chans, h->d_items_co, h->n_items_co, parity, s));
+    HIP_TRY(h->ops->ensemble_ro(h->p.storage, nc, fields, false, h->ens_cached, h->d_chans, h->d_items_co,
+                                h->n_items_co, parity, s));
     if ((rc = prof_mark(h, 1, false))) return rc;
     if ((rc = prof_mark(h, 2, true))) return rc;
-    HIP_TRY(h->ops->ensemble_ro(h->p.storage, nc, fields, true, h->d_chans, h->d_items_cb, h->n_items_cb, parity, s));
+    HIP_TRY(h->ops->ensemble_ro(h->p.storage, nc, fields, true, false, h->d_chans, h->d_items_cb, h->n_items_cb,
+                                parity, s));
     return prof_mark(h, 2, false);
   }
   if (h->tune.mode == LB_ENSEMBLE_BATCHED) {

@@ -137,7 +137,7 @@ struct CollideLaunch {
 // read-once batched ensemble launches (two-copy streaming)
 template <class L>
 struct EnsembleRoLaunch {
-  template <class S, bool TOT>
+  template <class S, bool TOT, int SCP = CPOL_NT>
   static hipError_t run_s(bool nc, bool fields, bool combine, const ChannelDev* chans, const uint32_t* items,
                           uint32_t nitems, int parity, hipStream_t s) {
     using R = typename Storage<S>::real;
@@ -150,17 +150,26 @@ struct EnsembleRoLaunch {
     }
     if (nc) {
       using T = Tile<TILE_X, TILE_Y, 4, L::D>;
-      if (fields) k_ensemble_ro<L, S, T, true, true, TOT><<<grid, block, 0, s>>>(chans, items, parity);
-      else k_ensemble_ro<L, S, T, true, false, TOT><<<grid, block, 0, s>>>(chans, items, parity);
+      if (fields) k_ensemble_ro<L, S, T, true, true, TOT, SCP><<<grid, block, 0, s>>>(chans, items, parity);
+      else k_ensemble_ro<L, S, T, true, false, TOT, SCP><<<grid, block, 0, s>>>(chans, items, parity);
     } else {
       using T = Tile<TILE_X, TILE_Y, 1, L::D>;
-      if (fields) k_ensemble_ro<L, S, T, false, true, TOT><<<grid, block, 0, s>>>(chans, items, parity);
-      else k_ensemble_ro<L, S, T, false, false, TOT><<<grid, block, 0, s>>>(chans, items, parity);
+      if (fields) k_ensemble_ro<L, S, T, false, true, TOT, SCP><<<grid, block, 0, s>>>(chans, items, parity);
+      else k_ensemble_ro<L, S, T, false, false, TOT, SCP><<<grid, block, 0, s>>>(chans, items, parity);
     }
     return hipGetLastError();
   }
-  static hipError_t run(int st, bool nc, bool fields, bool combine, const ChannelDev* chans, const uint32_t* items,
-                        uint32_t nitems, int parity, hipStream_t s) {
+  static hipError_t run(int st, bool nc, bool fields, bool combine, bool cached, const ChannelDev* chans,
+                        const uint32_t* items, uint32_t nitems, int parity, hipStream_t s) {
+    // cached stores for the 4- and 8-byte storages (16-bit ensembles take the
+    // two-pass step unless asked otherwise)
+    if (cached && !combine) {
+      switch (st) {
+        case ST_F64: return run_s<double, false, 0>(nc, fields, combine, chans, items, nitems, parity, s);
+        case ST_F32: return run_s<float, false, 0>(nc, fields, combine, chans, items, nitems, parity, s);
+        case ST_F32T: return run_s<float, true, 0>(nc, fields, combine, chans, items, nitems, parity, s);
+      }
+    }
     switch (st) {
       case ST_F64: return run_s<double, false>(nc, fields, combine, chans, items, nitems, parity, s);
       case ST_F32: return run_s<float, false>(nc, fields, combine, chans, items, nitems, parity, s);
@@ -174,9 +183,9 @@ struct EnsembleRoLaunch {
 };
 
 template <class L>
-hipError_t ensemble_ro_impl(int st, bool nc, bool fields, bool combine, const ChannelDev* chans,
+hipError_t ensemble_ro_impl(int st, bool nc, bool fields, bool combine, bool cached, const ChannelDev* chans,
                             const uint32_t* items, uint32_t nitems, int parity, hipStream_t s) {
-  return EnsembleRoLaunch<L>::run(st, nc, fields, combine, chans, items, nitems, parity, s);
+  return EnsembleRoLaunch<L>::run(st, nc, fields, combine, cached, chans, items, nitems, parity, s);
 }
 
 template <class L, int STREAM, bool RO>
@@ -208,6 +217,6 @@ hipError_t collide_mlp_impl(int st, bool fields, const void* fin, void* fout, fl
 // the read-once ensemble launches of one lattice (in its two-copy read-once unit)
 #define LB_INSTANTIATE_ENSEMBLE_RO(LAT)                                                                      \
   namespace lbm {                                                                                          \
-  template hipError_t ensemble_ro_impl<LAT>(int, bool, bool, bool, const ChannelDev*, const uint32_t*,      \
+  template hipError_t ensemble_ro_impl<LAT>(int, bool, bool, bool, bool, const ChannelDev*, const uint32_t*,\
                                             uint32_t, int, hipStream_t);                                   \
   }

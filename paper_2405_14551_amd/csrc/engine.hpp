@@ -60,8 +60,10 @@ struct LatticeOps {
                      hipStream_t s);
   // read-once batched ensemble launch (storages as for `ensemble`): combine
   // false: every item is a collision tile-march (collision with the
-  // scatter); combine true: every item is a combine block
-  hipError_t (*ensemble_ro)(int storage, bool nc, bool fields, bool combine, const ChannelDev* chans,
+  // scatter); combine true: every item is a combine block.  cached: the
+  // populations are stored through L2 instead of non-temporally (for rows
+  // that do not start on 64-byte boundaries, whose line ends two tiles write)
+  hipError_t (*ensemble_ro)(int storage, bool nc, bool fields, bool combine, bool cached, const ChannelDev* chans,
                             const uint32_t* items, uint32_t nitems, int parity, hipStream_t s);
 };
 

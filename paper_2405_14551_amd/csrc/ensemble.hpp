@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(T::NT) k_ensemble(const ChannelDev* __restrict
 // Read-once ensemble step, first launch: every channel's collision tiles with
 // the read-once scatter (one tile-march per workgroup; the item names the
 // channel and the tile-march, as for the two-pass collision).
-template <class L, class S, class T, bool NC, bool FIELDS, bool TOT>
+template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, int SCP = CPOL_NT>
 __global__ void __launch_bounds__(T::NT, (collide_min_waves<S, TOT, true>()))
     k_ensemble_ro(const ChannelDev* __restrict__ chans, const uint32_t* __restrict__ items, int parity) {
   using R = typename Storage<S>::real;
@@ -150,8 +150,8 @@ __global__ void __launch_bounds__(T::NT, (collide_min_waves<S, TOT, true>()))
   fo.fnc = uniform_ptr(C->fo.fnc);
   fo.flags = uniform_ptr(C->fo.flags);
   const ScatterOut so{uniform_ptr(C->part), uniform_ptr(C->halo)};
-  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM_AB, false, true>(fin, fout, phi, scout, fo, a, tc, sm, nullptr,
-                                                                        so);
+  collide_tile<L, S, T, NC, FIELDS, TOT, false, STREAM_AB, false, true, false, SCP>(fin, fout, phi, scout, fo, a, tc,
+                                                                                    sm, nullptr, so);
 }
 
 // Read-once ensemble step, second launch: every channel's combine blocks.

@@ -21,7 +21,7 @@ hipError_t collide_mlp_impl(int st, bool fields, const void* fin, void* fout, fl
                             const FieldPtrs& fo, const StepArgs& a, const MlpPacked* net, const ScatterOut* ro,
                             hipStream_t s);
 template <class L>
-hipError_t ensemble_ro_impl(int st, bool nc, bool fields, bool combine, const ChannelDev* chans,
+hipError_t ensemble_ro_impl(int st, bool nc, bool fields, bool combine, bool cached, const ChannelDev* chans,
                             const uint32_t* items, uint32_t nitems, int parity, hipStream_t s);
 
 template <class L>

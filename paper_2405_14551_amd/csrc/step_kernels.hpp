@@ -89,10 +89,10 @@ struct Storage<double> {
   __device__ static __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, double h) {
     return shift_down<I, L>(__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, CP)), h);
   }
-  template <int I, class L>
+  template <int I, class L, int CP = CPOL_NT>
   __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double d, double h) {
     using u2 = unsigned __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, shift_up<I, L>(d, h)), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, shift_up<I, L>(d, h)), r, vo, so, CP);
   }
   template <int I, class L>
   __device__ static __forceinline__ double load(const double* p, double h) { return shift_down<I, L>(*p, h); }
@@ -122,9 +122,9 @@ struct Storage<float> {
   __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float h) {
     return shift_down<I, L>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, CP)), h);
   }
-  template <int I, class L>
+  template <int I, class L, int CP = CPOL_NT>
   __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float h) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, shift_up<I, L>(d, h)), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, shift_up<I, L>(d, h)), r, vo, so, CP);
   }
   template <int I, class L>
   __device__ static __forceinline__ float load(const float* p, float h) { return shift_down<I, L>(*p, h); }
@@ -151,9 +151,9 @@ struct Storage<_Float16> {
   __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float) {
     return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, CP));
   }
-  template <int I, class L>
+  template <int I, class L, int CP = CPOL_NT>
   __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)d), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)d), r, vo, so, CP);
   }
   template <int I, class L>
   __device__ static __forceinline__ float load(const _Float16* p, float) { return (float)(*p); }
@@ -178,9 +178,9 @@ struct Storage<__bf16> {
   __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float) {
     return (float)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, 0, CP));
   }
-  template <int I, class L>
+  template <int I, class L, int CP = CPOL_NT>
   __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)d), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)d), r, vo, so, CP);
   }
   template <int I, class L>
   __device__ static __forceinline__ float load(const __bf16* p, float) { return (float)(*p); }
@@ -213,9 +213,9 @@ struct Storage<F32S> {
   __device__ static __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, CP));
   }
-  template <int I, class L>
+  template <int I, class L, int CP = CPOL_NT>
   __device__ static __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float d, float) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, d), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, d), r, vo, so, CP);
   }
   template <int I, class L>
   __device__ static __forceinline__ float load(const F32S* p, float) { return p->v; }
@@ -740,14 +740,14 @@ __device__ __forceinline__ unsigned short sround_bits(float v, uint32_t word) {
   }
 }
 
-template <class S>
+template <class S, int CP = CPOL_NT>
 __device__ __forceinline__ void total_bstore(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
   if constexpr (sizeof(S) == 4)
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, CP);
   else if constexpr (std::is_same_v<S, F16C>)
-    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)f16c_encode(v), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)f16c_encode(v), r, vo, so, CP);
   else
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r, vo, so, CPOL_NT);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r, vo, so, CP);
 }
 // the total a load returns after total_bstore<S>(v)
 template <class S>
@@ -1122,7 +1122,7 @@ struct CollideSmem<L, S, T, TOT, true, RO> : CollideSmem<L, S, T, TOT, false, RO
 // scattered it, which starts the read-once step after an initialisation or a
 // restore with the same phase field, bit for bit.
 template <class L, class S, class T, bool NC, bool FIELDS, bool TOT, bool MLP = false, int STREAM = STREAM_AB,
-          bool SR = false, bool RO = false, bool BOOT = false>
+          bool SR = false, bool RO = false, bool BOOT = false, int SCP = CPOL_NT>
 __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __restrict__ fout,
                                              const typename Storage<S>::real* __restrict__ phi,
                                              float* __restrict__ scout,
@@ -1547,10 +1547,10 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
             [[maybe_unused]] float tv;  // the stored total as a load returns it
             if constexpr (SR) {
               const unsigned short bits = sround_bits<S>((float)ds, sround_word(sr_base, I, (float)ds));
-              if (!RO || live) __builtin_amdgcn_raw_buffer_store_b16(bits, rs, vo, so, CPOL_NT);
+              if (!RO || live) __builtin_amdgcn_raw_buffer_store_b16(bits, rs, vo, so, SCP);
               if constexpr (RO) tv = (float)__builtin_bit_cast(S, bits);
             } else {
-              if (!RO || live) total_bstore<S>(rs, vo, so, (float)ds);
+              if (!RO || live) total_bstore<S, SCP>(rs, vo, so, (float)ds);
               if constexpr (RO) tv = total_rt<S>((float)ds);
             }
             if constexpr (RO) {
@@ -1564,8 +1564,8 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
             const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
             const R db = ds - da;
             if (!RO || live) {
-              Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
-              Storage<S>::template bstore<I, L>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
+              Storage<S>::template bstore<I, L, SCP>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
+              Storage<S>::template bstore<I, L, SCP>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
             }
             if constexpr (RO)
               route(ic, Storage<S>::template stored<I, L>(da, hshift), Storage<S>::template stored<I, L>(db, hshift),
