@@ -255,6 +255,25 @@ class Simulation:
         check(lib().lb_set_tuning(self.h, ctypes.byref(t)))
         return self
 
+    def tuning(self):
+        """dict(z_per_block, use_graph) of this lattice (lb_get_tuning)."""
+        t = LbTuning()
+        check(lib().lb_get_tuning(self.h, ctypes.byref(t)))
+        return {"z_per_block": t.z_per_block, "use_graph": t.use_graph}
+
+    def autotune(self, steps=4):
+        """Time z-planes per march {1, 2, 4, 8, 16} (up to nz) with and without
+        graph replays (the timed steps advance the simulation), keep the
+        fastest and return (best, table) (lb_autotune)."""
+        best = LbTuning()
+        cap = 64
+        res = (ctypes.c_double * (4 * cap))()
+        n = ctypes.c_int()
+        check(lib().lb_autotune(self.h, int(steps), ctypes.byref(best), res, cap, ctypes.byref(n)))
+        table = [{"z_per_block": int(res[4 * k + 1]), "use_graph": int(res[4 * k + 2]), "ms_per_step": res[4 * k + 3]}
+                 for k in range(min(n.value, cap))]
+        return {"z_per_block": best.z_per_block, "use_graph": best.use_graph, "ms_per_step": best.ms_per_step}, table
+
     def set_graph(self, on=True):
         """Replay pairs of non-field steps from a captured hipGraph
         (lb_tuning.use_graph on a single lattice)."""

@@ -1,8 +1,8 @@
 """GPU tests of the batched ensemble (independent channels of different
 sizes, walls, tau and forces advanced together): each channel against the
 FP64 oracle in both launch modes, with and without the captured graph; graph
-replays against eager stepping; the read-once step's launch modes, restart
-and stand-alone channels bit for bit; and the autotuner."""
+replays against eager stepping; the read-once step's launch modes, store
+policies, restart and stand-alone channels bit for bit; and the autotuner."""
 import sys
 
 import numpy as np
@@ -138,6 +138,26 @@ def test_read_once_modes_restart_and_single_lattice_agree_bitwise(storage):
         off += nb
         sim.close()
     assert off == raw.numel()
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("stores", ["nt", "cached"])
+def test_read_once_store_policies_agree_bitwise(stores, monkeypatch):
+    """The batched read-once collision stores the populations non-temporally
+    or through L2 (chosen from the channels' row alignment, forced here both
+    ways): the state equals the per-channel launches' bit for bit."""
+    say(f"case ensemble read-once stores={stores}")
+    monkeypatch.setenv("LB_ENSEMBLE_STORES", stores)
+    a = make("f32")
+    b = make("f32")
+    a.set_tuning("batched", z_per_block=4, use_graph=0)
+    b.set_tuning("per_channel", z_per_block=4, use_graph=0)
+    a.step(7)
+    b.step(7)
+    a.sync()
+    b.sync()
+    assert torch.equal(a.get_state(), b.get_state())
     a.close()
     b.close()
 

@@ -4,7 +4,8 @@ direct launches bit for bit, in every step structure: the read-once step
 (two copies and in place), the two-pass step (two copies and in place), the
 moment scheme, the learned closure and a D2Q9 lattice.  Replays alternate
 with direct steps, field reads, restores and a change of march depth, and
-every replay is compared with the direct run."""
+every replay is compared with the direct run.  Also the single-lattice
+autotuner over march depths and graph replays."""
 import sys
 
 import numpy as np
@@ -95,3 +96,20 @@ def test_graph_replays_match_direct_launches_bitwise(name):
         assert same(a, b), (name, "z_per_block")
     a.close()
     b.close()
+
+
+def test_single_lattice_autotune_covers_depths_and_graphs():
+    """lb_autotune on a single lattice times every march depth up to nz with
+    and without graph replays, keeps the fastest and leaves it set."""
+    say("case single-lattice autotune")
+    sim = make("f32_read_once", False)
+    best, table = sim.autotune(steps=3)
+    cands = {(r["z_per_block"], r["use_graph"]) for r in table}
+    assert cands == {(zb, g) for zb in (1, 2, 4, 8, 16) for g in (0, 1)}, cands
+    assert len(table) == len(cands)
+    assert best["ms_per_step"] == min(r["ms_per_step"] for r in table)
+    assert sim.tuning() == {"z_per_block": best["z_per_block"], "use_graph": best["use_graph"]}
+    sim.step(5)
+    sim.sync()
+    assert torch.isfinite(sim.fields(("rho_a",))["rho_a"]).all()
+    sim.close()
