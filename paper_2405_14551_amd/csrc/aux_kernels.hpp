@@ -17,7 +17,9 @@ struct InitArgs {
   int nx, ny, nz, dims;
   int wall_x, wall_y, wall_z;
   uint32_t N;
-  uint64_t QN;     // elements per colour block
+  uint32_t px;     // row pitch of the population planes (sites, >= nx)
+  uint32_t NF;     // elements per population plane (px * ny * nz)
+  uint64_t QN;     // elements per colour block (Q * NF)
   int ndrop;
   double width, phi_in, rho0;
   double u0x, u0y, u0z;
@@ -54,6 +56,7 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ f, typename Storag
   const int x = s % a.nx;
   const int y = (s / a.nx) % a.ny;
   const int z = s / ((uint32_t)a.nx * a.ny);
+  const uint32_t fs = x + a.px * (y + (uint32_t)a.ny * z);  // the site in the population planes
   const double phi = droplet_phi(x, y, z, drops, a);
   const double rho_k[2] = {a.rho0 * (1.0 + phi) * 0.5, a.rho0 * (1.0 - phi) * 0.5};
   const double uu = a.u0x * a.u0x + a.u0y * a.u0y + a.u0z * a.u0z;
@@ -63,8 +66,8 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ f, typename Storag
     const double cu = L::cx[I] * a.u0x + L::cy[I] * a.u0y + L::cz[I] * a.u0z;
     const double shape = L::w[I] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
     const double hw = L::w[I] * a.half_rho0;  // kernels keep f^k_i - w_i rho0 / 2
-    Storage<S>::template store<I, L>(f + (size_t)I * a.N + s, (R)(rho_k[0] * shape - hw), hs);
-    Storage<S>::template store<I, L>(f + a.QN + (size_t)I * a.N + s, (R)(rho_k[1] * shape - hw), hs);
+    Storage<S>::template store<I, L>(f + (size_t)I * a.NF + fs, (R)(rho_k[0] * shape - hw), hs);
+    Storage<S>::template store<I, L>(f + a.QN + (size_t)I * a.NF + fs, (R)(rho_k[1] * shape - hw), hs);
   });
   phi_out[s] = (R)phi;
   R* rA = (R*)fo.rho_a;
@@ -90,6 +93,7 @@ __global__ void __launch_bounds__(256) k_init_total(S* __restrict__ f, float* __
   const int x = s % a.nx;
   const int y = (s / a.nx) % a.ny;
   const int z = s / ((uint32_t)a.nx * a.ny);
+  const uint32_t fs = x + a.px * (y + (uint32_t)a.ny * z);  // the site in the population planes
   const double phi = droplet_phi(x, y, z, drops, a);
   const double ra = a.rho0 * (1.0 + phi) * 0.5, rb = a.rho0 * (1.0 - phi) * 0.5, rho = ra + rb;
   const double uu = a.u0x * a.u0x + a.u0y * a.u0y + a.u0z * a.u0z;
@@ -97,7 +101,7 @@ __global__ void __launch_bounds__(256) k_init_total(S* __restrict__ f, float* __
     constexpr int I = decltype(ic)::value;
     const double cu = L::cx[I] * a.u0x + L::cy[I] * a.u0y + L::cz[I] * a.u0z;
     const double T = L::w[I] * ((rho - a.rho0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-    total_store(f + (size_t)I * a.N + s, (float)T);
+    total_store(f + (size_t)I * a.NF + fs, (float)T);
   });
   sc[s] = (float)(ra / rho);
   sc[a.N + s] = 0.f;

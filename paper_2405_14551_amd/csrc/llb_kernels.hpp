@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) k_llb_pull(const S* __restrict__ M, S* __
     constexpr int I = decltype(ic)::value;
     constexpr int ix = 1 - L::cx[I], iy = 1 - L::cy[I], iz = 1 - L::cz[I];
     const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
-    const uint32_t src = solid ? n.site : n.xs[ix] + n.ys[iy] + n.zs[iz];
+    const uint32_t src = solid ? n.fsite : n.xs[ix] + n.ys[iy] + n.zs[iz];
     llb_pull_dir<L, I>(M + src, N, solid ? R(-1) : R(1), rho0, acc);
   });
   llb_pull_store(acc, rho0, n.site, N, W, phi);

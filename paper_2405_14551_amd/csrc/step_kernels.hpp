@@ -278,8 +278,13 @@ struct Storage<F16C> {
 struct StepArgs {
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;
-  uint32_t N;        // sites
-  uint64_t QN;       // Q * N (elements per colour block)
+  uint32_t N;        // sites (phase field, scalars, fields, scatter buffers)
+  // population planes: rows of px >= nx sites (read-once two-copy steps with
+  // 4- and 8-byte populations pad each row to a multiple of 128 bytes, so
+  // that every row starts on a cache line; the padding is never read)
+  uint32_t px;
+  uint32_t NF;       // px * ny * nz: elements per population plane
+  uint64_t QN;       // Q * NF (elements per colour block)
   double omega;      // 1/tau
   double guo;        // 1 - 1/(2 tau)
   int visc_mix;      // colours of different viscosity: tau from the mixture at each site
@@ -358,7 +363,8 @@ struct FieldPtrs {
 // is x - c_i; on a walled axis a source outside [0, n) is solid and the
 // population is bounced back from the site itself (halfway bounce-back).
 struct Nbr {
-  uint32_t site;
+  uint32_t site;    // x + nx (y + ny z)
+  uint32_t fsite;   // the same site in the population planes: x + px (y + ny z)
   uint32_t xs[3];   // x - 1, x, x + 1 (wrapped)      indexed by 1 - c
   uint32_t ys[3];   // row offsets
   uint32_t zs[3];   // plane offsets
@@ -368,14 +374,17 @@ struct Nbr {
 __device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const StepArgs& a) {
   Nbr n;
   const uint32_t nx = a.nx, nxy = (uint32_t)a.nx * a.ny;
+  const uint32_t px = a.px, pxy = (uint32_t)a.px * a.ny;
   n.site = x + nx * y + nxy * z;
+  n.fsite = x + px * y + pxy * z;
   int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
   int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
   int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
   // index 0 <-> c = +1 (source x-1), 1 <-> c = 0, 2 <-> c = -1 (source x+1)
   n.xs[0] = xm; n.xs[1] = x; n.xs[2] = xp;
-  n.ys[0] = ym * nx; n.ys[1] = y * nx; n.ys[2] = yp * nx;
-  n.zs[0] = zm * nxy; n.zs[1] = z * nxy; n.zs[2] = zp * nxy;
+  // (row and plane offsets in the population planes)
+  n.ys[0] = ym * px; n.ys[1] = y * px; n.ys[2] = yp * px;
+  n.zs[0] = zm * pxy; n.zs[1] = z * pxy; n.zs[2] = zp * pxy;
   n.solid_x[0] = a.wall_x && x == 0; n.solid_x[1] = false; n.solid_x[2] = a.wall_x && x == a.nx - 1;
   n.solid_y[0] = a.wall_y && y == 0; n.solid_y[1] = false; n.solid_y[2] = a.wall_y && y == a.ny - 1;
   n.solid_z[0] = a.wall_z && z == 0; n.solid_z[1] = false; n.solid_z[2] = a.wall_z && z == a.nz - 1;
@@ -401,7 +410,7 @@ __device__ __forceinline__ uint32_t pull_index(const Nbr& n, uint32_t N) {
   constexpr uint32_t lo = pair_lo<L, I>();
   const uint32_t solid = (uint32_t)n.solid_x[ix] | (uint32_t)n.solid_y[iy] | (uint32_t)n.solid_z[iz];
   const uint32_t moving = (uint32_t)(I - lo) * N + (n.xs[ix] + n.ys[iy] + n.zs[iz]);
-  const uint32_t bounced = (uint32_t)(L::opp[I] - lo) * N + n.site;
+  const uint32_t bounced = (uint32_t)(L::opp[I] - lo) * N + n.fsite;
   return moving ^ ((moving ^ bounced) & (0u - solid));
 }
 
@@ -427,7 +436,7 @@ __device__ __forceinline__ uint32_t pull_index_sel(const Nbr& n, uint32_t N) {
   constexpr uint32_t lo = pair_lo<L, I>();
   const bool solid = n.solid_x[ix] || n.solid_y[iy] || n.solid_z[iz];
   const uint32_t src = n.xs[ix] + n.ys[iy] + n.zs[iz];
-  return solid ? (uint32_t)(L::opp[I] - lo) * N + n.site : (uint32_t)(I - lo) * N + src;
+  return solid ? (uint32_t)(L::opp[I] - lo) * N + n.fsite : (uint32_t)(I - lo) * N + src;
 }
 
 // first plane of the pair of direction i in a block of Q planes at f
@@ -462,7 +471,7 @@ enum { STREAM_AB = 0, STREAM_EVEN = 1, STREAM_ODD = 2 };
 // population i of a STREAM_ODD pass
 template <class L, int I>
 __device__ __forceinline__ uint32_t own_reversed_index(const Nbr& n, uint32_t N) {
-  return (uint32_t)(L::opp[I] - pair_lo<L, I>()) * N + n.site;
+  return (uint32_t)(L::opp[I] - pair_lo<L, I>()) * N + n.fsite;
 }
 
 
@@ -489,10 +498,10 @@ __global__ void __launch_bounds__(256) k_phase(const S* __restrict__ fin,
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     uint32_t e;
-    if constexpr (OWN) e = own_reversed_index<L, I>(n, a.N) * (uint32_t)sizeof(S);
-    else e = pull_index_sel<L, I>(n, a.N) * (uint32_t)sizeof(S);
-    sa += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(fin, a.N), e, h);
-    sb += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.N), e, h);
+    if constexpr (OWN) e = own_reversed_index<L, I>(n, a.NF) * (uint32_t)sizeof(S);
+    else e = pull_index_sel<L, I>(n, a.NF) * (uint32_t)sizeof(S);
+    sa += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(fin, a.NF), e, h);
+    sb += Storage<S>::template bload<I, L>(pair_rsrc<L, I>(finB, a.NF), e, h);
   });
   phi[n.site] = (sa - sb) / (R(2) * h + (sa + sb));
 }
@@ -898,9 +907,9 @@ __device__ __forceinline__ void phase_total_tile(const S* __restrict__ fin, cons
         float Tv[L::Q];
         static_for<I0, I1>([&](auto ic) {
           constexpr int I = decltype(ic)::value;
-          const uint32_t e = OWN ? own_reversed_index<L, I>(n, a.N)
-                                 : (OPEN ? pull_index_open<L, I>(n, a.N) : pull_index<L, I>(n, a.N));
-          Tv[I] = total_bload<S>(pair_rsrc<L, I>(finT, a.N), e * (uint32_t)sizeof(S));
+          const uint32_t e = OWN ? own_reversed_index<L, I>(n, a.NF)
+                                 : (OPEN ? pull_index_open<L, I>(n, a.NF) : pull_index<L, I>(n, a.NF));
+          Tv[I] = total_bload<S>(pair_rsrc<L, I>(finT, a.NF), e * (uint32_t)sizeof(S));
         });
         static_for<I0, I1>([&](auto ic) {
           constexpr int I = decltype(ic)::value;
@@ -952,9 +961,9 @@ __device__ __forceinline__ void phase_tile(const S* __restrict__ fin, typename S
     const S* finB = fin + a.QN;
     static_for<0, L::Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      const uint32_t e = pull_index_sel<L, I>(n, a.N);
-      sa += Storage<S>::template load<I, L>(pair_base<L, I>(fin, a.N) + e, h);
-      sb += Storage<S>::template load<I, L>(pair_base<L, I>(finB, a.N) + e, h);
+      const uint32_t e = pull_index_sel<L, I>(n, a.NF);
+      sa += Storage<S>::template load<I, L>(pair_base<L, I>(fin, a.NF) + e, h);
+      sb += Storage<S>::template load<I, L>(pair_base<L, I>(finB, a.NF) + e, h);
     });
     phi[n.site] = (sa - sb) / (R(2) * h + (sa + sb));
   }
@@ -1299,13 +1308,13 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       static_for<0, L::Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
         uint32_t vo;
-        if constexpr (STREAM == STREAM_ODD) vo = own_reversed_index<L, I>(nn, a.N) * ES;
-        else vo = (decltype(open)::value ? pull_index_open<L, I>(nn, a.N) : pull_index<L, I>(nn, a.N)) * ES;
+        if constexpr (STREAM == STREAM_ODD) vo = own_reversed_index<L, I>(nn, a.NF) * ES;
+        else vo = (decltype(open)::value ? pull_index_open<L, I>(nn, a.NF) : pull_index<L, I>(nn, a.NF)) * ES;
         if constexpr (TOT) {
-          va[I] = (R)total_bload<S, LCP>(pair_rsrc<L, I>(fA, a.N), vo);
+          va[I] = (R)total_bload<S, LCP>(pair_rsrc<L, I>(fA, a.NF), vo);
         } else {
-          va[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(fA, a.N), vo, hshift);
-          vb[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(fB, a.N), vo, hshift);
+          va[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(fA, a.NF), vo, hshift);
+          vb[I] = Storage<S>::template bload<I, L, LCP>(pair_rsrc<L, I>(fB, a.NF), vo, hshift);
         }
       });
     };
@@ -1353,14 +1362,14 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       }
       auto own = [&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        const uint32_t vo = own_reversed_index<L, L::opp[I]>(n, a.N) * (uint32_t)sizeof(S);
+        const uint32_t vo = own_reversed_index<L, L::opp[I]>(n, a.NF) * (uint32_t)sizeof(S);
         if constexpr (TOT) {
-          const float tv = total_bload<S>(pair_rsrc<L, I>(finA, a.N), vo);
+          const float tv = total_bload<S>(pair_rsrc<L, I>(finA, a.NF), vo);
           const R cA = colour_of_total<L, I>(tv, sc_a, sc_bx, sc_by, sc_bz, rho0, hshift);
           route(ic, cA, (R)tv - cA, n, open, live, ragged);
         } else {
-          route(ic, Storage<S>::template bload_stored<I, L>(pair_rsrc<L, I>(finA, a.N), vo),
-                Storage<S>::template bload_stored<I, L>(pair_rsrc<L, I>(finB, a.N), vo), n, open, live, ragged);
+          route(ic, Storage<S>::template bload_stored<I, L>(pair_rsrc<L, I>(finA, a.NF), vo),
+                Storage<S>::template bload_stored<I, L>(pair_rsrc<L, I>(finB, a.NF), vo), n, open, live, ragged);
         }
       };
       own(std::integral_constant<int, 0>{});
@@ -1455,6 +1464,13 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       // clamped site) and only lanes inside the lattice store.
       const bool live = valid_xy;
       [[maybe_unused]] const bool ragged = RO && __ballot(!live) != 0;
+      // RO with two copies: lanes in the padding of a population row
+      // (nx <= x < px) also store their clamped site's values, into their own
+      // pad slots, so that the row's last cache line is written whole; the
+      // padding is never read
+      [[maybe_unused]] const bool padl =
+          RO && STREAM == STREAM_AB && x >= a.nx && x < (int)a.px && y < a.ny;
+      [[maybe_unused]] const uint32_t pad_shift = padl ? (uint32_t)(x - (a.nx - 1)) : 0u;
       if (!MLP || RO || valid_xy) {
         // ---- moments of the pulled populations
         R d[L::Q];  // d_i = f_i - w_i rho0, total over both colours
@@ -1536,21 +1552,21 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           // offset in the scalar offset operand, or pushed (in place, even kind)
           uint32_t vo, so;
           if constexpr (STREAM == STREAM_EVEN) {
-            vo = pull_index<L, L::opp[I]>(n, a.N) * ES;
+            vo = pull_index<L, L::opp[I]>(n, a.NF) * ES;
             so = 0;
           } else {
-            vo = n.site * ES;
-            so = (uint32_t)(I - pair_lo<L, I>()) * a.N * ES;
+            vo = (n.fsite + pad_shift) * ES;
+            so = (uint32_t)(I - pair_lo<L, I>()) * a.NF * ES;
           }
           if constexpr (TOT) {
-            const auto rs = pair_rsrc<L, I>((const S*)foutA, a.N);
+            const auto rs = pair_rsrc<L, I>((const S*)foutA, a.NF);
             [[maybe_unused]] float tv;  // the stored total as a load returns it
             if constexpr (SR) {
               const unsigned short bits = sround_bits<S>((float)ds, sround_word(sr_base, I, (float)ds));
-              if (!RO || live) __builtin_amdgcn_raw_buffer_store_b16(bits, rs, vo, so, SCP);
+              if (!RO || live || padl) __builtin_amdgcn_raw_buffer_store_b16(bits, rs, vo, so, SCP);
               if constexpr (RO) tv = (float)__builtin_bit_cast(S, bits);
             } else {
-              if (!RO || live) total_bstore<S, SCP>(rs, vo, so, (float)ds);
+              if (!RO || live || padl) total_bstore<S, SCP>(rs, vo, so, (float)ds);
               if constexpr (RO) tv = total_rt<S>((float)ds);
             }
             if constexpr (RO) {
@@ -1563,9 +1579,9 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
             const R wi = (R)L::w[I];
             const R da = fa_frac * ds + wi * (half_phi_rho0 + rec_odd);
             const R db = ds - da;
-            if (!RO || live) {
-              Storage<S>::template bstore<I, L, SCP>(pair_rsrc<L, I>((const S*)foutA, a.N), vo, so, da, hshift);
-              Storage<S>::template bstore<I, L, SCP>(pair_rsrc<L, I>((const S*)foutB, a.N), vo, so, db, hshift);
+            if (!RO || live || padl) {
+              Storage<S>::template bstore<I, L, SCP>(pair_rsrc<L, I>((const S*)foutA, a.NF), vo, so, da, hshift);
+              Storage<S>::template bstore<I, L, SCP>(pair_rsrc<L, I>((const S*)foutB, a.NF), vo, so, db, hshift);
             }
             if constexpr (RO)
               route(ic, Storage<S>::template stored<I, L>(da, hshift), Storage<S>::template stored<I, L>(db, hshift),
@@ -1899,7 +1915,7 @@ __global__ void __launch_bounds__(256) k_canonical(const E* __restrict__ f, E* _
   const Nbr n = make_nbr(x, y, z, a);
   static_for<0, L::Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    if (I >= i0 && I < i1) out[(size_t)(I - i0) * a.N + s] = pair_base<L, I>(f, a.N)[pull_index<L, L::opp[I]>(n, a.N)];
+    if (I >= i0 && I < i1) out[(size_t)(I - i0) * a.N + s] = pair_base<L, I>(f, a.NF)[pull_index<L, L::opp[I]>(n, a.NF)];
   });
 }
 
