@@ -1446,7 +1446,7 @@ int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int c
     // step count varies per call), so only the batched mode has graph
     // candidates
     for (int mode : {LB_ENSEMBLE_BATCHED, LB_ENSEMBLE_PER_CHANNEL})
-      for (int zb : {1, 2, 4, 8, 16})
+      for (int zb : {1, 2, 4, 8, 16, 32})
         for (int graph : {0, 1}) {
           if (mode == LB_ENSEMBLE_PER_CHANNEL && graph) continue;
           lb_tuning t{};
@@ -1456,7 +1456,7 @@ int lb_autotune(lb_handle* h, int steps, lb_tuning* best, double* results, int c
           cand.push_back(t);
         }
   } else {
-    for (int zb : {1, 2, 4, 8, 16})
+    for (int zb : {1, 2, 4, 8, 16, 32})
       for (int graph : {0, 1})
         if (zb <= h->p.nz) {
           lb_tuning t{};

@@ -262,7 +262,7 @@ class Simulation:
         return {"z_per_block": t.z_per_block, "use_graph": t.use_graph}
 
     def autotune(self, steps=4):
-        """Time z-planes per march {1, 2, 4, 8, 16} (up to nz) with and without
+        """Time z-planes per march {1, 2, 4, 8, 16, 32} (up to nz) with and without
         graph replays (the timed steps advance the simulation), keep the
         fastest and return (best, table) (lb_autotune)."""
         best = LbTuning()
