@@ -166,16 +166,19 @@ def test_other_storages_match_the_two_pass_step(storage, streaming):
     assert d < PHI_BAR[storage], f"phase field after three steps differs by {d:.2e}"
 
 
+@pytest.mark.parametrize("shape", [(64, 16, 16), (70, 13, 12)])
 @pytest.mark.parametrize("storage", ["f32", "f16t", "f64"])
-def test_restore_repeats_the_uninterrupted_run_bit_for_bit(storage):
+def test_restore_repeats_the_uninterrupted_run_bit_for_bit(storage, shape):
     """lb_set_state drops the scattered phase field; the bootstrap pass
     scatters the restored state exactly as the collision pass that stored it
     did, so the restored run repeats the uninterrupted one bit for bit (also
-    after a second restore on the same handle)."""
-    kw = dict(lattice="D3Q27", storage=storage, nc="explicit", shape=(64, 16, 16), walls=(0, 1, 1),
+    after a second restore on the same handle).  70 sites per row: the FP32
+    and FP64 population rows are padded on the device, and the state moves
+    through pitched copies."""
+    kw = dict(lattice="D3Q27", storage=storage, nc="explicit", shape=shape, walls=(0, 1, 1),
               body_force=(1e-5, 0, 0))
     cen, rad = droplets(kw["shape"], "D3Q27")
-    say(f"case restore {storage}")
+    say(f"case restore {storage} {shape}")
     a = lb.Simulation(**kw).init_droplets(cen, rad)
     a.step(5)
     saved = a.get_state().clone()
@@ -190,6 +193,30 @@ def test_restore_repeats_the_uninterrupted_run_bit_for_bit(storage):
     a.close()
     b.close()
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f32t"])
+def test_padded_population_rows_hold_the_canonical_state(storage):
+    """The read-once two-copy step keeps FP32 / FP64 population rows padded to
+    128 bytes on the device (70 sites per row here).  Its state after
+    initialisation equals the unpadded two-pass handle's bit for bit, and any
+    state set on it reads back unchanged."""
+    kw = dict(lattice="D3Q27", storage=storage, nc="explicit", shape=(70, 13, 12), walls=(0, 1, 1),
+              body_force=(1e-5, 0, 0))
+    cen, rad = droplets(kw["shape"], "D3Q27")
+    say(f"case padded rows {storage}")
+    a = lb.Simulation(**dict(kw, phase="scatter")).init_droplets(cen, rad)
+    b = lb.Simulation(**dict(kw, phase="pass")).init_droplets(cen, rad)
+    sa, sb = a.get_state(), b.get_state()
+    assert sa.shape == sb.shape
+    assert torch.equal(sa.contiguous().view(torch.uint8), sb.contiguous().view(torch.uint8))
+    g = torch.Generator(device="cpu").manual_seed(3)
+    raw = torch.randint(0, 256, (sa.numel() * sa.element_size(),), generator=g, dtype=torch.uint8)
+    a.set_state(raw.to(sa.device).view(sa.dtype).reshape(sa.shape))
+    back = a.get_state().contiguous().view(torch.uint8).reshape(-1).cpu()
+    assert torch.equal(back, raw)
+    a.close()
+    b.close()
 
 
 def test_learned_closure_read_once_matches_two_pass():
