@@ -100,6 +100,9 @@ struct lb_handle {
   // populations to a multiple of 128 bytes; the padding is never read)
   uint32_t px = 0;
   size_t NF = 0;
+  // stride of the per-site planes of the total layout's scalars and of the
+  // read-once partial sums P (N rounded up to 64 sites, plus 64)
+  size_t NS = 0;
   size_t rsize = 0;  // bytes per field value (8 for FP64, else 4)
   hipStream_t stream = nullptr;
   int device = 0;
@@ -126,7 +129,7 @@ struct lb_handle {
   void* phi_at(int k) const { return k ? phi2 : phi; }
   void* phi_field() const { return phi_at(pfield); }
   // read-once step (lb_params.phase_pass, lb_phase_mode): the collision
-  // pass scatters the next step's colour densities into ro_part (2 x N) and
+  // pass scatters the next step's colour densities into ro_part (2 x NS) and
   // ro_halo (per tile-march halo blocks, marches of ro_zb planes); phi_ready
   // says that phi_at(pcur) already holds the phase field of the next pull
   bool ro = false;
@@ -196,6 +199,7 @@ struct lb_handle {
     a.N = N;
     a.px = px;
     a.NF = (uint32_t)NF;
+    a.NS = (uint32_t)NS;
     a.QN = (uint64_t)q * NF;
     a.omega = 1.0 / p.tau;
     a.guo = 1.0 - 0.5 / p.tau;
@@ -495,13 +499,17 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
   {
     const size_t g = 256 / h->esize;
     size_t nf = (size_t)h->px * p->ny * p->nz;
+    const char* env = std::getenv("LB_PLANE_PAD");  // measurement override: "0" keeps plain planes
     if (!h->moments()) {
-      const char* env = std::getenv("LB_PLANE_PAD");  // measurement override: "0" keeps plain planes
       const size_t padded = (nf + g - 1) / g * g + g;
       const double span = p->lattice == LB_D2Q9 ? 3.0 : 2.0;
       if (!(env && !std::strcmp(env, "0")) && (double)padded * span * h->esize <= 4294967295.0) nf = padded;
     }
     h->NF = nf;
+    // the same for the planes of N sites that the passes read and write
+    // together (the four scalars, P of both colours)
+    const size_t ns = (N + 63) / 64 * 64 + 64;
+    h->NS = (h->moments() || (env && !std::strcmp(env, "0"))) ? N : ns;
   }
   const size_t pop =
       h->moments() ? (size_t)LLB_NM * N * h->esize : (h->total ? 1ull : 2ull) * h->q * h->NF * h->esize;
@@ -517,13 +525,13 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
   if (!h->in_place()) ALLOC(h->f[1], pop);
   if (h->moments()) ALLOC(h->W, (size_t)LLB_NW * N * h->esize);
   if (h->total) {
-    ALLOC(h->sc[0], sizeof(float) * NSC * N);
-    if (!h->in_place()) ALLOC(h->sc[1], sizeof(float) * NSC * N);
+    ALLOC(h->sc[0], sizeof(float) * NSC * h->NS);
+    if (!h->in_place()) ALLOC(h->sc[1], sizeof(float) * NSC * h->NS);
   }
   ALLOC(h->phi, N * h->rsize);
   if (h->ro) {
     ALLOC(h->phi2, N * h->rsize);
-    ALLOC(h->ro_part, 2 * N * h->rsize);
+    ALLOC(h->ro_part, 2 * h->NS * h->rsize);
     // the read-once collision with FP32 arithmetic measured fastest with
     // about 2048 workgroups, half the march depth of the rule above (256 x
     // 128 x 128 channel: per-colour FP32 step 0.4616 -> 0.4478 ms, FP32 total
@@ -627,7 +635,7 @@ int lb_init_droplets(lb_handle* h, int channel, int n, const double* centres, co
   InitArgs a{};
   a.nx = h->p.nx; a.ny = h->p.ny; a.nz = h->p.nz; a.dims = h->d;
   a.wall_x = h->p.wall[0]; a.wall_y = h->p.wall[1]; a.wall_z = h->p.wall[2];
-  a.N = h->N; a.px = h->px; a.NF = (uint32_t)h->NF; a.QN = (uint64_t)h->q * h->NF;
+  a.N = h->N; a.px = h->px; a.NF = (uint32_t)h->NF; a.NS = (uint32_t)h->NS; a.QN = (uint64_t)h->q * h->NF;
   a.ndrop = n;
   a.width = width; a.phi_in = phi_in; a.rho0 = h->p.rho0;
   a.u0x = h->p.u0[0]; a.u0y = h->p.u0[1]; a.u0z = h->d == 3 ? h->p.u0[2] : 0.0;
@@ -1328,7 +1336,9 @@ int lb_get_state(lb_handle* h, void* dst, size_t bytes, int dst_on_device) {
       HIP_TRY(hipMemcpy2DAsync((char*)dst + i * plane, row, (const char*)h->f[h->cur] + i * h->NF * h->esize,
                                (size_t)h->px * h->esize, row, plane / row, k, h->stream));
   }
-  if (h->total) HIP_TRY(hipMemcpyAsync((char*)dst + pop, h->sc[h->cur], need - pop, k, h->stream));
+  if (h->total)
+    HIP_TRY(hipMemcpy2DAsync((char*)dst + pop, sizeof(float) * h->N, h->sc[h->cur], sizeof(float) * h->NS,
+                             sizeof(float) * h->N, NSC, k, h->stream));
   if (!dst_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
   return LB_OK;
 }
@@ -1359,7 +1369,9 @@ int lb_set_state(lb_handle* h, const void* src, size_t bytes, int src_on_device)
       HIP_TRY(hipMemcpy2DAsync((char*)h->f[h->cur] + i * h->NF * h->esize, (size_t)h->px * h->esize,
                                (const char*)src + i * plane, row, row, plane / row, k, h->stream));
   }
-  if (h->total) HIP_TRY(hipMemcpyAsync(h->sc[h->cur], (const char*)src + pop, need - pop, k, h->stream));
+  if (h->total)
+    HIP_TRY(hipMemcpy2DAsync(h->sc[h->cur], sizeof(float) * h->NS, (const char*)src + pop, sizeof(float) * h->N,
+                             sizeof(float) * h->N, NSC, k, h->stream));
   if (!src_on_device) HIP_TRY(hipStreamSynchronize(h->stream));
   h->ip_odd = 0;  // the state given is canonical
   h->initialised = true;

@@ -18,7 +18,8 @@ struct InitArgs {
   int wall_x, wall_y, wall_z;
   uint32_t N;
   uint32_t px;     // row pitch of the population planes (sites, >= nx)
-  uint32_t NF;     // elements per population plane (px * ny * nz)
+  uint32_t NF;     // elements per population plane (>= px * ny * nz)
+  uint32_t NS;     // stride of the scalar planes (>= N)
   uint64_t QN;     // elements per colour block (Q * NF)
   int ndrop;
   double width, phi_in, rho0;
@@ -104,9 +105,9 @@ __global__ void __launch_bounds__(256) k_init_total(S* __restrict__ f, float* __
     total_store(f + (size_t)I * a.NF + fs, (float)T);
   });
   sc[s] = (float)(ra / rho);
-  sc[a.N + s] = 0.f;
-  sc[2 * (size_t)a.N + s] = 0.f;
-  sc[3 * (size_t)a.N + s] = 0.f;
+  sc[a.NS + s] = 0.f;
+  sc[2 * (size_t)a.NS + s] = 0.f;
+  sc[3 * (size_t)a.NS + s] = 0.f;
   phi_out[s] = (float)phi;
   float* rA = (float*)fo.rho_a;
   float* rB = (float*)fo.rho_b;

@@ -283,7 +283,8 @@ struct StepArgs {
   // 4- and 8-byte populations pad each row to a multiple of 128 bytes, so
   // that every row starts on a cache line; the padding is never read)
   uint32_t px;
-  uint32_t NF;       // px * ny * nz: elements per population plane
+  uint32_t NF;       // elements per population plane (>= px * ny * nz)
+  uint32_t NS;       // stride of the per-site planes of the scalars and of P (>= N)
   uint64_t QN;       // Q * NF (elements per colour block)
   double omega;      // 1/tau
   double guo;        // 1 - 1/(2 tau)
@@ -799,7 +800,7 @@ __device__ __forceinline__ void fetch_scalars(float (&v)[ScalarRing<TS>::NPER], 
 #pragma unroll
     for (int ch = 0; ch < NSC; ++ch)
       v[ch * ScalarRing<TS>::NPC + k] = __builtin_bit_cast(
-          float, __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(sc + (size_t)ch * a.N, a.N * 4u), off, 0, 0));
+          float, __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(sc + (size_t)ch * a.NS, a.N * 4u), off, 0, 0));
   }
 }
 
@@ -1356,9 +1357,9 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
       [[maybe_unused]] float sc_a = 0.f, sc_bx = 0.f, sc_by = 0.f, sc_bz = 0.f;
       if constexpr (TOT) {
         sc_a = scout[n.site];
-        sc_bx = scout[a.N + n.site];
-        sc_by = scout[2 * (size_t)a.N + n.site];
-        sc_bz = scout[3 * (size_t)a.N + n.site];
+        sc_bx = scout[a.NS + n.site];
+        sc_by = scout[2 * (size_t)a.NS + n.site];
+        sc_bz = scout[3 * (size_t)a.NS + n.site];
       }
       auto own = [&](auto ic) {
         constexpr int I = decltype(ic)::value;
@@ -1623,9 +1624,9 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
         if (TOT && (!RO || live)) {
           // recolouring scalars of this site for the next pull
           __builtin_nontemporal_store((float)fa_frac, scout + n.site);
-          __builtin_nontemporal_store((float)(bs * gx), scout + a.N + n.site);
-          __builtin_nontemporal_store((float)(bs * gy), scout + 2 * (size_t)a.N + n.site);
-          __builtin_nontemporal_store((float)(bs * gz), scout + 3 * (size_t)a.N + n.site);
+          __builtin_nontemporal_store((float)(bs * gx), scout + a.NS + n.site);
+          __builtin_nontemporal_store((float)(bs * gy), scout + 2 * (size_t)a.NS + n.site);
+          __builtin_nontemporal_store((float)(bs * gz), scout + 3 * (size_t)a.NS + n.site);
         }
         if (FIELDS && (!RO || live)) {
           R* rA = (R*)fo.rho_a;
@@ -1704,7 +1705,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
           if (valid_xy) {
             const uint32_t s = (uint32_t)x + (uint32_t)a.nx * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)(z - 1));
             __builtin_nontemporal_store(accA[0], part + s);
-            __builtin_nontemporal_store(accB[0], part + a.N + s);
+            __builtin_nontemporal_store(accB[0], part + a.NS + s);
           }
           ring_emit(z - 1, false, false);
         }
@@ -1722,7 +1723,7 @@ __device__ __forceinline__ void collide_tile(const S* __restrict__ fin, S* __res
     if (valid_xy) {
       const uint32_t s = (uint32_t)x + (uint32_t)a.nx * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)zl);
       __builtin_nontemporal_store(accA[cur], part + s);
-      __builtin_nontemporal_store(accB[cur], part + a.N + s);
+      __builtin_nontemporal_store(accB[cur], part + a.NS + s);
     }
     ring_emit(zl, false, false);
     if constexpr (L::D == 3) {
@@ -1838,7 +1839,7 @@ __device__ __forceinline__ void combine_block(const R* __restrict__ part, const 
   for (int k = 0; k < CP; ++k) {
     const uint32_t s = s0 + nxy * (uint32_t)min(k, np - 1);
     sa[k] = part[s];
-    sb[k] = part[a.N + s];
+    sb[k] = part[a.NS + s];
   }
   // stage the block's slots of these planes
   const uint64_t base = (uint64_t)g.tile_index(tx, ty, tm) * g.stride();
