@@ -1148,9 +1148,17 @@ int lb_step(lb_handle* h, int nsteps) {
     const bool diag_now = h->p.diag_every > 0 && ((h->t + 1) % h->p.diag_every) == 0;
     const bool fields = (s == nsteps - 1) || diag_now;
     if (graph_ok && !fields && s + 2 <= nsteps - 1 && !h->prof_on && (!h->ro || h->phi_ready)) {
+      // a graph of neither this parity nor the next (after a restart that
+      // left the buffers paired differently) is captured again
+      const int key = single_graph_key(h);
+      const int flip = ((h->in_place() && !h->moments()) ? 4 : 1) | (h->ro ? 2 : 0);
+      if (h->graph && h->graph_key != key && h->graph_key != (key ^ flip)) {
+        int r = single_graph_drop(h);
+        if (r) return r;
+      }
       int r = single_graph(h);
       if (r) return r;
-      if (h->graph_key == single_graph_key(h)) {
+      if (h->graph_key == key) {
         HIP_TRY(hipGraphLaunch(h->graph, h->stream));
         single_advance(h, false);
         single_advance(h, false);
