@@ -289,10 +289,11 @@ def closure_speed(kw, cen, rad, theta, ranges, steps, warmup):
     return out
 
 
-def ensemble(steps, warmup):
+def ensemble(steps, warmup, tune=None):
     """96 independent D3Q19 channels (sizes 64..160 x 64..96 x 64..96, tau
     0.6..1.2, 4..40 droplets each; FP32, near contact): autotuned launch
-    configuration and aggregate MLUPS."""
+    configuration (or the given (mode, z_per_block, use_graph)) and
+    aggregate MLUPS."""
     import torch
     from paper_2405_14551_amd import lb, workloads as W
     w = W.ensemble_channels()
@@ -302,9 +303,13 @@ def ensemble(steps, warmup):
     ens = lb.Ensemble(plain, lattice=w["lattice"], storage=w["storage"], nc=w["nc"])
     for k, c in enumerate(chans):
         ens.init_droplets(k, c["centres"], c["radii"])
-    best, table = ens.autotune(steps=4)
-    for k, c in enumerate(chans):
-        ens.init_droplets(k, c["centres"], c["radii"])
+    if tune is None:
+        best, table = ens.autotune(steps=4)
+        for k, c in enumerate(chans):
+            ens.init_droplets(k, c["centres"], c["radii"])
+    else:
+        ens.set_tuning(*tune)
+        best, table = ens.tuning(), []
     ens.step(warmup)
     ens.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -415,6 +420,9 @@ def main():
                     help="storage of the channel workload (profiling runs; the headline is f32)")
     ap.add_argument("--phase", default="auto", choices=("auto", "scatter", "pass"),
                     help="read-once or two-pass step for the channel workload (profiling runs)")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the ensemble workload, batched with 16 planes per march and no autotuning "
+                         "(for profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
@@ -430,6 +438,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": ensemble(args.steps, args.warmup, tune=("batched", 16, 0))}), flush=True)
+        return 0
 
     kw, cen, rad, n, ms, per, diag = headline(args)
     q = 27
