@@ -251,10 +251,9 @@ void lb_params_default(lb_params* p);
  * layout, and nc_mode LB_NC_MLP is single-lattice only.  hip_stream is a
  * hipStream_t (NULL allowed).  Allocates two copies of the state (see
  * lb_state_bytes), or one with LB_STREAM_IN_PLACE, plus the fields, per
- * channel.  The read-once two-copy step with 4- and 8-byte populations keeps
- * each population row padded to a multiple of 128 bytes on the device (up to
- * 31 FP32 / 15 FP64 extra sites per row); lb_get_state and lb_set_state move
- * the unpadded state.
+ * channel.  The population rows are kept padded to a multiple of 128 bytes on
+ * the device (up to 63 16-bit, 31 FP32 or 15 FP64 extra sites per row; not in
+ * the moment scheme); lb_get_state and lb_set_state move the unpadded state.
  * Size limits per lattice: sites < 2^31, and the planes of one velocity pair
  * below 4 GiB (2 x sites x element bytes in 3D, 3 x in D2Q9): 536M sites in
  * FP32, 268M in FP64, 1.07G in the 16-bit layouts.  Near contact needs every

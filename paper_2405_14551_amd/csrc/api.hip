@@ -476,19 +476,23 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
   // Row pitch of the population planes.  Rows whose length is not a multiple
   // of 128 bytes start inside a cache line, so a wave's loads and stores
   // touch an extra line and the line at a row end is written in two parts
-  // by neighbouring tiles (measured on ensembles of 96 D3Q19 channels, FP32:
+  // by neighbouring tiles.  Measured: ensembles of 96 D3Q19 channels (FP32),
   // 100 x 80 x 80 channels at 2.4 TB/s against 4.0-5.0 TB/s for 96-, 112-,
-  // 128- and 160-wide ones).  The read-once two-copy step with 4- and 8-byte
-  // populations pads each row to the next multiple of 128 bytes; the pad
-  // sites are never read (pulls wrap at nx) nor written.
+  // 128- and 160-wide ones; a 250 x 128 x 128 channel at 5829 (FP32
+  // read-once), 5014 (FP32 two-pass) and 12502 MLUPS (FP16 total) with
+  // unpadded rows, 9633, 7455 and 17889 with padded ones.  Every population
+  // layout but the moment scheme pads each row to the next multiple of 128
+  // bytes.  The pad sites are never read (pulls wrap at nx); in the
+  // read-once two-copy step the lanes in the padding store into it, so that
+  // a row's last line is written whole.
   h->px = (uint32_t)p->nx;
-  if (h->ro && !h->in_place() && h->esize >= 4) {
-    const char* env = std::getenv("LB_ROW_PAD");  // measurement override: "0" keeps px = nx
+  const char* row_env = std::getenv("LB_ROW_PAD");  // measurement override: "0" keeps px = nx
+  if (!(row_env && !std::strcmp(row_env, "0")) && !h->moments()) {
     const uint32_t m = (uint32_t)(128 / h->esize);
     const uint32_t px = ((uint32_t)p->nx + m - 1) / m * m;
     const double span = p->lattice == LB_D2Q9 ? 3.0 : 2.0;
     const double nf = (double)px * p->ny * p->nz;
-    if (!(env && !std::strcmp(env, "0")) && nf * span * h->esize <= 4294967295.0) h->px = px;
+    if (nf * span * h->esize <= 4294967295.0) h->px = px;
   }
   // Plane stride: 256 bytes more than the plane (rounded to 256 bytes), so
   // that the 2Q planes a site's loads and stores touch do not all start at
