@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_llb_pull(const S* __restrict__ M, S* __
   const int y = ty_ * blockDim.y + threadIdx.y;
   if (x >= a.nx || y >= a.ny) return;
   const Nbr n = make_nbr(x, y, z, a);
-  const size_t N = a.N;
+  const size_t N = a.NF;  // moment plane stride
   const R rho0 = R(2) * (R)a.half_rho0;
   LlbPullSums<R> acc;
   static_for<0, L::Q>([&](auto ic) {
@@ -206,7 +206,7 @@ __device__ __forceinline__ void llb_fetch_plane(float (&v)[LLB_NM * ((TS::PL + T
     const uint32_t gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
     const float* m = M + (zoff + gy * (uint32_t)a.nx + gx);
 #pragma unroll
-    for (int ch = 0; ch < LLB_NM; ++ch) v[ch * NPC + k] = m[(size_t)ch * a.N];
+    for (int ch = 0; ch < LLB_NM; ++ch) v[ch * NPC + k] = m[(size_t)ch * a.NF];
     // channel 0 as the FOLD form of llb_pull_dir reads it
     v[k] = v[k] - 1.5f * (v[4 * NPC + k] + v[5 * NPC + k] + v[6 * NPC + k]) - (2.0f / 3.0f) * v[10 * NPC + k];
   }
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(TS::NT) k_llb_pull_ring(const float* __restric
         if constexpr (cz != 0) m.g3 = r[3 * TS::PL];
         llb_pull_dir_v<L, I, true>(m, solid ? -1.0f : 1.0f, rho0, acc);
       });
-      llb_pull_store(acc, rho0, n.site, a.N, W, phi);
+      llb_pull_store(acc, rho0, n.site, a.NF, W, phi);
     }
     __syncthreads();  // the oldest plane is no longer read
     if (more) llb_commit_plane<TS>(sm.rec, plane_slot(z + 1 + TS::RZ, NS), nxt, tid);
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(T::NT) k_llb_collide(const S* __restrict__ W, 
   for (int dz = -T::RZ; dz <= T::RZ; ++dz)
     load_plane<T>(ring, plane_slot(z0 + dz, T::NPL), z0 + dz, phi, x0, y0, a, tid);
   __syncthreads();
-  const size_t N = a.N;
+  const size_t N = a.N, NF = a.NF;  // field planes, moment planes
   const R hshift = (R)a.half_rho0, rho0 = R(2) * hshift, phiI = (R)a.phi_I;
   const R Aamp = (R)a.A, beta = (R)a.beta;
   const int c0 = (ty + T::RAD) * T::TXH + (tx + T::RAD);
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(T::NT) k_llb_collide(const S* __restrict__ W, 
       const uint32_t s = (uint32_t)x + (uint32_t)a.nx * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)z);
       R wv[LLB_NW];
 #pragma unroll
-      for (int k = 0; k < LLB_NW; ++k) wv[k] = W[k * N + s];
+      for (int k = 0; k < LLB_NW; ++k) wv[k] = W[k * NF + s];
       const int p0 = zc * T::PL;
       constexpr int dz1 = T::RZ ? 1 : 0;
       const int pm = ring_slot(zc, -dz1, T::NPL) * T::PL;
@@ -355,9 +355,9 @@ __global__ void __launch_bounds__(T::NT) k_llb_collide(const S* __restrict__ W, 
       // new moments
       S* out = M + s;
       out[0] = drho;
-      out[1 * N] = rho * ux + om1 * (jx - rho * ux) + guo * Fx;
-      out[2 * N] = rho * uy + om1 * (jy - rho * uy) + guo * Fy;
-      out[3 * N] = rho * uz + om1 * (jz - rho * uz) + guo * Fz;
+      out[1 * NF] = rho * ux + om1 * (jx - rho * ux) + guo * Fx;
+      out[2 * NF] = rho * uy + om1 * (jy - rho * uy) + guo * Fy;
+      out[3 * NF] = rho * uz + om1 * (jz - rho * uz) + guo * Fz;
       const R gn = has_g ? sqrt(gg) : R(0);
       const R inv_gn = has_g ? R(1) / gn : R(0);
       const R kg = R(2.0 / 9.0) * Aamp * inv_gn;      // (2A/9) / |g|
@@ -370,14 +370,14 @@ __global__ void __launch_bounds__(T::NT) k_llb_collide(const S* __restrict__ W, 
         const int p = PA_[k], q = PB_[k];
         const R ruu = rho * uvec[p] * uvec[q];
         const R pin = wv[5 + k] - ((p == q && p < L::D) ? iso : R(0)) - ruu;
-        out[(4 + k) * N] = ruu + om1 * pin + guo * (uvec[p] * Fvec[q] + Fvec[p] * uvec[q]) + kg * gvec[p] * gvec[q];
+        out[(4 + k) * NF] = ruu + om1 * pin + guo * (uvec[p] * Fvec[q] + Fvec[p] * uvec[q]) + kg * gvec[p] * gvec[q];
       }
-      out[10 * N] = Aamp * gn;
-      out[11 * N] = ra * inv_rho;
+      out[10 * NF] = Aamp * gn;
+      out[11 * NF] = ra * inv_rho;
       const R bc = beta * ra * rb * inv_rho * inv_gn;
-      out[12 * N] = bc * gx;
-      out[13 * N] = bc * gy;
-      out[14 * N] = bc * gz;
+      out[12 * NF] = bc * gx;
+      out[13 * NF] = bc * gy;
+      out[14 * NF] = bc * gz;
       if (FIELDS) {
         R* rA = (R*)fo.rho_a;
         R* rB = (R*)fo.rho_b;
@@ -409,14 +409,14 @@ __global__ void __launch_bounds__(256) k_llb_init(S* __restrict__ M, S* __restri
   const double phi = droplet_phi(x, y, z, drops, a);
   const double ra = a.rho0 * (1.0 + phi) * 0.5, rb = a.rho0 * (1.0 - phi) * 0.5, rho = ra + rb;
   const double u[3] = {a.u0x, a.u0y, a.u0z};
-  const size_t N = a.N;
+  const size_t N = a.N, NF = a.NF;  // field planes, moment planes
   M[s] = (S)(rho - a.rho0);
-  for (int k = 0; k < 3; ++k) M[(1 + k) * N + s] = (S)(rho * u[k]);
+  for (int k = 0; k < 3; ++k) M[(1 + k) * NF + s] = (S)(rho * u[k]);
   constexpr int PA_[6] = {0, 1, 2, 0, 0, 1}, PB_[6] = {0, 1, 2, 1, 2, 2};
-  for (int k = 0; k < 6; ++k) M[(4 + k) * N + s] = (S)(rho * u[PA_[k]] * u[PB_[k]]);
-  M[10 * N + s] = 0;
-  M[11 * N + s] = (S)(ra / rho);
-  for (int k = 0; k < 3; ++k) M[(12 + k) * N + s] = 0;
+  for (int k = 0; k < 6; ++k) M[(4 + k) * NF + s] = (S)(rho * u[PA_[k]] * u[PB_[k]]);
+  M[10 * NF + s] = 0;
+  M[11 * NF + s] = (S)(ra / rho);
+  for (int k = 0; k < 3; ++k) M[(12 + k) * NF + s] = 0;
   phi_out[s] = (S)phi;
   S* rA = (S*)fo.rho_a;
   S* rB = (S*)fo.rho_b;
