@@ -503,19 +503,17 @@ static int create_single(const lb_params* p, void* hip_stream, lb_handle** out, 
   // pre-collision moment planes take the same stride (its collision pass
   // 115 -> 103 us, the step 13326 -> 13876 MLUPS).
   {
-    const size_t g = 256 / h->esize;
-    size_t nf = (size_t)h->px * p->ny * p->nz;
     const char* env = std::getenv("LB_PLANE_PAD");  // measurement override: "0" keeps plain planes
-    {
-      const size_t padded = (nf + g - 1) / g * g + g;
-      const double span = p->lattice == LB_D2Q9 ? 3.0 : 2.0;
-      if (!(env && !std::strcmp(env, "0")) && (double)padded * span * h->esize <= 4294967295.0) nf = padded;
-    }
-    h->NF = nf;
+    const bool plain = env && !std::strcmp(env, "0");
+    const size_t g = 256 / h->esize;
+    const size_t nf = (size_t)h->px * p->ny * p->nz;
+    const size_t padded = (nf + g - 1) / g * g + g;
+    const double span = p->lattice == LB_D2Q9 ? 3.0 : 2.0;
+    h->NF = (!plain && (double)padded * span * h->esize <= 4294967295.0) ? padded : nf;
     // the same for the planes of N sites that the passes read and write
     // together (the four scalars, P of both colours)
     const size_t ns = (N + 63) / 64 * 64 + 64;
-    h->NS = (h->moments() || (env && !std::strcmp(env, "0"))) ? N : ns;
+    h->NS = (h->moments() || plain) ? N : ns;
   }
   const size_t pop =
       h->moments() ? (size_t)LLB_NM * h->NF * h->esize : (h->total ? 1ull : 2ull) * h->q * h->NF * h->esize;
