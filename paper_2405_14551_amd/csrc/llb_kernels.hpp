@@ -197,14 +197,13 @@ __device__ __forceinline__ void llb_fetch_plane(float (&v)[LLB_NM * ((TS::PL + T
                                                 int tid) {
   constexpr int NPC = (TS::PL + TS::NT - 1) / TS::NT;
   const uint32_t gz = halo_coord(zz, a.nz, a.wall_z);
-  const uint32_t zoff = gz * (uint32_t)a.nx * (uint32_t)a.ny;
 #pragma unroll
   for (int k = 0; k < NPC; ++k) {
     const int rr = min(tid + k * TS::NT, TS::PL - 1);  // surplus lanes reload the last position
     const int hy = rr / TS::TXH, hx = rr - hy * TS::TXH;
     const uint32_t gx = halo_coord(x0 - TS::RAD + hx, a.nx, a.wall_x);
     const uint32_t gy = halo_coord(y0 - TS::RAD + hy, a.ny, a.wall_y);
-    const float* m = M + (zoff + gy * (uint32_t)a.nx + gx);
+    const float* m = M + ((size_t)gz * a.px * a.ny + gy * (uint32_t)a.px + gx);  // moment rows at pitch px
 #pragma unroll
     for (int ch = 0; ch < LLB_NM; ++ch) v[ch * NPC + k] = m[(size_t)ch * a.NF];
     // channel 0 as the FOLD form of llb_pull_dir reads it
@@ -353,7 +352,7 @@ __global__ void __launch_bounds__(T::NT) k_llb_collide(const S* __restrict__ W, 
       }
       const R om1 = R(1) - omega;
       // new moments
-      S* out = M + s;
+      S* out = M + ((uint32_t)x + a.px * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)z));  // rows at pitch px
       out[0] = drho;
       out[1 * NF] = rho * ux + om1 * (jx - rho * ux) + guo * Fx;
       out[2 * NF] = rho * uy + om1 * (jy - rho * uy) + guo * Fy;
@@ -410,13 +409,14 @@ __global__ void __launch_bounds__(256) k_llb_init(S* __restrict__ M, S* __restri
   const double ra = a.rho0 * (1.0 + phi) * 0.5, rb = a.rho0 * (1.0 - phi) * 0.5, rho = ra + rb;
   const double u[3] = {a.u0x, a.u0y, a.u0z};
   const size_t N = a.N, NF = a.NF;  // field planes, moment planes
-  M[s] = (S)(rho - a.rho0);
-  for (int k = 0; k < 3; ++k) M[(1 + k) * NF + s] = (S)(rho * u[k]);
+  const uint32_t fs = x + a.px * (y + (uint32_t)a.ny * z);  // the site in the moment planes (rows at pitch px)
+  M[fs] = (S)(rho - a.rho0);
+  for (int k = 0; k < 3; ++k) M[(1 + k) * NF + fs] = (S)(rho * u[k]);
   constexpr int PA_[6] = {0, 1, 2, 0, 0, 1}, PB_[6] = {0, 1, 2, 1, 2, 2};
-  for (int k = 0; k < 6; ++k) M[(4 + k) * NF + s] = (S)(rho * u[PA_[k]] * u[PB_[k]]);
-  M[10 * NF + s] = 0;
-  M[11 * NF + s] = (S)(ra / rho);
-  for (int k = 0; k < 3; ++k) M[(12 + k) * NF + s] = 0;
+  for (int k = 0; k < 6; ++k) M[(4 + k) * NF + fs] = (S)(rho * u[PA_[k]] * u[PB_[k]]);
+  M[10 * NF + fs] = 0;
+  M[11 * NF + fs] = (S)(ra / rho);
+  for (int k = 0; k < 3; ++k) M[(12 + k) * NF + fs] = 0;
   phi_out[s] = (S)phi;
   S* rA = (S*)fo.rho_a;
   S* rB = (S*)fo.rho_b;
